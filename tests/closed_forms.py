@@ -1,0 +1,228 @@
+"""Closed-form and quadrature references that pin the oracle (fp64, numpy/scipy).
+
+Each function states the textbook result it evaluates.  None of them calls the
+oracle or the GPU library.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+from scipy import integrate, special
+
+LN10 = math.log(10.0)
+
+
+# ---------------------------------------------------------------- spectra
+def grid_lambda(n_bins, lo=300.0, hi=800.0):
+    return lo + (hi - lo) / (n_bins - 1) * np.arange(n_bins)
+
+
+def gauss_mix(lam, terms):
+    lam = np.asarray(lam, float)
+    return sum(w * np.exp(-0.5 * ((lam - mu) / sd) ** 2) for mu, sd, w in terms)
+
+
+def emission_pmf(n_bins, terms):
+    e = gauss_mix(grid_lambda(n_bins), terms)
+    return e / e.sum()
+
+
+def dye_sigma_a(lam, terms, epsilon, conc_uM, n_bins, decadic=True):
+    """Dye absorption coefficient in 1/mm: (ln10) * eps[1/(M cm)] * c[uM] * 1e-7 * a_hat."""
+    grid = grid_lambda(n_bins)
+    peak = gauss_mix(grid, terms).max()
+    base = LN10 if decadic else 1.0
+    return base * epsilon * conc_uM * 1e-7 * gauss_mix(lam, terms) / peak
+
+
+# ---------------------------------------------------------------- slab optics
+def half_e2(tau):
+    """Escape probability of an isotropic emitter at optical depth tau below a
+    free surface, uncollided: (1/2) E_2(tau)."""
+    return 0.5 * special.expn(2, tau)
+
+
+def dye_slab_fluorescent_film(d, sig_t_x, sig_a_dye_x, qy, pmf, sig_t_em):
+    """Non-scattering dye slab [0, d], collimated beam at excitation wavelength.
+
+    First collisions at depth z have density sig_t_x * exp(-sig_t_x z); the dye
+    takes a fraction sig_a_dye_x / sig_t_x; emission with probability qy at
+    bin k with probability pmf[k], isotropic; the fluorescent photon escapes
+    uncollided with probability E_2/2 of its optical distance to each face.
+    Returns (R[k], T[k]) as fractions of source photons."""
+    R = np.zeros(len(pmf))
+    T = np.zeros(len(pmf))
+    for k in range(len(pmf)):
+        if pmf[k] < 1e-300:
+            continue
+        st = sig_t_em[k]
+        fr = lambda z: math.exp(-sig_t_x * z) * half_e2(st * z)  # noqa: E731
+        ft = lambda z: math.exp(-sig_t_x * z) * half_e2(st * (d - z))  # noqa: E731
+        R[k] = qy * pmf[k] * sig_a_dye_x * integrate.quad(fr, 0.0, d, limit=200)[0]
+        T[k] = qy * pmf[k] * sig_a_dye_x * integrate.quad(ft, 0.0, d, limit=200)[0]
+    return R, T
+
+
+def single_scatter_slab(tau, albedo=1.0):
+    """Slab of optical thickness tau, normal collimated beam, isotropic phase.
+    Probability that a photon scatters exactly once and leaves through the
+    lit face (R1) or the far face (T1) without further collision."""
+    r1 = integrate.quad(lambda mu: mu / (1 + mu) * (1 - math.exp(-tau * (1 + 1 / mu))),
+                        0.0, 1.0, limit=200)[0]
+
+    def t_int(mu):
+        # int_0^tau exp(-t) exp(-(tau-t)/mu) dt
+        if abs(mu - 1.0) < 1e-12:
+            return tau * math.exp(-tau)
+        a = 1.0 - 1.0 / mu
+        return math.exp(-tau / mu) * (1 - math.exp(-a * tau)) / a
+
+    t1 = integrate.quad(t_int, 0.0, 1.0, limit=200)[0]
+    return 0.5 * albedo * r1, 0.5 * albedo * t1
+
+
+def chandrasekhar_h(omega, mu, n=200, iters=20000, tol=1e-14):
+    """H-function for isotropic scattering with single-scattering albedo omega,
+    from the alternative form of its integral equation:
+        1/H(mu) = sqrt(1-omega) + (omega/2) int_0^1 mu' H(mu') / (mu + mu') dmu'.
+    Solved by damped fixed-point iteration on a Gauss-Legendre grid (fp64)."""
+    x, w = np.polynomial.legendre.leggauss(n)
+    x = 0.5 * (x + 1.0)
+    w = 0.5 * w
+    s = math.sqrt(max(0.0, 1.0 - omega))
+    H = np.ones(n)
+    K = (omega / 2.0) * (w * x)[None, :] / (x[:, None] + x[None, :])
+    for _ in range(iters):
+        # damped: the undamped map oscillates with period two near omega = 1
+        Hn = 0.5 * (H + 1.0 / (s + K @ H))
+        if np.max(np.abs(Hn - H)) < tol:
+            H = Hn
+            break
+        H = Hn
+    mu = np.atleast_1d(np.asarray(mu, float))
+    Km = (omega / 2.0) * (w * x)[None, :] / (mu[:, None] + x[None, :])
+    out = 1.0 / (s + Km @ H)
+    return out, (x, w, H)
+
+
+def halfspace_albedo(omega):
+    """Total reflectance of a semi-infinite isotropically scattering medium under
+    a normal collimated beam: 1 - H(1) sqrt(1 - omega) (Chandrasekhar)."""
+    h1, _ = chandrasekhar_h(omega, [1.0])
+    return 1.0 - h1[0] * math.sqrt(1.0 - omega)
+
+
+# ---------------------------------------------------------------- camera
+class Pinhole:
+    def __init__(self, eye, look, up, fov_y_deg, width, height):
+        self.eye = np.asarray(eye, float)
+        f = np.asarray(look, float) - self.eye
+        self.f = f / np.linalg.norm(f)
+        r = np.cross(self.f, np.asarray(up, float))
+        self.r = r / np.linalg.norm(r)
+        self.u = np.cross(self.r, self.f)
+        self.tany = math.tan(math.radians(fov_y_deg) / 2)
+        self.tanx = self.tany * width / height
+        self.W, self.H = width, height
+
+    def ray(self, px, py):
+        """Unit direction through image position (px, py) in pixel units."""
+        xi = 2.0 * px / self.W - 1.0
+        yi = 1.0 - 2.0 * py / self.H
+        d = self.f + xi * self.tanx * self.r + yi * self.tany * self.u
+        return d / np.linalg.norm(d)
+
+
+def ray_box_exit(o, d, lo, hi):
+    t = np.inf
+    for a in range(3):
+        if d[a] > 0:
+            t = min(t, (hi[a] - o[a]) / d[a])
+        elif d[a] < 0:
+            t = min(t, (lo[a] - o[a]) / d[a])
+    return t
+
+
+def ray_plane_rect(o, d, corner, u, v):
+    """Distance along ray to the parallelogram corner + a u + b v, or inf."""
+    n = np.cross(u, v)
+    dn = n @ d
+    if dn == 0:
+        return np.inf
+    t = n @ (corner - o) / dn
+    if t <= 0:
+        return np.inf
+    q = o + t * d - corner
+    a = q @ u / (u @ u)
+    b = q @ v / (v @ v)
+    return t if (0 <= a <= 1 and 0 <= b <= 1) else np.inf
+
+
+def ray_sphere(o, d, c, r):
+    oc = o - c
+    b = oc @ d
+    cc = oc @ oc - r * r
+    disc = b * b - cc
+    if disc <= 0:
+        return np.inf, np.inf
+    s = math.sqrt(disc)
+    return -b - s, -b + s
+
+
+def quad_irradiance(x, normal, corner, u, v, radiance, n=48, medium=None):
+    """Irradiance at x (surface normal `normal`, or None for the
+    direction-independent integral int L cos_l T / r^2 dA seen by an isotropic
+    scatterer) from a Lambertian parallelogram of radiance L, by Gauss-Legendre
+    quadrature.  `medium` = (center, radius, sigma_t): attenuate the light
+    through that sphere (Beer-Lambert along the chord)."""
+    x = np.asarray(x, float)
+    g, w = np.polynomial.legendre.leggauss(n)
+    g = 0.5 * (g + 1)
+    w = 0.5 * w
+    nl = np.cross(u, v)
+    area = np.linalg.norm(nl)
+    nl = nl / area
+    A, B = np.meshgrid(g, g, indexing="ij")
+    W = np.outer(w, w)
+    y = corner[None, None, :] + A[..., None] * u + B[..., None] * v
+    dv = y - x
+    r2 = (dv * dv).sum(-1)
+    r = np.sqrt(r2)
+    dirn = dv / r[..., None]
+    cl = -(dirn @ nl)
+    cx = np.ones_like(cl) if normal is None else dirn @ np.asarray(normal, float)
+    ok = (cl > 0) & (cx > 0)
+    tr = np.ones_like(cl)
+    if medium is not None:
+        c, rad, st = medium
+        oc = x - np.asarray(c, float)
+        b = dirn @ oc
+        cc = oc @ oc - rad * rad
+        disc = b * b - cc
+        sq = np.sqrt(np.maximum(disc, 0.0))
+        lo = np.maximum(-b - sq, 0.0)
+        hi = np.minimum(-b + sq, r)
+        ln = np.where((disc > 0) & (hi > lo), hi - lo, 0.0)
+        tr = np.exp(-st * ln)
+    val = np.where(ok, W * radiance * cl * cx * tr / r2, 0.0)
+    return float(val.sum() * area)
+
+
+def single_scatter_radiance(eye, d, c, rad, sig_s, sig_t, corner, u, v, radiance,
+                            n_line=24, n_quad=32):
+    """Radiance along the camera ray (eye, d) from photons scattered exactly once
+    inside a sphere lit by a Lambertian quad (isotropic phase 1/4pi):
+      L = int_{ray in sphere} T(eye, x) sigma_s/(4 pi) int_quad L_e T(x, y) cos_l / r^2 dA dt."""
+    t0, t1 = ray_sphere(eye, d, np.asarray(c, float), rad)
+    if not np.isfinite(t0):
+        return 0.0
+    g, w = np.polynomial.legendre.leggauss(n_line)
+    ts = t0 + (t1 - t0) * 0.5 * (g + 1)
+    ws = (t1 - t0) * 0.5 * w
+    tot = 0.0
+    for t, wt in zip(ts, ws):
+        x = eye + t * d
+        q = quad_irradiance(x, None, corner, u, v, radiance, n=n_quad, medium=(c, rad, sig_t))
+        tot += wt * math.exp(-sig_t * (t - t0)) * q
+    return sig_s / (4 * math.pi) * tot
