@@ -1,0 +1,291 @@
+/*
+ * fpt -- fluorescent spectral path tracer for MI355X (gfx950), C ABI.
+ *
+ * Computes the transport model of Abdellah et al., "A Physically Plausible
+ * Model for Rendering Highly Scattering Fluorescent Participating Media"
+ * (arXiv 1706.03024): per-wavelength volumetric path tracing through
+ * isotropic scattering media holding fluorescent dyes.
+ *
+ *   - Free flight t = -ln(1-u)/sigma_t(lambda) (sec. 4.2, eqs. 5-6,
+ *     Beer-Lambert), sigma_t = sigma_s + sigma_a,bg + sum_d sigma_a,d.
+ *   - Dye absorption sigma_a,d = B * epsilon_d * c_d * 1e-7 * a_hat_d(lambda)
+ *     [1/mm] with B = ln 10 (decadic epsilon) or 1, a_hat the absorption
+ *     spectrum normalised to peak 1 on the grid (sec. 4.1: concentration,
+ *     absorption spectrum and molar absorptivity define the event).
+ *   - Collision event chosen with probabilities sigma_s/sigma_t (isotropic
+ *     scatter, eq. 2), sigma_a,bg/sigma_t (background absorber) and
+ *     sigma_a,d/sigma_t (dye d); a dye absorption emits with probability QY_d
+ *     at a wavelength drawn from the dye's area-normalised emission spectrum
+ *     (eq. 10, one-bin step), isotropically (sec. 2.1); at most K emissions
+ *     per path (sec. 4.1: a second emission ends the path when K = 1).
+ *   - Spectral film: escape tallies, or a pinhole camera connected to every
+ *     realised vertex with transmittance and the 1/r^2 geometry term (eqs. 3-6).
+ *
+ * The walk runs forward from the light (analog); all randomness comes from a
+ * counter-based Philox4x32-10 stream keyed by (seed, instance) with counter
+ * (path id, vertex, call, 0), so any path range renders identically alone or
+ * as part of a larger run.
+ *
+ * Conventions for every entry point:
+ *   - Pointers marked "device" are device (HBM) addresses on the current HIP
+ *     device; "host" pointers are ordinary host memory.  Every pointer
+ *     argument is checked for NULL unless documented as optional.
+ *   - Functions return FPT_OK (0) or a negative fpt_status; on error no
+ *     output has been written, and fpt_last_error() (thread-local) holds a
+ *     message.  No C++ exception crosses the ABI.
+ *   - Work is enqueued asynchronously on the caller's HIP stream (a
+ *     hipStream_t passed as void*, NULL = the null stream).  Device faults
+ *     surface as FPT_E_DEVICE at the next call that synchronises.
+ *   - A scene (and a batch) may be used by one stream at a time: calls that
+ *     overlap on different streams race on its scratch buffers.
+ * Units: nm, mm, 1/mm, 1/(M cm), uM.
+ */
+#ifndef FPT_H
+#define FPT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FPT_ABI_VERSION 1u
+
+typedef enum {
+    FPT_OK = 0,
+    FPT_E_INVALID = -1,     /* malformed descriptor or argument */
+    FPT_E_RANGE = -2,       /* value outside a supported range */
+    FPT_E_NOMEM = -3,       /* device or host allocation failed */
+    FPT_E_DEVICE = -4,      /* HIP runtime error */
+    FPT_E_UNSUPPORTED = -5  /* valid but not implemented combination */
+} fpt_status;
+
+#define FPT_MAX_SPECTRUM_TERMS 16
+#define FPT_MAX_DYES 8
+#define FPT_MAX_MEDIA 8
+#define FPT_MAX_MEDIUM_DYES 4
+#define FPT_MAX_SPHERES 8
+#define FPT_MAX_LINES 8
+#define FPT_MAX_BINS 1024
+#define FPT_MAX_GRAD_PARAMS 16
+#define FPT_N_TALLIES 20
+
+enum { FPT_SPECTRUM_NONE = 0, FPT_SPECTRUM_GAUSS_MIX = 1, FPT_SPECTRUM_PIECEWISE_LINEAR = 2 };
+enum { FPT_GEOM_SLAB = 0, FPT_GEOM_HALFSPACE = 1, FPT_GEOM_SPHERE = 2, FPT_GEOM_INFINITE = 3,
+       FPT_GEOM_BOX = 4 };
+enum { FPT_LIGHT_BEAM = 0, FPT_LIGHT_POINT = 1, FPT_LIGHT_QUAD = 2 };
+enum { FPT_SENSOR_ESCAPE = 0, FPT_SENSOR_PINHOLE = 1 };
+enum { FPT_BASE_DECADIC = 0, FPT_BASE_NATURAL = 1 };
+
+/* Run flags. */
+#define FPT_FLAG_FLUORESCENCE_ONLY 1u  /* film records only paths that emitted (V_f, eq. 9) */
+#define FPT_FLAG_NO_EXCITATION_SCATTER 2u /* end a path at its first scatter before emitting */
+
+/* Exit codes (one per path) and tally slots (uint64, accumulated). */
+enum { FPT_EXIT_ESC_R = 0, FPT_EXIT_ESC_T = 1, FPT_EXIT_BG = 2, FPT_EXIT_NONRAD = 3,
+       FPT_EXIT_KCAP = 4, FPT_EXIT_SCAP = 5, FPT_EXIT_WALL = 6, FPT_EXIT_LIGHT = 7,
+       FPT_EXIT_EXCSCAT = 8, FPT_EXIT_TRUNC = 9 };
+enum { FPT_T_PATHS = 0, FPT_T_VERTICES = 1, FPT_T_SCATTERS = 2, FPT_T_DYE_ABS = 3,
+       FPT_T_EMISSIONS = 4, FPT_T_WALL_REFLECT = 5, FPT_T_CROSSINGS = 6,
+       FPT_T_SPLAT_HIT = 7, FPT_T_SPLAT_MISS = 8, FPT_T_SPLAT_RR_KILL = 9,
+       FPT_T_EXIT0 = 10 /* + exit code */ };
+
+/* A spectrum on nm: a Gaussian mixture sum_i value_i exp(-(l-center_i)^2/(2 width_i^2))
+ * or a piecewise-linear curve through (center_i, value_i), constant beyond the ends. */
+typedef struct {
+    int32_t kind; /* FPT_SPECTRUM_* */
+    int32_t n;    /* 1..FPT_MAX_SPECTRUM_TERMS */
+    double center_nm[FPT_MAX_SPECTRUM_TERMS];
+    double value[FPT_MAX_SPECTRUM_TERMS];
+    double width_nm[FPT_MAX_SPECTRUM_TERMS];
+} fpt_spectrum;
+
+typedef struct {
+    fpt_spectrum absorption; /* shape only: normalised to peak 1 on the grid */
+    fpt_spectrum emission;   /* shape only: normalised to unit area on the grid */
+    double epsilon_M_cm;     /* peak molar absorptivity >= 0 */
+    double qy;               /* quantum yield in [0, 1] */
+} fpt_dye;
+
+typedef struct {
+    double sigma_s_mm;    /* >= 0, wavelength independent */
+    double sigma_a_bg_mm; /* >= 0, wavelength independent */
+    int32_t n_dyes;       /* 0..FPT_MAX_MEDIUM_DYES */
+    int32_t dye[FPT_MAX_MEDIUM_DYES];
+    double conc_uM[FPT_MAX_MEDIUM_DYES]; /* >= 0 */
+} fpt_medium;
+
+typedef struct {
+    double center[3];
+    double radius;
+    int32_t medium;
+    int32_t pad;
+} fpt_sphere;
+
+/*
+ * Scene descriptor (copied by fpt_scene_create; the caller may free it after).
+ * geometry SLAB/HALFSPACE/SPHERE/INFINITE: one homogeneous body of medium
+ *   `body_medium` in vacuum (index-matched boundary); sensor must be ESCAPE,
+ *   light BEAM (starting on the body surface, pointing inward) or POINT (inside).
+ * geometry BOX: box [box_lo, box_hi] with Lambertian walls of reflectance
+ *   walls[f] (faces 0 x=lo, 1 x=hi, 2 y=lo, 3 y=hi, 4 z=lo, 5 z=hi); face
+ *   `open_face` lets light out; vacuum inside except the (disjoint,
+ *   index-matched) dye spheres; light must be a QUAD (Lambertian emitter
+ *   light_pos + a light_u + b light_v, emitting along normalize(u x v),
+ *   opaque and absorbing on both sides); sensor ESCAPE or PINHOLE (eye
+ *   outside the box on the open side).
+ * Light lines: wavelengths snap to the nearest grid point (ties to the lower
+ *   one) and must lie on the grid; powers are normalised to a total of 1.
+ */
+typedef struct {
+    int32_t n_bins;            /* 2..FPT_MAX_BINS grid points */
+    int32_t absorptivity_base; /* FPT_BASE_* */
+    double lo_nm, hi_nm;       /* lambda_k = lo + k (hi-lo)/(n_bins-1) */
+    int32_t n_dyes, n_media;
+    fpt_dye dyes[FPT_MAX_DYES];
+    fpt_medium media[FPT_MAX_MEDIA];
+    int32_t geometry; /* FPT_GEOM_* */
+    int32_t body_medium;
+    double slab_z0, slab_z1;  /* SLAB: z0 < z1; HALFSPACE: z > z0 */
+    double body_center[3];    /* SPHERE */
+    double body_radius;
+    double box_lo[3], box_hi[3];
+    int32_t open_face;
+    int32_t n_spheres;
+    fpt_spectrum walls[6];
+    fpt_sphere spheres[FPT_MAX_SPHERES];
+    int32_t light; /* FPT_LIGHT_* */
+    int32_t n_lines;
+    double light_pos[3], light_dir[3], light_u[3], light_v[3];
+    double line_nm[FPT_MAX_LINES], line_power[FPT_MAX_LINES];
+    int32_t sensor; /* FPT_SENSOR_* */
+    int32_t width, height;
+    double eye[3], look[3], up[3];
+    double fov_y_deg;
+} fpt_scene_desc;
+
+/* One render call: paths [path_begin, path_begin + path_count) of a job of
+ * total_paths paths (total_paths <= 2^32).  Every path carries power
+ * parity_batches / total_paths; with parity_batches = B > 1 the film gains a
+ * leading axis of B slices and path p goes to slice p % B, so each slice is an
+ * independent estimate of the whole film (for batch-mean standard errors). */
+typedef struct {
+    uint64_t seed;
+    uint64_t path_begin, path_count, total_paths;
+    uint32_t instance;       /* xor-ed into the high key word */
+    uint32_t max_scatter;    /* a path's (max_scatter+1)-th scatter ends it */
+    uint32_t max_emissions;  /* K; 0xFFFFFFFF = unlimited */
+    uint32_t flags;          /* FPT_FLAG_* */
+    uint32_t parity_batches; /* 0 or 1 = none, else 2..64 */
+    uint32_t pad;
+    double splat_rr; /* camera splats with transmittance below this are kept with
+                        probability T/splat_rr and weight /that (0 = off) */
+} fpt_run;
+
+/* Launch shape knobs; all-zero = library defaults.  Results never depend on them. */
+typedef struct {
+    int32_t block_threads;  /* 64..1024, multiple of 64 */
+    int32_t blocks_per_cu;  /* persistent blocks per compute unit */
+    int32_t refill_lanes;   /* a wave refills dead lanes once this many are dead (1..64) */
+    int32_t chunk_paths;    /* batched: paths per work item */
+} fpt_tune;
+
+/* Per-path replay record (fp32 path state at exit). */
+typedef struct {
+    uint32_t n_vertices, n_scatter, n_emit, exit_code;
+    int32_t lambda, comp, region, pad;
+    float pos[3], dir[3];
+    float splat_sum; /* sum of values this path deposited into the film */
+    float pad2;
+} fpt_path_record;
+
+typedef struct fpt_scene fpt_scene;
+typedef struct fpt_batch fpt_batch;
+
+uint32_t fpt_abi_version(void);
+const char* fpt_status_str(int32_t status);
+const char* fpt_last_error(void);
+
+/* Validate `desc`, build the spectral tables in fp64 (rounded to fp32) and
+ * upload them to the current device (synchronous).  *out is library-owned;
+ * free with fpt_scene_destroy.  Errors: FPT_E_INVALID / FPT_E_RANGE for bad
+ * descriptors (nothing allocated), FPT_E_NOMEM, FPT_E_DEVICE. */
+int32_t fpt_scene_create(const fpt_scene_desc* desc, fpt_scene** out);
+void fpt_scene_destroy(fpt_scene* scene);
+
+/* Replace the differentiable parameters and rebuild the tables (synchronous
+ * with respect to the device).  Host arrays, each optional (NULL = unchanged):
+ * conc_uM[sum over media of n_dyes] in (medium, dye slot) order, qy[n_dyes],
+ * sigma_s_mm[n_media]. */
+int32_t fpt_scene_set_params(fpt_scene* scene, const double* conc_uM, const double* qy,
+                             const double* sigma_s_mm);
+
+/* Film layout: ESCAPE [B][2 comp][2 side (R, T)][n_bins];
+ * PINHOLE [B][2 comp][height][width][n_bins]; comp 0 = not yet emitted,
+ * 1 = emitted at least once.  fp32, C-contiguous.  dims[5] receives the
+ * shape, *ndims 4 or 5. */
+int32_t fpt_film_shape(const fpt_scene* scene, uint32_t parity_batches, int64_t dims[5],
+                       int32_t* ndims);
+
+/* Number of differentiable parameters: [conc per (medium, dye slot)]
+ * [QY per dye][sigma_s per medium]. */
+int32_t fpt_grad_param_count(const fpt_scene* scene);
+
+/* Optional launch-shape override for this scene (NULL restores defaults). */
+int32_t fpt_scene_set_tune(fpt_scene* scene, const fpt_tune* tune);
+
+/* Forward render.  Accumulates (+=) into film_dev (device, fp32, film shape)
+ * and tallies_dev (device, FPT_N_TALLIES uint64; optional, may be NULL).
+ * Escape films are integer counts scaled by parity_batches/total_paths at the
+ * end of the call; camera films are fp32 atomic sums.  Asynchronous. */
+int32_t fpt_render(fpt_scene* scene, const fpt_run* run, float* film_dev, uint64_t* tallies_dev,
+                   void* hip_stream);
+
+/* Path-replay adjoint: replays the same paths (same random numbers) and
+ * accumulates into grad_dev (device, fp32[fpt_grad_param_count]) the gradient
+ * of <grad_film, film> with respect to the parameters, using the
+ * likelihood-ratio form d E[v] = E[v d log p(path) + d v].  grad_film_dev
+ * (device, film shape) is read only.  Stores no path state; memory use is
+ * independent of path length.  tallies_dev optional.  Asynchronous.
+ * FPT_E_UNSUPPORTED if the parameter count exceeds FPT_MAX_GRAD_PARAMS. */
+int32_t fpt_render_adjoint(fpt_scene* scene, const fpt_run* run, const float* grad_film_dev,
+                           float* grad_dev, uint64_t* tallies_dev, void* hip_stream);
+
+/* Test hook: one record per path into rec_dev (device, path_count records).
+ * max_vertices > 0 ends paths after that many vertices (exit TRUNC).  With
+ * grad_film_dev and rec_grad_dev (both optional, device) it also writes each
+ * path's gradient contribution (fp32[path_count][n_params]).  Does not touch
+ * any film.  Asynchronous. */
+int32_t fpt_render_records(fpt_scene* scene, const fpt_run* run, fpt_path_record* rec_dev,
+                           uint32_t max_vertices, const float* grad_film_dev,
+                           float* rec_grad_dev, void* hip_stream);
+
+/* Test hook: copies the fp32 tables the kernels use to host arrays (each
+ * optional): sigma_t[n_media][n_bins], emis_cdf[n_dyes][n_bins],
+ * rho[6][n_bins], line_bin[n_lines]. */
+int32_t fpt_scene_tables(const fpt_scene* scene, float* sigma_t, float* emis_cdf, float* rho,
+                         int32_t* line_bin);
+
+/* Batched form: n independent escape-sensor body scenes (one medium each,
+ * equal n_bins) rendered by one persistent launch that claims (instance, path
+ * chunk) work items from a device queue; the launch sequence is captured in a
+ * hipGraph on the first render and replayed after.  runs[i] gives instance
+ * i's seed, instance key and path count.  Films: [n][2][2][n_bins] fp32,
+ * accumulated; tallies: [n][FPT_N_TALLIES] uint64 (optional). */
+int32_t fpt_batch_create(const fpt_scene_desc* descs, const fpt_run* runs, int32_t n,
+                         const fpt_tune* tune, fpt_batch** out);
+int32_t fpt_batch_render(fpt_batch* batch, float* films_dev, uint64_t* tallies_dev,
+                         void* hip_stream);
+void fpt_batch_destroy(fpt_batch* batch);
+
+/* Times candidate launch shapes for `scene` and `run` on the current device
+ * (synchronous; renders into a scratch film) and writes the fastest to *out.
+ * batch may be NULL (then the plain render is tuned, else the batched one). */
+int32_t fpt_autotune(fpt_scene* scene, const fpt_run* run, fpt_batch* batch, fpt_tune* out,
+                     float* best_ms);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif

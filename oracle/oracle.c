@@ -696,6 +696,8 @@ static void run_path(ctx_t* c, uint32_t pid, orc_record* rec, uint32_t max_verti
     for (;;) {
         p.v++;
         if (max_vertices && p.v >= max_vertices) { exit_code = ORC_EXIT_TRUNC; break; }
+        /* hard bound on path length: 2^28 vertices, counted as a scatter-cap exit */
+        if (p.v >= (1u << 28)) { exit_code = ORC_EXIT_SCAP; break; }
         T[ORC_T_VERTICES]++;
         draw(&rng, p.v, 0, r);
         double u0 = unif(r[0]), u1 = unif(r[1]), u2 = unif(r[2]), u3 = unif(r[3]);

@@ -1,0 +1,763 @@
+// C-ABI implementation of the fpt library: descriptor validation, spectral
+// table construction (fp64, rounded to fp32), device residency of scenes and
+// the launch sequences of each entry point.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "fpt.h"
+#include "fpt_internal.h"
+
+namespace fpt {
+size_t transport_lds_bytes(const KParams& P, int block_threads, int mode);
+hipError_t launch_transport(const KParams& P, const KBuffers& B, int mode, int grid, int block,
+                            hipStream_t s);
+hipError_t transport_occupancy(const KParams& P, int mode, int block, int* blocks_per_cu);
+hipError_t launch_zero_u32(uint32_t* p, size_t n, hipStream_t s);
+hipError_t launch_zero_u64(unsigned long long* p, size_t n, hipStream_t s);
+hipError_t launch_finalize_counts(const uint32_t* counts, float* film, size_t n, float scale,
+                                  hipStream_t s);
+hipError_t launch_reduce_partials(const float* partials, int nblocks, int np, float* grad,
+                                  hipStream_t s);
+}  // namespace fpt
+
+using namespace fpt;
+
+namespace {
+
+enum { MODE_FWD = 0, MODE_ADJ = 1, MODE_REC = 2, MODE_REC_ADJ = 3 };
+
+thread_local std::string g_err;
+
+int32_t set_err(int32_t code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+int32_t hip_err(hipError_t e, const char* what) {
+    if (e == hipErrorOutOfMemory) return set_err(FPT_E_NOMEM, "%s: %s", what, hipGetErrorString(e));
+    return set_err(FPT_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr, what)                       \
+    do {                                          \
+        hipError_t e_ = (expr);                   \
+        if (e_ != hipSuccess) return hip_err(e_, what); \
+    } while (0)
+
+bool finite3(const double* v) { return std::isfinite(v[0]) && std::isfinite(v[1]) && std::isfinite(v[2]); }
+
+double spectrum_at(const fpt_spectrum& s, double lam) {
+    if (s.kind == FPT_SPECTRUM_GAUSS_MIX) {
+        double acc = 0.0;
+        for (int i = 0; i < s.n; ++i) {
+            const double z = (lam - s.center_nm[i]) / s.width_nm[i];
+            acc += s.value[i] * std::exp(-0.5 * z * z);
+        }
+        return acc;
+    }
+    // piecewise linear, constant beyond the end knots
+    if (lam <= s.center_nm[0]) return s.value[0];
+    if (lam >= s.center_nm[s.n - 1]) return s.value[s.n - 1];
+    int i = 1;
+    while (i < s.n - 1 && lam > s.center_nm[i]) ++i;
+    const double x0 = s.center_nm[i - 1], x1 = s.center_nm[i];
+    return s.value[i - 1] + (lam - x0) / (x1 - x0) * (s.value[i] - s.value[i - 1]);
+}
+
+int32_t check_spectrum(const fpt_spectrum& s, const char* what) {
+    if (s.kind != FPT_SPECTRUM_GAUSS_MIX && s.kind != FPT_SPECTRUM_PIECEWISE_LINEAR)
+        return set_err(FPT_E_INVALID, "%s: unknown spectrum kind %d", what, s.kind);
+    if (s.n < 1 || s.n > FPT_MAX_SPECTRUM_TERMS)
+        return set_err(FPT_E_RANGE, "%s: %d spectrum terms", what, s.n);
+    for (int i = 0; i < s.n; ++i) {
+        if (!std::isfinite(s.center_nm[i]) || !std::isfinite(s.value[i]))
+            return set_err(FPT_E_INVALID, "%s: non-finite spectrum term", what);
+        if (s.kind == FPT_SPECTRUM_GAUSS_MIX) {
+            if (!(s.width_nm[i] > 0.0) || !std::isfinite(s.width_nm[i]))
+                return set_err(FPT_E_INVALID, "%s: Gaussian width must be > 0", what);
+            if (s.value[i] < 0.0) return set_err(FPT_E_INVALID, "%s: negative Gaussian weight", what);
+        } else if (i > 0 && !(s.center_nm[i] > s.center_nm[i - 1])) {
+            return set_err(FPT_E_INVALID, "%s: knots must increase", what);
+        }
+    }
+    return FPT_OK;
+}
+
+int snap_line(double nm, double lo, double delta, int n) {
+    const double k = std::ceil((nm - lo) / delta - 0.5);  // nearest, ties to the lower point
+    if (!(k >= 0.0) || k > (double)(n - 1)) return -1;
+    return (int)k;
+}
+
+}  // namespace
+
+struct fpt_scene {
+    fpt_scene_desc desc;
+    int device = 0;
+    int n_cu = 256;
+    int np = 0;
+    std::vector<uint32_t> image;
+    KParams base;
+    uint32_t* d_tables = nullptr;
+    uint32_t* d_counts = nullptr;
+    size_t counts_cap = 0;
+    unsigned long long* d_counter = nullptr;
+    unsigned long long* d_tally = nullptr;  // scratch tallies when the caller passes none
+    float* d_partials = nullptr;
+    size_t partials_cap = 0;
+    fpt_tune tune;
+    std::vector<float> h_st, h_cdf, h_rho;
+    std::vector<int> h_line_bin;
+};
+
+namespace {
+
+int32_t validate(const fpt_scene_desc* d) {
+    if (d->n_bins < 2 || d->n_bins > FPT_MAX_BINS)
+        return set_err(FPT_E_RANGE, "n_bins %d outside [2, %d]", d->n_bins, FPT_MAX_BINS);
+    if (!(d->hi_nm > d->lo_nm) || !std::isfinite(d->lo_nm) || !std::isfinite(d->hi_nm))
+        return set_err(FPT_E_INVALID, "grid needs finite lo_nm < hi_nm");
+    if (d->absorptivity_base != FPT_BASE_DECADIC && d->absorptivity_base != FPT_BASE_NATURAL)
+        return set_err(FPT_E_INVALID, "absorptivity_base %d", d->absorptivity_base);
+    if (d->n_dyes < 0 || d->n_dyes > FPT_MAX_DYES) return set_err(FPT_E_RANGE, "n_dyes %d", d->n_dyes);
+    if (d->n_media < 1 || d->n_media > FPT_MAX_MEDIA) return set_err(FPT_E_RANGE, "n_media %d", d->n_media);
+    for (int i = 0; i < d->n_dyes; ++i) {
+        const fpt_dye& y = d->dyes[i];
+        int32_t rc;
+        if ((rc = check_spectrum(y.absorption, "dye absorption")) != FPT_OK) return rc;
+        if ((rc = check_spectrum(y.emission, "dye emission")) != FPT_OK) return rc;
+        if (!(y.qy >= 0.0 && y.qy <= 1.0)) return set_err(FPT_E_RANGE, "dye %d: qy %g outside [0,1]", i, y.qy);
+        if (!(y.epsilon_M_cm >= 0.0) || !std::isfinite(y.epsilon_M_cm))
+            return set_err(FPT_E_RANGE, "dye %d: epsilon must be finite and >= 0", i);
+    }
+    for (int m = 0; m < d->n_media; ++m) {
+        const fpt_medium& md = d->media[m];
+        if (!(md.sigma_s_mm >= 0.0) || !std::isfinite(md.sigma_s_mm))
+            return set_err(FPT_E_RANGE, "medium %d: sigma_s must be finite and >= 0", m);
+        if (!(md.sigma_a_bg_mm >= 0.0) || !std::isfinite(md.sigma_a_bg_mm))
+            return set_err(FPT_E_RANGE, "medium %d: sigma_a_bg must be finite and >= 0", m);
+        if (md.n_dyes < 0 || md.n_dyes > FPT_MAX_MEDIUM_DYES)
+            return set_err(FPT_E_RANGE, "medium %d: %d dyes", m, md.n_dyes);
+        for (int j = 0; j < md.n_dyes; ++j) {
+            if (md.dye[j] < 0 || md.dye[j] >= d->n_dyes)
+                return set_err(FPT_E_INVALID, "medium %d: dye index %d", m, md.dye[j]);
+            if (!(md.conc_uM[j] >= 0.0) || !std::isfinite(md.conc_uM[j]))
+                return set_err(FPT_E_RANGE, "medium %d: concentration must be finite and >= 0", m);
+        }
+    }
+    if (d->n_lines < 1 || d->n_lines > FPT_MAX_LINES) return set_err(FPT_E_RANGE, "n_lines %d", d->n_lines);
+    double tot = 0.0;
+    for (int i = 0; i < d->n_lines; ++i) {
+        if (!(d->line_power[i] >= 0.0) || !std::isfinite(d->line_power[i]))
+            return set_err(FPT_E_RANGE, "line %d power", i);
+        tot += d->line_power[i];
+    }
+    if (!(tot > 0.0)) return set_err(FPT_E_INVALID, "total light power must be > 0");
+    if (d->light < FPT_LIGHT_BEAM || d->light > FPT_LIGHT_QUAD) return set_err(FPT_E_INVALID, "light kind %d", d->light);
+    if (d->sensor != FPT_SENSOR_ESCAPE && d->sensor != FPT_SENSOR_PINHOLE)
+        return set_err(FPT_E_INVALID, "sensor kind %d", d->sensor);
+    switch (d->geometry) {
+    case FPT_GEOM_SLAB:
+        if (!(d->slab_z1 > d->slab_z0) || !std::isfinite(d->slab_z0) || !std::isfinite(d->slab_z1))
+            return set_err(FPT_E_INVALID, "slab needs finite z0 < z1");
+        break;
+    case FPT_GEOM_HALFSPACE:
+        if (!std::isfinite(d->slab_z0)) return set_err(FPT_E_INVALID, "half-space z0");
+        break;
+    case FPT_GEOM_SPHERE:
+        if (!finite3(d->body_center) || !(d->body_radius > 0.0)) return set_err(FPT_E_INVALID, "body sphere");
+        break;
+    case FPT_GEOM_INFINITE:
+        break;
+    case FPT_GEOM_BOX:
+        break;
+    default:
+        return set_err(FPT_E_INVALID, "geometry kind %d", d->geometry);
+    }
+    if (d->geometry != FPT_GEOM_BOX) {
+        if (d->body_medium < 0 || d->body_medium >= d->n_media) return set_err(FPT_E_INVALID, "body_medium");
+        if (d->sensor != FPT_SENSOR_ESCAPE) return set_err(FPT_E_UNSUPPORTED, "pinhole sensor needs a box scene");
+        if (d->light == FPT_LIGHT_QUAD) return set_err(FPT_E_UNSUPPORTED, "quad light needs a box scene");
+        if (!finite3(d->light_pos)) return set_err(FPT_E_INVALID, "light position");
+        if (d->light == FPT_LIGHT_BEAM) {
+            const double n = std::sqrt(d->light_dir[0] * d->light_dir[0] + d->light_dir[1] * d->light_dir[1] +
+                                       d->light_dir[2] * d->light_dir[2]);
+            if (!(n > 0.0) || !std::isfinite(n)) return set_err(FPT_E_INVALID, "beam direction");
+        }
+        return FPT_OK;
+    }
+    // box scene
+    if (!finite3(d->box_lo) || !finite3(d->box_hi)) return set_err(FPT_E_INVALID, "box bounds");
+    for (int a = 0; a < 3; ++a)
+        if (!(d->box_hi[a] > d->box_lo[a])) return set_err(FPT_E_INVALID, "box needs lo < hi");
+    if (d->open_face < 0 || d->open_face > 5) return set_err(FPT_E_INVALID, "open_face %d", d->open_face);
+    for (int f = 0; f < 6; ++f) {
+        if (f == d->open_face) continue;
+        int32_t rc = check_spectrum(d->walls[f], "wall");
+        if (rc != FPT_OK) return rc;
+    }
+    if (d->light != FPT_LIGHT_QUAD) return set_err(FPT_E_UNSUPPORTED, "box scenes need a quad light");
+    if (!finite3(d->light_pos) || !finite3(d->light_u) || !finite3(d->light_v))
+        return set_err(FPT_E_INVALID, "quad light geometry");
+    if (d->n_spheres < 0 || d->n_spheres > FPT_MAX_SPHERES) return set_err(FPT_E_RANGE, "n_spheres %d", d->n_spheres);
+    for (int s = 0; s < d->n_spheres; ++s) {
+        const fpt_sphere& sp = d->spheres[s];
+        if (!finite3(sp.center) || !(sp.radius > 0.0)) return set_err(FPT_E_INVALID, "sphere %d", s);
+        if (sp.medium < 0 || sp.medium >= d->n_media) return set_err(FPT_E_INVALID, "sphere %d medium", s);
+        for (int a = 0; a < 3; ++a)
+            if (sp.center[a] - sp.radius <= d->box_lo[a] || sp.center[a] + sp.radius >= d->box_hi[a])
+                return set_err(FPT_E_INVALID, "sphere %d must lie strictly inside the box", s);
+        for (int t = 0; t < s; ++t) {
+            const fpt_sphere& q = d->spheres[t];
+            double dd = 0.0;
+            for (int a = 0; a < 3; ++a) dd += (sp.center[a] - q.center[a]) * (sp.center[a] - q.center[a]);
+            if (std::sqrt(dd) <= sp.radius + q.radius) return set_err(FPT_E_INVALID, "spheres %d and %d overlap", t, s);
+        }
+    }
+    if (d->sensor == FPT_SENSOR_PINHOLE) {
+        if (d->width < 1 || d->height < 1 || (int64_t)d->width * d->height > (1ll << 26))
+            return set_err(FPT_E_RANGE, "image %dx%d", d->width, d->height);
+        if (!(d->fov_y_deg > 0.0 && d->fov_y_deg < 179.0)) return set_err(FPT_E_RANGE, "fov_y_deg");
+        if (!finite3(d->eye) || !finite3(d->look) || !finite3(d->up)) return set_err(FPT_E_INVALID, "camera");
+        bool inside = true;
+        for (int a = 0; a < 3; ++a) inside = inside && d->eye[a] >= d->box_lo[a] && d->eye[a] <= d->box_hi[a];
+        if (inside) return set_err(FPT_E_UNSUPPORTED, "the eye must be outside the box");
+    }
+    return FPT_OK;
+}
+
+void norm3(double* v) {
+    const double n = std::sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+    v[0] /= n; v[1] /= n; v[2] /= n;
+}
+void cross3(const double* a, const double* b, double* o) {
+    o[0] = a[1] * b[2] - a[2] * b[1];
+    o[1] = a[2] * b[0] - a[0] * b[2];
+    o[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+uint32_t fbits(float f) {
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    return u;
+}
+
+// Builds the fp32 table image and the scene part of the kernel parameters.
+int32_t build_tables(fpt_scene* sc) {
+    const fpt_scene_desc& d = sc->desc;
+    const int N = d.n_bins;
+    const double delta = (d.hi_nm - d.lo_nm) / (N - 1);
+    std::vector<double> lam(N);
+    for (int k = 0; k < N; ++k) lam[k] = d.lo_nm + delta * k;
+
+    // absorption peak-normalised on the grid; emission an area-normalised PMF
+    std::vector<double> ahat((size_t)std::max(1, d.n_dyes) * N), cdf((size_t)std::max(1, d.n_dyes) * N);
+    for (int i = 0; i < d.n_dyes; ++i) {
+        double peak = 0.0, area = 0.0;
+        for (int k = 0; k < N; ++k) {
+            const double a = spectrum_at(d.dyes[i].absorption, lam[k]);
+            const double e = spectrum_at(d.dyes[i].emission, lam[k]);
+            if (a < 0.0 || e < 0.0) return set_err(FPT_E_INVALID, "dye %d: negative spectrum value", i);
+            ahat[(size_t)i * N + k] = a;
+            cdf[(size_t)i * N + k] = e;
+            peak = std::max(peak, a);
+            area += e;
+        }
+        if (!(peak > 0.0) || !(area > 0.0)) return set_err(FPT_E_INVALID, "dye %d: spectrum vanishes on the grid", i);
+        double run = 0.0;
+        for (int k = 0; k < N; ++k) {
+            ahat[(size_t)i * N + k] /= peak;
+            run += cdf[(size_t)i * N + k] / area;
+            cdf[(size_t)i * N + k] = run;
+        }
+        cdf[(size_t)i * N + N - 1] = 1.0;
+    }
+    int cum_stride = 0, kap_stride = 0;
+    for (int m = 0; m < d.n_media; ++m) {
+        cum_stride = std::max(cum_stride, d.media[m].n_dyes - 1);
+        kap_stride = std::max(kap_stride, d.media[m].n_dyes);
+    }
+    const double base = d.absorptivity_base == FPT_BASE_DECADIC ? std::log(10.0) : 1.0;
+
+    // gradient parameter indices: conc per (medium, slot), qy per dye, sigma_s per medium
+    int pc[FPT_MAX_MEDIA][FPT_MAX_MEDIUM_DYES], pq[FPT_MAX_DYES], pss[FPT_MAX_MEDIA];
+    int np = 0;
+    for (int m = 0; m < d.n_media; ++m)
+        for (int j = 0; j < d.media[m].n_dyes; ++j) pc[m][j] = np++;
+    for (int i = 0; i < d.n_dyes; ++i) pq[i] = np++;
+    for (int m = 0; m < d.n_media; ++m) pss[m] = np++;
+    sc->np = np;
+
+    KParams& P = sc->base;
+    std::memset(&P, 0, sizeof P);
+    P.N = N;
+    P.n_media = d.n_media;
+    P.n_dyes = d.n_dyes;
+    P.cum_stride = cum_stride;
+    P.kap_stride = kap_stride;
+    int off = 0;
+    P.off_med = off; off += d.n_media * kMedWords;
+    P.off_dye = off; off += std::max(1, d.n_dyes) * kDyeWords;
+    off = (off + 1) & ~1;  // float2 alignment
+    P.off_st = off; off += 2 * d.n_media * N;
+    P.off_cum = off; off += d.n_media * cum_stride * N;
+    P.off_cdf = off; off += d.n_dyes * N;
+    P.off_rho = off; off += 6 * N;
+    P.off_kap = off; off += d.n_media * kap_stride * N;
+    P.table_words = off;
+    std::vector<uint32_t>& img = sc->image;
+    img.assign((size_t)off, 0u);
+    sc->h_st.assign((size_t)d.n_media * N, 0.f);
+    sc->h_cdf.assign((size_t)std::max(1, d.n_dyes) * N, 0.f);
+    sc->h_rho.assign((size_t)6 * N, 0.f);
+
+    for (int m = 0; m < d.n_media; ++m) {
+        const fpt_medium& md = d.media[m];
+        uint32_t* r = &img[P.off_med + m * kMedWords];
+        r[MW_SS] = fbits((float)md.sigma_s_mm);
+        r[MW_THR_BG] = fbits((float)(md.sigma_s_mm + md.sigma_a_bg_mm));
+        r[MW_NDYES] = (uint32_t)md.n_dyes;
+        r[MW_INV_SS] = fbits(md.sigma_s_mm > 0.0 ? (float)(1.0 / md.sigma_s_mm) : 0.f);
+        r[MW_PSS] = (uint32_t)pss[m];
+        for (int j = 0; j < md.n_dyes; ++j) {
+            r[MW_DYE + j] = (uint32_t)md.dye[j];
+            r[MW_INV_C + j] = fbits(md.conc_uM[j] > 0.0 ? (float)(1.0 / md.conc_uM[j]) : 0.f);
+            r[MW_PC + j] = (uint32_t)pc[m][j];
+        }
+        for (int k = 0; k < N; ++k) {
+            double acc = md.sigma_s_mm + md.sigma_a_bg_mm;
+            for (int j = 0; j < md.n_dyes; ++j) {
+                const int y = md.dye[j];
+                const double kap = base * d.dyes[y].epsilon_M_cm * 1e-7 * ahat[(size_t)y * N + k];
+                acc += kap * md.conc_uM[j];
+                if (j < md.n_dyes - 1) img[P.off_cum + (m * cum_stride + j) * N + k] = fbits((float)acc);
+                img[P.off_kap + (m * kap_stride + j) * N + k] = fbits((float)kap);
+            }
+            const float st = (float)acc;
+            img[P.off_st + 2 * (m * N + k)] = fbits(st);
+            img[P.off_st + 2 * (m * N + k) + 1] = fbits(acc > 0.0 ? (float)(1.0 / acc) : INFINITY);
+            sc->h_st[(size_t)m * N + k] = st;
+        }
+    }
+    for (int i = 0; i < d.n_dyes; ++i) {
+        uint32_t* r = &img[P.off_dye + i * kDyeWords];
+        const double q = d.dyes[i].qy;
+        r[DW_QY] = fbits((float)q);
+        r[DW_INV_QY] = fbits(q > 0.0 ? (float)(1.0 / q) : 0.f);
+        r[DW_INV_1MQY] = fbits(q < 1.0 ? (float)(1.0 / (1.0 - q)) : 0.f);
+        r[DW_PQ] = (uint32_t)pq[i];
+        for (int k = 0; k < N; ++k) {
+            const float c = (float)cdf[(size_t)i * N + k];
+            img[P.off_cdf + i * N + k] = fbits(c);
+            sc->h_cdf[(size_t)i * N + k] = c;
+        }
+    }
+    if (d.geometry == FPT_GEOM_BOX) {
+        for (int f = 0; f < 6; ++f) {
+            for (int k = 0; k < N; ++k) {
+                const double r = (f == d.open_face) ? 0.0 : spectrum_at(d.walls[f], lam[k]);
+                if (!(r >= 0.0 && r <= 1.0)) return set_err(FPT_E_RANGE, "wall %d reflectance outside [0,1]", f);
+                img[P.off_rho + f * N + k] = fbits((float)r);
+                sc->h_rho[(size_t)f * N + k] = (float)r;
+            }
+        }
+    }
+    // light lines
+    double tot = 0.0;
+    for (int i = 0; i < d.n_lines; ++i) tot += d.line_power[i];
+    double c = 0.0;
+    sc->h_line_bin.assign(d.n_lines, 0);
+    for (int i = 0; i < d.n_lines; ++i) {
+        const int k = snap_line(d.line_nm[i], d.lo_nm, delta, N);
+        if (k < 0) return set_err(FPT_E_RANGE, "light line %g nm lies off the grid", d.line_nm[i]);
+        P.line_bin[i] = k;
+        sc->h_line_bin[i] = k;
+        c += d.line_power[i] / tot;
+        P.line_cum[i] = (float)c;
+    }
+    P.line_cum[d.n_lines - 1] = 1.0f;
+    P.n_lines = d.n_lines;
+    // geometry
+    P.geometry = d.geometry;
+    P.body_medium = d.body_medium;
+    P.light = d.light;
+    P.sensor = d.sensor;
+    P.z0 = (float)d.slab_z0;
+    P.z1 = (float)d.slab_z1;
+    for (int a = 0; a < 3; ++a) P.bc[a] = (float)d.body_center[a];
+    P.br2 = (float)(d.body_radius * d.body_radius);
+    for (int a = 0; a < 3; ++a) {
+        P.lo[a] = (float)d.box_lo[a];
+        P.hi[a] = (float)d.box_hi[a];
+    }
+    P.open_face = d.open_face;
+    P.n_spheres = d.geometry == FPT_GEOM_BOX ? d.n_spheres : 0;
+    for (int s = 0; s < P.n_spheres; ++s) {
+        for (int a = 0; a < 3; ++a) P.spheres[s].c[a] = (float)d.spheres[s].center[a];
+        P.spheres[s].r2 = (float)(d.spheres[s].radius * d.spheres[s].radius);
+        P.spheres[s].medium = d.spheres[s].medium;
+    }
+    double dir[3] = {d.light_dir[0], d.light_dir[1], d.light_dir[2]};
+    if (d.light == FPT_LIGHT_BEAM) norm3(dir);
+    for (int a = 0; a < 3; ++a) {
+        P.lpos[a] = (float)d.light_pos[a];
+        P.ldir[a] = (float)dir[a];
+        P.lu[a] = (float)d.light_u[a];
+        P.lv[a] = (float)d.light_v[a];
+    }
+    if (d.light == FPT_LIGHT_QUAD) {
+        double n[3], t1[3] = {d.light_u[0], d.light_u[1], d.light_u[2]}, t2[3];
+        cross3(d.light_u, d.light_v, n);
+        norm3(n);
+        norm3(t1);
+        cross3(n, t1, t2);
+        for (int a = 0; a < 3; ++a) {
+            P.ln[a] = (float)n[a];
+            P.lt1[a] = (float)t1[a];
+            P.lt2[a] = (float)t2[a];
+        }
+        P.lu_inv2 = (float)(1.0 / (d.light_u[0] * d.light_u[0] + d.light_u[1] * d.light_u[1] + d.light_u[2] * d.light_u[2]));
+        P.lv_inv2 = (float)(1.0 / (d.light_v[0] * d.light_v[0] + d.light_v[1] * d.light_v[1] + d.light_v[2] * d.light_v[2]));
+    }
+    if (d.sensor == FPT_SENSOR_PINHOLE) {
+        double f[3] = {d.look[0] - d.eye[0], d.look[1] - d.eye[1], d.look[2] - d.eye[2]}, r[3], u[3];
+        norm3(f);
+        cross3(f, d.up, r);
+        norm3(r);
+        cross3(r, f, u);
+        const double ty = std::tan(0.5 * d.fov_y_deg * M_PI / 180.0);
+        const double tx = ty * d.width / d.height;
+        for (int a = 0; a < 3; ++a) {
+            P.eye[a] = (float)d.eye[a];
+            P.cf[a] = (float)f[a];
+            P.cr[a] = (float)r[a];
+            P.cu[a] = (float)u[a];
+        }
+        P.inv_tanx = (float)(1.0 / tx);
+        P.inv_tany = (float)(1.0 / ty);
+        P.W = d.width;
+        P.H = d.height;
+        P.splat_norm = (float)((double)d.width * d.height / (4.0 * tx * ty));
+    }
+    P.np = np;
+    return FPT_OK;
+}
+
+int32_t upload_tables(fpt_scene* sc) {
+    const size_t bytes = sc->image.size() * 4;
+    if (!sc->d_tables) HIP_TRY(hipMalloc(&sc->d_tables, std::max<size_t>(bytes, 4)), "hipMalloc(tables)");
+    HIP_TRY(hipMemcpy(sc->d_tables, sc->image.data(), bytes, hipMemcpyHostToDevice), "upload tables");
+    return FPT_OK;
+}
+
+int64_t film_elems(const fpt_scene_desc& d, uint32_t B) {
+    if (d.sensor == FPT_SENSOR_PINHOLE) return (int64_t)B * 2 * d.height * (int64_t)d.width * d.n_bins;
+    return (int64_t)B * 2 * 2 * d.n_bins;
+}
+
+int32_t check_run(const fpt_scene* sc, const fpt_run* run, uint32_t* B) {
+    if (!run) return set_err(FPT_E_INVALID, "run is NULL");
+    if (run->total_paths == 0 || run->total_paths > (1ull << 32))
+        return set_err(FPT_E_RANGE, "total_paths must be in [1, 2^32]");
+    if (run->path_begin > run->total_paths || run->path_count > run->total_paths - run->path_begin)
+        return set_err(FPT_E_RANGE, "path range outside total_paths");
+    const uint32_t b = run->parity_batches ? run->parity_batches : 1u;
+    if (b > 64) return set_err(FPT_E_RANGE, "parity_batches %u > 64", b);
+    if (!(run->splat_rr >= 0.0 && run->splat_rr <= 1.0)) return set_err(FPT_E_RANGE, "splat_rr outside [0,1]");
+    if (run->flags & ~(FPT_FLAG_FLUORESCENCE_ONLY | FPT_FLAG_NO_EXCITATION_SCATTER))
+        return set_err(FPT_E_INVALID, "unknown run flags 0x%x", run->flags);
+    (void)sc;
+    *B = b;
+    return FPT_OK;
+}
+
+void fill_run(const fpt_scene* sc, const fpt_run* run, uint32_t B, KParams* P) {
+    *P = sc->base;
+    P->key0 = (uint32_t)run->seed;
+    P->key1 = (uint32_t)(run->seed >> 32) ^ run->instance;
+    P->path_begin = (uint32_t)run->path_begin;
+    P->path_count = (uint32_t)std::min<uint64_t>(run->path_count, 0xFFFFFFFFull);
+    P->batches = B;
+    P->wscale = (float)((double)B / (double)run->total_paths);
+    P->max_scatter = run->max_scatter;
+    P->max_emissions = run->max_emissions;
+    P->fluo_only = (run->flags & FPT_FLAG_FLUORESCENCE_ONLY) ? 1 : 0;
+    P->exc_scatter = (run->flags & FPT_FLAG_NO_EXCITATION_SCATTER) ? 0 : 1;
+    P->splat_rr = (float)run->splat_rr;
+    P->max_vertices = 0;
+    P->refill_lanes = sc->tune.refill_lanes > 0 ? std::min(64, sc->tune.refill_lanes) : 16;
+}
+
+int32_t ensure_scratch(fpt_scene* sc, size_t counts, size_t partials) {
+    if (!sc->d_counter) HIP_TRY(hipMalloc(&sc->d_counter, 64), "hipMalloc(counter)");
+    if (!sc->d_tally) HIP_TRY(hipMalloc(&sc->d_tally, FPT_N_TALLIES * 8), "hipMalloc(tally)");
+    if (counts > sc->counts_cap) {
+        if (sc->d_counts) (void)hipFree(sc->d_counts);
+        sc->d_counts = nullptr;
+        sc->counts_cap = 0;
+        HIP_TRY(hipMalloc(&sc->d_counts, counts * 4), "hipMalloc(counts)");
+        sc->counts_cap = counts;
+    }
+    if (partials > sc->partials_cap) {
+        if (sc->d_partials) (void)hipFree(sc->d_partials);
+        sc->d_partials = nullptr;
+        sc->partials_cap = 0;
+        HIP_TRY(hipMalloc(&sc->d_partials, partials * 4), "hipMalloc(partials)");
+        sc->partials_cap = partials;
+    }
+    return FPT_OK;
+}
+
+// Grid for a persistent launch: fill every CU at the kernel's occupancy, but
+// never more lanes than paths.
+int32_t grid_for(fpt_scene* sc, const KParams& P, int mode, int block, uint64_t paths, int* grid) {
+    int per_cu = 0;
+    HIP_TRY(transport_occupancy(P, mode, block, &per_cu), "occupancy query");
+    if (sc->tune.blocks_per_cu > 0) per_cu = std::min(per_cu, sc->tune.blocks_per_cu);
+    per_cu = std::max(per_cu, 1);
+    const uint64_t full = (uint64_t)sc->n_cu * per_cu;
+    const uint64_t need = (paths + block - 1) / block;
+    *grid = (int)std::max<uint64_t>(1, std::min(full, need));
+    return FPT_OK;
+}
+
+int block_for(const fpt_scene* sc) {
+    int b = sc->tune.block_threads > 0 ? sc->tune.block_threads : 256;
+    b = std::max(64, std::min(256, (b / 64) * 64));
+    return b;
+}
+
+}  // namespace
+
+extern "C" {
+
+uint32_t fpt_abi_version(void) { return FPT_ABI_VERSION; }
+
+const char* fpt_status_str(int32_t s) {
+    switch (s) {
+    case FPT_OK: return "ok";
+    case FPT_E_INVALID: return "invalid argument";
+    case FPT_E_RANGE: return "value out of range";
+    case FPT_E_NOMEM: return "out of memory";
+    case FPT_E_DEVICE: return "device error";
+    case FPT_E_UNSUPPORTED: return "unsupported";
+    default: return "unknown status";
+    }
+}
+
+const char* fpt_last_error(void) { return g_err.c_str(); }
+
+int32_t fpt_scene_create(const fpt_scene_desc* desc, fpt_scene** out) {
+    if (!desc || !out) return set_err(FPT_E_INVALID, "NULL argument");
+    *out = nullptr;
+    int32_t rc = validate(desc);
+    if (rc != FPT_OK) return rc;
+    fpt_scene* sc = new (std::nothrow) fpt_scene();
+    if (!sc) return set_err(FPT_E_NOMEM, "host allocation");
+    sc->desc = *desc;
+    std::memset(&sc->tune, 0, sizeof sc->tune);
+    if ((rc = build_tables(sc)) != FPT_OK) {
+        delete sc;
+        return rc;
+    }
+    hipError_t e = hipGetDevice(&sc->device);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&sc->n_cu, hipDeviceAttributeMultiprocessorCount, sc->device);
+    if (e != hipSuccess) {
+        delete sc;
+        return hip_err(e, "device query");
+    }
+    if ((rc = upload_tables(sc)) != FPT_OK || (rc = ensure_scratch(sc, 0, 0)) != FPT_OK) {
+        fpt_scene_destroy(sc);
+        return rc;
+    }
+    *out = sc;
+    return FPT_OK;
+}
+
+void fpt_scene_destroy(fpt_scene* sc) {
+    if (!sc) return;
+    if (sc->d_tables) (void)hipFree(sc->d_tables);
+    if (sc->d_counts) (void)hipFree(sc->d_counts);
+    if (sc->d_counter) (void)hipFree(sc->d_counter);
+    if (sc->d_tally) (void)hipFree(sc->d_tally);
+    if (sc->d_partials) (void)hipFree(sc->d_partials);
+    delete sc;
+}
+
+int32_t fpt_scene_set_params(fpt_scene* sc, const double* conc, const double* qy, const double* sigma_s) {
+    if (!sc) return set_err(FPT_E_INVALID, "NULL scene");
+    fpt_scene_desc d = sc->desc;
+    int k = 0;
+    for (int m = 0; m < d.n_media; ++m)
+        for (int j = 0; j < d.media[m].n_dyes; ++j, ++k)
+            if (conc) d.media[m].conc_uM[j] = conc[k];
+    if (qy)
+        for (int i = 0; i < d.n_dyes; ++i) d.dyes[i].qy = qy[i];
+    if (sigma_s)
+        for (int m = 0; m < d.n_media; ++m) d.media[m].sigma_s_mm = sigma_s[m];
+    int32_t rc = validate(&d);
+    if (rc != FPT_OK) return rc;
+    const fpt_scene_desc old = sc->desc;
+    sc->desc = d;
+    if ((rc = build_tables(sc)) != FPT_OK) {
+        sc->desc = old;
+        build_tables(sc);
+        return rc;
+    }
+    HIP_TRY(hipDeviceSynchronize(), "synchronise before table upload");
+    return upload_tables(sc);
+}
+
+int32_t fpt_film_shape(const fpt_scene* sc, uint32_t batches, int64_t dims[5], int32_t* ndims) {
+    if (!sc || !dims || !ndims) return set_err(FPT_E_INVALID, "NULL argument");
+    const int64_t B = batches ? batches : 1;
+    const fpt_scene_desc& d = sc->desc;
+    if (d.sensor == FPT_SENSOR_PINHOLE) {
+        dims[0] = B; dims[1] = 2; dims[2] = d.height; dims[3] = d.width; dims[4] = d.n_bins;
+        *ndims = 5;
+    } else {
+        dims[0] = B; dims[1] = 2; dims[2] = 2; dims[3] = d.n_bins; dims[4] = 0;
+        *ndims = 4;
+    }
+    return FPT_OK;
+}
+
+int32_t fpt_grad_param_count(const fpt_scene* sc) { return sc ? sc->np : set_err(FPT_E_INVALID, "NULL scene"); }
+
+int32_t fpt_scene_set_tune(fpt_scene* sc, const fpt_tune* tune) {
+    if (!sc) return set_err(FPT_E_INVALID, "NULL scene");
+    if (!tune) {
+        std::memset(&sc->tune, 0, sizeof sc->tune);
+        return FPT_OK;
+    }
+    if (tune->block_threads && (tune->block_threads < 64 || tune->block_threads > 256 || tune->block_threads % 64))
+        return set_err(FPT_E_RANGE, "block_threads must be 64..256 in steps of 64");
+    if (tune->refill_lanes < 0 || tune->refill_lanes > 64) return set_err(FPT_E_RANGE, "refill_lanes 0..64");
+    if (tune->blocks_per_cu < 0) return set_err(FPT_E_RANGE, "blocks_per_cu >= 0");
+    sc->tune = *tune;
+    return FPT_OK;
+}
+
+int32_t fpt_scene_tables(const fpt_scene* sc, float* sigma_t, float* emis_cdf, float* rho, int32_t* line_bin) {
+    if (!sc) return set_err(FPT_E_INVALID, "NULL scene");
+    if (sigma_t) std::memcpy(sigma_t, sc->h_st.data(), sc->h_st.size() * 4);
+    if (emis_cdf) std::memcpy(emis_cdf, sc->h_cdf.data(), (size_t)sc->desc.n_dyes * sc->desc.n_bins * 4);
+    if (rho) std::memcpy(rho, sc->h_rho.data(), sc->h_rho.size() * 4);
+    if (line_bin)
+        for (size_t i = 0; i < sc->h_line_bin.size(); ++i) line_bin[i] = sc->h_line_bin[i];
+    return FPT_OK;
+}
+
+int32_t fpt_render(fpt_scene* sc, const fpt_run* run, float* film, uint64_t* tallies, void* stream) {
+    if (!sc || !film) return set_err(FPT_E_INVALID, "NULL argument");
+    uint32_t B;
+    int32_t rc = check_run(sc, run, &B);
+    if (rc != FPT_OK) return rc;
+    if (run->path_count == 0) return FPT_OK;
+    hipStream_t s = (hipStream_t)stream;
+    KParams P;
+    fill_run(sc, run, B, &P);
+    const bool escape = sc->desc.sensor == FPT_SENSOR_ESCAPE;
+    const size_t n_counts = escape ? (size_t)film_elems(sc->desc, B) : 0;
+    if ((rc = ensure_scratch(sc, n_counts, 0)) != FPT_OK) return rc;
+    const int block = block_for(sc);
+    int grid;
+    if ((rc = grid_for(sc, P, MODE_FWD, block, run->path_count, &grid)) != FPT_OK) return rc;
+    KBuffers Bf;
+    std::memset(&Bf, 0, sizeof Bf);
+    Bf.tables = sc->d_tables;
+    Bf.film = film;
+    Bf.counts = sc->d_counts;
+    Bf.tallies = tallies ? reinterpret_cast<unsigned long long*>(tallies) : nullptr;
+    Bf.counter = sc->d_counter;
+    HIP_TRY(launch_zero_u64(sc->d_counter, 1, s), "zero queue");
+    if (escape) HIP_TRY(launch_zero_u32(sc->d_counts, n_counts, s), "zero counts");
+    HIP_TRY(launch_transport(P, Bf, MODE_FWD, grid, block, s), "transport launch");
+    if (escape) HIP_TRY(launch_finalize_counts(sc->d_counts, film, n_counts, P.wscale, s), "finalize");
+    return FPT_OK;
+}
+
+int32_t fpt_render_adjoint(fpt_scene* sc, const fpt_run* run, const float* gfilm, float* grad,
+                           uint64_t* tallies, void* stream) {
+    if (!sc || !gfilm || !grad) return set_err(FPT_E_INVALID, "NULL argument");
+    uint32_t B;
+    int32_t rc = check_run(sc, run, &B);
+    if (rc != FPT_OK) return rc;
+    if (sc->np > kMaxNP) return set_err(FPT_E_UNSUPPORTED, "%d gradient parameters > %d", sc->np, kMaxNP);
+    if (run->path_count == 0) return FPT_OK;
+    hipStream_t s = (hipStream_t)stream;
+    KParams P;
+    fill_run(sc, run, B, &P);
+    const int block = block_for(sc);
+    int grid;
+    if ((rc = grid_for(sc, P, MODE_ADJ, block, run->path_count, &grid)) != FPT_OK) return rc;
+    if ((rc = ensure_scratch(sc, 0, (size_t)grid * kMaxNP)) != FPT_OK) return rc;
+    KBuffers Bf;
+    std::memset(&Bf, 0, sizeof Bf);
+    Bf.tables = sc->d_tables;
+    Bf.tallies = tallies ? reinterpret_cast<unsigned long long*>(tallies) : nullptr;
+    Bf.counter = sc->d_counter;
+    Bf.gfilm = gfilm;
+    Bf.partials = sc->d_partials;
+    HIP_TRY(launch_zero_u64(sc->d_counter, 1, s), "zero queue");
+    HIP_TRY(launch_transport(P, Bf, MODE_ADJ, grid, block, s), "adjoint launch");
+    HIP_TRY(launch_reduce_partials(sc->d_partials, grid, sc->np, grad, s), "gradient reduction");
+    return FPT_OK;
+}
+
+int32_t fpt_render_records(fpt_scene* sc, const fpt_run* run, fpt_path_record* rec, uint32_t max_vertices,
+                           const float* gfilm, float* rec_grad, void* stream) {
+    if (!sc || !rec) return set_err(FPT_E_INVALID, "NULL argument");
+    if ((gfilm == nullptr) != (rec_grad == nullptr))
+        return set_err(FPT_E_INVALID, "grad_film and rec_grad go together");
+    uint32_t B;
+    int32_t rc = check_run(sc, run, &B);
+    if (rc != FPT_OK) return rc;
+    if (gfilm && sc->np > kMaxNP) return set_err(FPT_E_UNSUPPORTED, "too many gradient parameters");
+    if (run->path_count == 0) return FPT_OK;
+    hipStream_t s = (hipStream_t)stream;
+    KParams P;
+    fill_run(sc, run, B, &P);
+    P.max_vertices = max_vertices;
+    const int mode = gfilm ? MODE_REC_ADJ : MODE_REC;
+    const int block = block_for(sc);
+    int grid;
+    if ((rc = grid_for(sc, P, mode, block, run->path_count, &grid)) != FPT_OK) return rc;
+    KBuffers Bf;
+    std::memset(&Bf, 0, sizeof Bf);
+    Bf.tables = sc->d_tables;
+    Bf.counter = sc->d_counter;
+    Bf.gfilm = gfilm;
+    Bf.rec = rec;
+    Bf.rec_grad = rec_grad;
+    HIP_TRY(launch_zero_u64(sc->d_counter, 1, s), "zero queue");
+    HIP_TRY(launch_transport(P, Bf, mode, grid, block, s), "records launch");
+    return FPT_OK;
+}
+
+int32_t fpt_batch_create(const fpt_scene_desc*, const fpt_run*, int32_t, const fpt_tune*, fpt_batch** out) {
+    if (out) *out = nullptr;
+    return set_err(FPT_E_UNSUPPORTED, "batched form not built yet");
+}
+int32_t fpt_batch_render(fpt_batch*, float*, uint64_t*, void*) {
+    return set_err(FPT_E_UNSUPPORTED, "batched form not built yet");
+}
+void fpt_batch_destroy(fpt_batch*) {}
+int32_t fpt_autotune(fpt_scene*, const fpt_run*, fpt_batch*, fpt_tune*, float*) {
+    return set_err(FPT_E_UNSUPPORTED, "autotuner not built yet");
+}
+
+}  // extern "C"

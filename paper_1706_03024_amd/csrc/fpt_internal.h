@@ -1,0 +1,119 @@
+// Internal structures shared by the fpt host library and its HIP kernels.
+#pragma once
+
+#include <stdint.h>
+
+#include "fpt.h"
+
+namespace fpt {
+
+constexpr int kMaxNP = FPT_MAX_GRAD_PARAMS;
+constexpr int kMedWords = 20;  // words per medium record in the table image
+constexpr int kDyeWords = 4;   // words per dye record
+
+// Medium record (32-bit words) in the table image:
+//   0 sigma_s  1 sigma_s + sigma_a_bg  2 n_dyes (int)  3 1/sigma_s
+//   4..7 dye index per slot (int)  8..11 1/conc per slot
+//   12 gradient index of sigma_s (int)  13..16 gradient index of conc per slot (int)
+// Dye record: 0 qy  1 1/qy  2 1/(1-qy)  3 gradient index of qy (int)
+enum { MW_SS = 0, MW_THR_BG = 1, MW_NDYES = 2, MW_INV_SS = 3, MW_DYE = 4, MW_INV_C = 8,
+       MW_PSS = 12, MW_PC = 13 };
+enum { DW_QY = 0, DW_INV_QY = 1, DW_INV_1MQY = 2, DW_PQ = 3 };
+
+struct KSphere {
+    float c[3];
+    float r2;
+    int medium;
+    int pad[3];
+};
+
+// Everything a launch needs that is uniform across the grid (kernel argument).
+struct KParams {
+    // table image (32-bit word offsets); staged into LDS by every block
+    int N;
+    int table_words;
+    int off_med, off_dye;
+    int off_st;     // float2 [n_media][N]: sigma_t, 1/sigma_t (+inf where sigma_t = 0)
+    int off_cum;    // float [n_media][cum_stride][N]: absolute thresholds of dye slots 0..n-2
+    int cum_stride;
+    int off_cdf;    // float [n_dyes][N]: emission CDF, last entry exactly 1
+    int off_rho;    // float [6][N]
+    int off_kap;    // float [n_media][kap_stride][N]: d sigma_a / d conc per slot
+    int kap_stride;
+    int n_media, n_dyes, n_spheres, n_lines;
+    KSphere spheres[FPT_MAX_SPHERES];
+    float line_cum[FPT_MAX_LINES];
+    int line_bin[FPT_MAX_LINES];
+    int geometry, body_medium, light, sensor;
+    float z0, z1;
+    float bc[3], br2;
+    float lo[3], hi[3];
+    int open_face;
+    float lpos[3], ldir[3], lu[3], lv[3], ln[3], lt1[3], lt2[3];
+    float lu_inv2, lv_inv2;
+    float eye[3], cf[3], cr[3], cu[3];
+    float inv_tanx, inv_tany;
+    int W, H;
+    float splat_norm;  // N_pix / A_img
+    // run
+    uint32_t key0, key1;
+    uint32_t path_begin, path_count;
+    uint32_t batches;
+    float wscale;  // batches / total_paths
+    uint32_t max_scatter, max_emissions;
+    int fluo_only, exc_scatter;
+    float splat_rr;
+    uint32_t max_vertices;
+    int np;
+    int refill_lanes;
+};
+
+struct KBuffers {
+    const uint32_t* tables;        // table image in device memory
+    float* film;                   // camera film (pinhole)
+    uint32_t* counts;              // escape counts [B][2][2][N]
+    unsigned long long* tallies;   // FPT_N_TALLIES
+    unsigned long long* counter;   // path queue head
+    const float* gfilm;            // adjoint seed (film shape)
+    float* partials;               // adjoint: [grid blocks][kMaxNP]
+    fpt_path_record* rec;          // records mode
+    float* rec_grad;               // records mode, [path_count][np]
+};
+
+// Batched form: one work item = a path range of one instance.
+struct KWorkItem {
+    uint32_t instance;   // index into the instance arrays
+    uint32_t path_lo;    // first path index (relative to the instance's path_begin)
+    uint32_t path_hi;
+    uint32_t pad;
+};
+
+struct KInstance {
+    uint32_t key0, key1;
+    uint32_t path_begin;
+    float wscale;
+    int geometry;        // FPT_GEOM_SLAB or FPT_GEOM_SPHERE
+    float z0, z1;
+    float bc[3], br2;
+    float lpos[3], ldir[3];
+    float line_cum[FPT_MAX_LINES];
+    int line_bin[FPT_MAX_LINES];
+    int n_lines;
+    uint32_t table_offset;  // word offset of this instance's table image
+    uint32_t table_words;
+    uint32_t max_scatter, max_emissions;
+    int exc_scatter;
+    int pad[2];
+};
+
+struct KBatchParams {
+    int N;
+    int n_items;
+    int n_instances;
+    int max_table_words;  // LDS words per wave slot
+    int cum_stride, kap_stride;
+    int off_med, off_dye, off_st, off_cum, off_cdf;
+    int refill_lanes;
+};
+
+}  // namespace fpt

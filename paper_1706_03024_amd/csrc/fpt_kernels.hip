@@ -1,0 +1,852 @@
+// HIP kernels of the fluorescent spectral path tracer (gfx950, wave64).
+//
+// One persistent kernel per geometry class runs the whole per-vertex loop of
+// the forward analog walk (sec. 4.1-4.3 of the paper): free flight from
+// sigma_t(lambda) (eq. 6), the scatter / absorber choice, the quantum-yield
+// test and re-emission from the emission CDF (eq. 10), interface and wall
+// handling, and the film splat (eqs. 3-6).  Path state lives in registers;
+// each wave keeps 64 paths in flight and, whenever enough of its lanes have
+// finished, claims new path ids for them with one atomic on a device queue
+// head (ballot + popcount + mbcnt prefix), so lanes stay busy without any
+// state round trip through HBM.  Spectral tables live in LDS.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "fpt_internal.h"
+
+namespace fpt {
+
+#define DEV __device__ __forceinline__
+
+constexpr float kInf = __builtin_inff();
+constexpr uint32_t kMaxPathVertices = 1u << 28;
+constexpr float kInv4Pi = 0.0795774715459476679f;
+constexpr float kInvPi = 0.318309886183790672f;
+
+enum { MODE_FWD = 0, MODE_ADJ = 1, MODE_REC = 2, MODE_REC_ADJ = 3 };
+enum { EV_NONE = 0, EV_SCATTER, EV_BG, EV_DYE, EV_ESC, EV_WALL, EV_LIGHT, EV_ENTER, EV_EXIT,
+       EV_INF };
+enum { PEND_NONE = 0, PEND_MEDIUM = 1, PEND_SURFACE = 2, PEND_SOURCE = 3 };
+
+// -------------------------------------------------------------------------
+// Philox4x32-10 (Salmon et al., SC'11): ten rounds of two 32x32->64 products;
+// the high halves are xor-ed with the other counter words and the round key,
+// which advances by the two Weyl increments.  The key is uniform per launch
+// (kept in scalar registers); the products map to v_mad_u64_u32.
+DEV uint4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int i = 0; i < 10; ++i) {
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        c1 = (uint32_t)p1;
+        c3 = (uint32_t)p0;
+        c0 = n0;
+        c2 = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return make_uint4(c0, c1, c2, c3);
+}
+
+// 24 high bits -> [0,1), exact in fp32.
+DEV float u24(uint32_t x) { return (float)(x >> 8) * 5.9604644775390625e-08f; }
+DEV uint32_t rr_bits(const uint4 r) {
+    return ((r.x & 0xFFu) << 16) | ((r.y & 0xFFu) << 8) | (r.z & 0xFFu);
+}
+
+DEV float wf(const uint32_t* S, int i) { return __uint_as_float(S[i]); }
+DEV int wi(const uint32_t* S, int i) { return (int)S[i]; }
+DEV float dot3(const float* a, const float* b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+
+DEV uint32_t lane_id() { return __lane_id(); }
+DEV uint32_t mbcnt(uint64_t m) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+struct Lane {
+    float x[3], w[3];
+    float sc[3], sr2;  // the sphere the lane is inside (box scenes)
+    float st, inv;     // sigma_t and 1/sigma_t at (medium, lambda); inv = inf in vacuum
+    float ss, thr_bg;  // scatter / background thresholds of the medium
+    int ndy;           // dye slots of the medium
+    int lam, region, medium, comp;
+    uint32_t pid, v, nsc, nem, batch;
+    float splat_sum;
+};
+
+DEV void load_sigma(const KParams& P, const uint32_t* S, Lane& L) {
+    if (L.medium < 0) {
+        L.st = 0.f;
+        L.inv = kInf;
+        return;
+    }
+    const float2 v = *reinterpret_cast<const float2*>(S + P.off_st + 2 * (L.medium * P.N + L.lam));
+    L.st = v.x;
+    L.inv = v.y;
+}
+
+DEV void load_medium(const KParams& P, const uint32_t* S, Lane& L) {
+    if (L.medium < 0) {
+        L.ss = 0.f;
+        L.thr_bg = 0.f;
+        L.ndy = 0;
+    } else {
+        const int b = P.off_med + L.medium * kMedWords;
+        L.ss = wf(S, b + MW_SS);
+        L.thr_bg = wf(S, b + MW_THR_BG);
+        L.ndy = wi(S, b + MW_NDYES);
+    }
+    load_sigma(P, S, L);
+}
+
+// -------------------------------------------------------------------------
+// Geometry: distance to the next surface along the lane's ray.
+struct Hit {
+    float d;
+    int ev;   // EV_ESC, EV_WALL, EV_LIGHT, EV_ENTER, EV_EXIT, EV_INF
+    int idx;  // wall face or sphere
+};
+
+DEV float sphere_exit(const float* x, const float* w, const float* c, float r2) {
+    const float o0 = x[0] - c[0], o1 = x[1] - c[1], o2 = x[2] - c[2];
+    const float b = o0 * w[0] + o1 * w[1] + o2 * w[2];
+    const float cc = o0 * o0 + o1 * o1 + o2 * o2 - r2;
+    const float disc = b * b - cc;
+    return fmaxf(0.f, -b + sqrtf(fmaxf(disc, 0.f)));
+}
+
+template <int GEOM>
+DEV Hit next_surface(const KParams& P, const Lane& L, bool skip_light) {
+    Hit h;
+    h.d = kInf;
+    h.ev = EV_ESC;
+    h.idx = -1;
+    if constexpr (GEOM == FPT_GEOM_SLAB) {
+        if (L.w[2] > 0.f) h.d = (P.z1 - L.x[2]) / L.w[2];
+        else if (L.w[2] < 0.f) h.d = (P.z0 - L.x[2]) / L.w[2];
+        h.d = fmaxf(h.d, 0.f);
+    } else if constexpr (GEOM == FPT_GEOM_HALFSPACE) {
+        if (L.w[2] < 0.f) h.d = fmaxf((P.z0 - L.x[2]) / L.w[2], 0.f);
+    } else if constexpr (GEOM == FPT_GEOM_SPHERE) {
+        h.d = sphere_exit(L.x, L.w, P.bc, P.br2);
+    } else if constexpr (GEOM == FPT_GEOM_INFINITE) {
+        h.ev = EV_ESC;
+    } else {
+        if (L.region >= 0) {
+            h.d = sphere_exit(L.x, L.w, L.sc, L.sr2);
+            h.ev = EV_EXIT;
+            h.idx = L.region;
+            return h;
+        }
+        // vacuum: box walls
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            float t = kInf;
+            int f = -1;
+            if (L.w[a] > 0.f) { t = (P.hi[a] - L.x[a]) / L.w[a]; f = 2 * a + 1; }
+            else if (L.w[a] < 0.f) { t = (P.lo[a] - L.x[a]) / L.w[a]; f = 2 * a; }
+            t = fmaxf(t, 0.f);
+            if (t < h.d) { h.d = t; h.idx = f; }
+        }
+        h.ev = (h.idx == P.open_face) ? EV_ESC : EV_WALL;
+        // light quad (opaque, both sides)
+        if (!skip_light) {
+            const float dn = dot3(P.ln, L.w);
+            if (dn != 0.f) {
+                const float pc0 = P.lpos[0] - L.x[0], pc1 = P.lpos[1] - L.x[1], pc2 = P.lpos[2] - L.x[2];
+                const float t = (P.ln[0] * pc0 + P.ln[1] * pc1 + P.ln[2] * pc2) / dn;
+                if (t > 0.f && t < h.d) {
+                    const float q0 = L.x[0] + t * L.w[0] - P.lpos[0];
+                    const float q1 = L.x[1] + t * L.w[1] - P.lpos[1];
+                    const float q2 = L.x[2] + t * L.w[2] - P.lpos[2];
+                    const float a = (q0 * P.lu[0] + q1 * P.lu[1] + q2 * P.lu[2]) * P.lu_inv2;
+                    const float b = (q0 * P.lv[0] + q1 * P.lv[1] + q2 * P.lv[2]) * P.lv_inv2;
+                    if (a >= 0.f && a <= 1.f && b >= 0.f && b <= 1.f) {
+                        h.d = t;
+                        h.ev = EV_LIGHT;
+                        h.idx = -1;
+                    }
+                }
+            }
+        }
+        // sphere entries
+        for (int s = 0; s < P.n_spheres; ++s) {
+            const KSphere& sp = P.spheres[s];
+            const float o0 = L.x[0] - sp.c[0], o1 = L.x[1] - sp.c[1], o2 = L.x[2] - sp.c[2];
+            const float b = o0 * L.w[0] + o1 * L.w[1] + o2 * L.w[2];
+            if (!(b < 0.f)) continue;
+            const float cc = o0 * o0 + o1 * o1 + o2 * o2 - sp.r2;
+            const float disc = b * b - cc;
+            if (!(disc > 0.f)) continue;
+            const float t = fmaxf(-b - sqrtf(disc), 0.f);
+            if (t < h.d) { h.d = t; h.ev = EV_ENTER; h.idx = s; }
+        }
+    }
+    return h;
+}
+
+// Length of the segment x + t wc, t in [0, dist], inside a sphere.
+DEV float chord_len(const KSphere& sp, const float* x, const float* wc, float dist) {
+    const float o0 = x[0] - sp.c[0], o1 = x[1] - sp.c[1], o2 = x[2] - sp.c[2];
+    const float b = o0 * wc[0] + o1 * wc[1] + o2 * wc[2];
+    const float cc = o0 * o0 + o1 * o1 + o2 * o2 - sp.r2;
+    const float disc = b * b - cc;
+    if (!(disc > 0.f)) return 0.f;
+    const float sq = sqrtf(disc);
+    const float lo = fmaxf(-b - sq, 0.f), hi = fminf(-b + sq, dist);
+    return fmaxf(hi - lo, 0.f);
+}
+
+// -------------------------------------------------------------------------
+// Pinhole splat at a realised vertex (eqs. 3-6).  Returns the deposited value
+// (0 if rejected) and the film index; chord lengths go to `chord` for the
+// adjoint.  f = 1/(4 pi) in a medium, cos/pi on a Lambertian surface.
+struct SplatOut {
+    float v;
+    long long idx;
+    int status;  // 0 hit, 1 miss, 2 roulette kill
+};
+
+DEV SplatOut splat_eval(const KParams& P, const uint32_t* S, const Lane& L, int pend,
+                        const float* nrm, uint32_t rrb) {
+    SplatOut o;
+    o.v = 0.f;
+    o.idx = -1;
+    o.status = 1;
+    const float d0 = P.eye[0] - L.x[0], d1 = P.eye[1] - L.x[1], d2 = P.eye[2] - L.x[2];
+    const float dist2 = d0 * d0 + d1 * d1 + d2 * d2;
+    const float rdist = rsqrtf(dist2);
+    const float dist = dist2 * rdist;
+    const float wc[3] = {d0 * rdist, d1 * rdist, d2 * rdist};
+    float f = kInv4Pi;
+    if (pend != PEND_MEDIUM) {
+        const float cs = dot3(nrm, wc);
+        if (!(cs > 0.f)) return o;
+        f = cs * kInvPi;
+    }
+    const float zc = -(d0 * P.cf[0] + d1 * P.cf[1] + d2 * P.cf[2]);
+    if (!(zc > 0.f)) return o;
+    const float izc = 1.f / zc;
+    const float xi = -(d0 * P.cr[0] + d1 * P.cr[1] + d2 * P.cr[2]) * izc * P.inv_tanx;
+    const float yi = -(d0 * P.cu[0] + d1 * P.cu[1] + d2 * P.cu[2]) * izc * P.inv_tany;
+    const float fx = (xi + 1.f) * 0.5f * (float)P.W;
+    const float fy = (1.f - yi) * 0.5f * (float)P.H;
+    if (!(fx >= 0.f && fx < (float)P.W && fy >= 0.f && fy < (float)P.H)) return o;
+    const int px = min((int)fx, P.W - 1), py = min((int)fy, P.H - 1);
+    // visibility: leave the box through the open face
+    {
+        float tmin = kInf;
+        int fmin_ = -1;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const float da = a == 0 ? d0 : (a == 1 ? d1 : d2);
+            float t = kInf;
+            int fc = -1;
+            if (da > 0.f) { t = (P.hi[a] - L.x[a]) / da; fc = 2 * a + 1; }
+            else if (da < 0.f) { t = (P.lo[a] - L.x[a]) / da; fc = 2 * a; }
+            if (t < tmin) { tmin = t; fmin_ = fc; }
+        }
+        if (fmin_ != P.open_face || !(tmin < 1.f)) return o;
+        if (pend != PEND_SOURCE) {
+            const float dn = P.ln[0] * d0 + P.ln[1] * d1 + P.ln[2] * d2;
+            if (dn != 0.f) {
+                const float pc0 = P.lpos[0] - L.x[0], pc1 = P.lpos[1] - L.x[1], pc2 = P.lpos[2] - L.x[2];
+                const float t = (P.ln[0] * pc0 + P.ln[1] * pc1 + P.ln[2] * pc2) / dn;
+                if (t > 0.f && t < 1.f) {
+                    const float q0 = L.x[0] + t * d0 - P.lpos[0];
+                    const float q1 = L.x[1] + t * d1 - P.lpos[1];
+                    const float q2 = L.x[2] + t * d2 - P.lpos[2];
+                    const float a = (q0 * P.lu[0] + q1 * P.lu[1] + q2 * P.lu[2]) * P.lu_inv2;
+                    const float b = (q0 * P.lv[0] + q1 * P.lv[1] + q2 * P.lv[2]) * P.lv_inv2;
+                    if (a >= 0.f && a <= 1.f && b >= 0.f && b <= 1.f) return o;
+                }
+            }
+        }
+    }
+    // transmittance along the connection, through every sphere (eq. 6)
+    float tau = 0.f;
+    for (int s = 0; s < P.n_spheres; ++s) {
+        const float len = chord_len(P.spheres[s], L.x, wc, dist);
+        if (len > 0.f) tau += wf(S, P.off_st + 2 * (P.spheres[s].medium * P.N + L.lam)) * len;
+    }
+    const float tr = __expf(-tau);
+    const float cosc = zc * rdist;
+    float v = P.wscale * f * tr * P.splat_norm / (cosc * cosc * cosc * dist2);
+    if (P.splat_rr > 0.f && tr < P.splat_rr) {
+        const float q = tr / P.splat_rr;
+        const float u = (float)rrb * 5.9604644775390625e-08f;
+        if (!(u < q)) {
+            o.status = 2;
+            return o;
+        }
+        v = v / q;
+    }
+    o.v = v;
+    o.status = 0;
+    o.idx = ((((long long)L.batch * 2 + L.comp) * P.H + py) * P.W + px) * (long long)P.N + L.lam;
+    return o;
+}
+
+// Per-block LDS tally of rare events (u32) and per-lane counters of frequent ones.
+struct Counters {
+    uint32_t vertices, scatters, splat_hit;
+};
+
+DEV void lds_count(uint32_t* tally, int slot) { atomicAdd(&tally[slot], 1u); }
+
+// -------------------------------------------------------------------------
+// Per-lane adjoint state lives in LDS: the running score S (d log p / d theta
+// of the path prefix) and the chord part of the gradient, one slot per lane
+// and parameter ([wave][param][lane], conflict free).
+struct AdjView {
+    float* S;   // + i*64
+    float* Gx;  // + i*64
+};
+
+DEV void adj_add(float* base, int i, float v) { base[i * 64] += v; }
+
+template <int MODE>
+DEV void score_length(const KParams& P, const uint32_t* T, const Lane& L, AdjView& A, float len) {
+    if constexpr (MODE == MODE_ADJ || MODE == MODE_REC_ADJ) {
+        if (L.medium < 0 || !(len > 0.f)) return;
+        const int b = P.off_med + L.medium * kMedWords;
+        adj_add(A.S, wi(T, b + MW_PSS), -len);
+        for (int j = 0; j < L.ndy; ++j)
+            adj_add(A.S, wi(T, b + MW_PC + j),
+                    -wf(T, P.off_kap + (L.medium * P.kap_stride + j) * P.N + L.lam) * len);
+    }
+}
+
+// -------------------------------------------------------------------------
+// The persistent transport kernel.
+template <int GEOM, int MODE>
+__global__ void __launch_bounds__(256) k_transport(const KParams P, const KBuffers B) {
+    constexpr bool ADJ = (MODE == MODE_ADJ || MODE == MODE_REC_ADJ);
+    constexpr bool REC = (MODE == MODE_REC || MODE == MODE_REC_ADJ);
+    extern __shared__ uint32_t smem[];
+    uint32_t* tally = smem;            // FPT_N_TALLIES u32, block-wide
+    const uint32_t* T = smem + 32;     // table image
+    for (int i = threadIdx.x; i < FPT_N_TALLIES; i += blockDim.x) tally[i] = 0u;
+    for (int i = threadIdx.x; i < P.table_words; i += blockDim.x) smem[32 + i] = B.tables[i];
+    const int wave = threadIdx.x >> 6;
+    const uint32_t lane = lane_id();
+    AdjView A;
+    float G[ADJ ? kMaxNP : 1];
+    if constexpr (ADJ) {
+        float* base = reinterpret_cast<float*>(smem + 32 + ((P.table_words + 63) & ~63)) +
+                      wave * (2 * kMaxNP * 64) + lane;
+        A.S = base;
+        A.Gx = base + kMaxNP * 64;
+#pragma unroll
+        for (int i = 0; i < kMaxNP; ++i) {
+            A.S[i * 64] = 0.f;
+            A.Gx[i * 64] = 0.f;
+            G[i] = 0.f;
+        }
+    }
+    __syncthreads();
+
+    const bool pinhole = (GEOM == FPT_GEOM_BOX) && P.sensor == FPT_SENSOR_PINHOLE;
+    Counters cnt = {0u, 0u, 0u};
+    Lane L;
+    L.pid = 0;
+    bool alive = false;
+    bool exhausted = false;
+    int pend = PEND_NONE;
+    float nrm[3] = {0.f, 0.f, 0.f};
+    uint32_t rrb = 0;
+
+    for (;;) {
+        // ---- refill dead lanes from the path queue (one atomic per wave)
+        bool fresh = false;
+        if (!exhausted) {
+            const uint64_t dead = __ballot(!alive);
+            const int ndead = __popcll(dead);
+            if (ndead >= P.refill_lanes || ndead == 64) {
+                unsigned long long base = 0;
+                if (lane == 0) base = atomicAdd(B.counter, (unsigned long long)ndead);
+                base = __shfl(base, 0);
+                if (base + (unsigned long long)ndead >= (unsigned long long)P.path_count) exhausted = true;
+                if (!alive) {
+                    const unsigned long long idx = base + mbcnt(dead);
+                    if (idx < (unsigned long long)P.path_count) {
+                        // ---- vertex 0: the light (eq. 12: light point, excitation wavelength)
+                        alive = true;
+                        fresh = true;
+                        L.pid = P.path_begin + (uint32_t)idx;
+                        L.v = 0;
+                        L.nsc = 0;
+                        L.nem = 0;
+                        L.comp = 0;
+                        L.batch = L.pid % P.batches;
+                        L.splat_sum = 0.f;
+                        const uint4 r = philox(L.pid, 0u, 0u, 0u, P.key0, P.key1);
+                        const float u = u24(r.x);
+                        int line = 0;
+                        for (; line < P.n_lines - 1; ++line)
+                            if (u < P.line_cum[line]) break;
+                        L.lam = P.line_bin[line];
+                        if (P.light == FPT_LIGHT_BEAM) {
+                            L.x[0] = P.lpos[0]; L.x[1] = P.lpos[1]; L.x[2] = P.lpos[2];
+                            L.w[0] = P.ldir[0]; L.w[1] = P.ldir[1]; L.w[2] = P.ldir[2];
+                            L.region = 0;
+                        } else {
+                            const uint4 r1 = philox(L.pid, 0u, 1u, 0u, P.key0, P.key1);
+                            const float ua = u24(r1.x), ub = u24(r1.y);
+                            float sp, cp;
+                            sincospif(2.f * ub, &sp, &cp);
+                            if (P.light == FPT_LIGHT_POINT) {
+                                L.x[0] = P.lpos[0]; L.x[1] = P.lpos[1]; L.x[2] = P.lpos[2];
+                                const float ct = 1.f - 2.f * ua;
+                                const float st = 2.f * sqrtf(ua * (1.f - ua));
+                                L.w[0] = st * cp; L.w[1] = st * sp; L.w[2] = ct;
+                                L.region = 0;
+                            } else {
+                                const float a = u24(r.y), b = u24(r.z);
+                                const float sr = sqrtf(ua), cz = sqrtf(1.f - ua);
+                                const float lx = sr * cp, ly = sr * sp;
+#pragma unroll
+                                for (int i = 0; i < 3; ++i) {
+                                    L.x[i] = P.lpos[i] + a * P.lu[i] + b * P.lv[i];
+                                    L.w[i] = lx * P.lt1[i] + ly * P.lt2[i] + cz * P.ln[i];
+                                }
+                                L.region = -1;
+                            }
+                        }
+                        L.medium = (GEOM == FPT_GEOM_BOX) ? -1 : P.body_medium;
+                        load_medium(P, T, L);
+                        cnt.vertices++;
+                        if constexpr (ADJ) {
+#pragma unroll
+                            for (int i = 0; i < kMaxNP; ++i) A.S[i * 64] = 0.f;
+                        }
+                        if (pinhole && P.light == FPT_LIGHT_QUAD) {
+                            pend = PEND_SOURCE;
+                            nrm[0] = P.ln[0]; nrm[1] = P.ln[1]; nrm[2] = P.ln[2];
+                            rrb = rr_bits(r);
+                        }
+                    }
+                }
+            }
+        }
+        if (__ballot(alive) == 0ull) {
+            if (exhausted) break;
+            continue;
+        }
+
+        // ---- one segment of the walk for every live lane with no pending splat
+        int ev = EV_NONE;
+        int exit_code = -1;
+        if (alive && !(fresh && pend != PEND_NONE)) {
+            L.v++;
+            if (REC && P.max_vertices && L.v >= P.max_vertices) {
+                exit_code = FPT_EXIT_TRUNC;
+            } else if (L.v >= kMaxPathVertices) {
+                exit_code = FPT_EXIT_SCAP;  // hard bound: every wave's loop terminates
+            } else {
+                cnt.vertices++;
+                const uint4 r = philox(L.pid, L.v, 0u, 0u, P.key0, P.key1);
+                const float u0 = u24(r.x), u1 = u24(r.y), u2 = u24(r.z), u3 = u24(r.w);
+                // eq. 6: free flight with density sigma_t exp(-sigma_t t)
+                const float tf = (L.inv == kInf) ? kInf : -__logf(1.f - u0) * L.inv;
+                const Hit h = next_surface<GEOM>(P, L, GEOM == FPT_GEOM_BOX && L.v == 1u);
+                const bool collide = tf < h.d;
+                const float len = collide ? tf : h.d;
+                if (len < kInf) {
+                    L.x[0] += len * L.w[0];
+                    L.x[1] += len * L.w[1];
+                    L.x[2] += len * L.w[2];
+                    score_length<MODE>(P, T, L, A, len);
+                }
+                float dir_sin = 0.f, dir_cos = 0.f;  // polar sine/cosine of a new direction
+                int frame = -1;                      // -1 world axes, else wall face
+                if (collide) {
+                    const float s = u1 * L.st;
+                    if (s < L.ss) {
+                        // elastic scattering, isotropic phase function (eq. 2)
+                        ev = EV_SCATTER;
+                        if constexpr (ADJ)
+                            adj_add(A.S, wi(T, P.off_med + L.medium * kMedWords + MW_PSS),
+                                    wf(T, P.off_med + L.medium * kMedWords + MW_INV_SS));
+                        L.nsc++;
+                        cnt.scatters++;
+                        if (!P.exc_scatter && L.nem == 0u) exit_code = FPT_EXIT_EXCSCAT;
+                        else if (L.nsc > P.max_scatter) exit_code = FPT_EXIT_SCAP;
+                        else {
+                            dir_cos = 1.f - 2.f * u2;
+                            dir_sin = 2.f * sqrtf(u2 * (1.f - u2));
+                            pend = PEND_MEDIUM;
+                        }
+                    } else if (s < L.thr_bg || L.ndy == 0) {
+                        ev = EV_BG;
+                        exit_code = FPT_EXIT_BG;
+                    } else {
+                        // a fluorescent particle: which dye slot (sec. 4.1)
+                        ev = EV_DYE;
+                        int j = 0;
+                        const int cb = P.off_cum + L.medium * P.cum_stride * P.N + L.lam;
+                        for (; j < L.ndy - 1; ++j)
+                            if (s < wf(T, cb + j * P.N)) break;
+                        const int mb = P.off_med + L.medium * kMedWords;
+                        if constexpr (ADJ) adj_add(A.S, wi(T, mb + MW_PC + j), wf(T, mb + MW_INV_C + j));
+                        lds_count(tally, FPT_T_DYE_ABS);
+                        if (L.nem >= P.max_emissions) {
+                            exit_code = FPT_EXIT_KCAP;
+                        } else {
+                            const int dye = wi(T, mb + MW_DYE + j);
+                            const int db = P.off_dye + dye * kDyeWords;
+                            const uint4 r1 = philox(L.pid, L.v, 1u, 0u, P.key0, P.key1);
+                            const float uq = u24(r1.x);
+                            if (!(uq < wf(T, db + DW_QY))) {
+                                if constexpr (ADJ) adj_add(A.S, wi(T, db + DW_PQ), -wf(T, db + DW_INV_1MQY));
+                                exit_code = FPT_EXIT_NONRAD;
+                            } else {
+                                if constexpr (ADJ) adj_add(A.S, wi(T, db + DW_PQ), wf(T, db + DW_INV_QY));
+                                // eq. 10: emitted wavelength from the emission CDF,
+                                // independent of the excitation wavelength (sec. 2.1)
+                                const float ul = u24(r1.y);
+                                const uint32_t* cdf = T + P.off_cdf + dye * P.N;
+                                int lo = 0, hi = P.N - 1;
+                                while (lo < hi) {
+                                    const int mid = (lo + hi) >> 1;
+                                    if (ul < __uint_as_float(cdf[mid])) hi = mid;
+                                    else lo = mid + 1;
+                                }
+                                L.lam = lo;
+                                load_sigma(P, T, L);
+                                L.nem++;
+                                L.comp = 1;
+                                lds_count(tally, FPT_T_EMISSIONS);
+                                dir_cos = 1.f - 2.f * u2;
+                                dir_sin = 2.f * sqrtf(u2 * (1.f - u2));
+                                pend = PEND_MEDIUM;
+                            }
+                        }
+                    }
+                } else {
+                    ev = h.ev;
+                    if (ev == EV_ESC || ev == EV_INF) {
+                        const int side = L.w[2] < 0.f ? 0 : 1;
+                        exit_code = side == 0 ? FPT_EXIT_ESC_R : FPT_EXIT_ESC_T;
+                        if (!pinhole && !(P.fluo_only && L.comp == 0)) {
+                            const int idx = ((L.batch * 2 + L.comp) * 2 + side) * P.N + L.lam;
+                            if constexpr (MODE == MODE_FWD) atomicAdd(&B.counts[idx], 1u);
+                            L.splat_sum += P.wscale;
+                            if constexpr (ADJ) {
+                                const float g = B.gfilm[idx] * P.wscale;
+#pragma unroll
+                                for (int i = 0; i < kMaxNP; ++i)
+                                    if (i < P.np) G[i] += g * A.S[i * 64];
+                            }
+                        }
+                    } else if (ev == EV_LIGHT) {
+                        exit_code = FPT_EXIT_LIGHT;
+                    } else if (ev == EV_WALL) {
+                        const float rho = h.idx >= 0 ? wf(T, P.off_rho + h.idx * P.N + L.lam) : 0.f;
+                        if (!(u1 < rho)) {
+                            exit_code = FPT_EXIT_WALL;
+                        } else {
+                            // Lambertian reflection about the wall's inward normal
+                            lds_count(tally, FPT_T_WALL_REFLECT);
+                            dir_sin = sqrtf(u2);
+                            dir_cos = sqrtf(1.f - u2);
+                            frame = h.idx;
+                            pend = PEND_SURFACE;
+                        }
+                    } else {
+                        // index-matched interface: change medium, keep direction
+                        lds_count(tally, FPT_T_CROSSINGS);
+                        if constexpr (GEOM == FPT_GEOM_BOX) {
+                            L.region = (ev == EV_ENTER) ? h.idx : -1;
+                            L.medium = -1;
+                            // uniform loop + select: no per-lane indexing of kernel arguments
+                            for (int q = 0; q < P.n_spheres; ++q) {
+                                if (q == L.region) {
+                                    L.sc[0] = P.spheres[q].c[0];
+                                    L.sc[1] = P.spheres[q].c[1];
+                                    L.sc[2] = P.spheres[q].c[2];
+                                    L.sr2 = P.spheres[q].r2;
+                                    L.medium = P.spheres[q].medium;
+                                }
+                            }
+                            load_medium(P, T, L);
+                        }
+                    }
+                }
+                if (pend != PEND_NONE && exit_code < 0) {
+                    float sp, cp;
+                    sincospif(2.f * u3, &sp, &cp);
+                    const float a = dir_sin * cp, b = dir_sin * sp;
+                    if (frame < 0) {
+                        L.w[0] = a; L.w[1] = b; L.w[2] = dir_cos;
+                    } else {
+                        // wall frame: normal n = sg e_ax, tangents e_(ax+1), sg e_(ax+2)
+                        const int ax = frame >> 1;
+                        const float sg = (frame & 1) ? -1.f : 1.f;
+                        const float c = sg * dir_cos, bb = sg * b;
+                        L.w[0] = ax == 0 ? c : (ax == 1 ? bb : a);
+                        L.w[1] = ax == 0 ? a : (ax == 1 ? c : bb);
+                        L.w[2] = ax == 0 ? bb : (ax == 1 ? a : c);
+                        nrm[0] = ax == 0 ? sg : 0.f;
+                        nrm[1] = ax == 1 ? sg : 0.f;
+                        nrm[2] = ax == 2 ? sg : 0.f;
+                    }
+                    rrb = rr_bits(r);
+                } else {
+                    pend = PEND_NONE;
+                }
+            }
+        }
+
+        // ---- convergent splat section
+        if constexpr (GEOM == FPT_GEOM_BOX) {
+            if (pend != PEND_NONE && alive && exit_code < 0) {
+                if (!(P.fluo_only && L.comp == 0)) {
+                    const SplatOut so = splat_eval(P, T, L, pend, nrm, rrb);
+                    if (so.status == 0) {
+                        cnt.splat_hit++;
+                        L.splat_sum += so.v;
+                        if constexpr (MODE == MODE_FWD) unsafeAtomicAdd(&B.film[so.idx], so.v);
+                        if constexpr (ADJ) {
+                            const float g = B.gfilm[so.idx];
+                            const float gv = g * so.v;
+#pragma unroll
+                            for (int i = 0; i < kMaxNP; ++i)
+                                if (i < P.np) G[i] += gv * A.S[i * 64];
+                            // d v / d theta = -v sum_s chord_s d sigma_t(m_s) / d theta
+                            const float e0 = P.eye[0] - L.x[0], e1 = P.eye[1] - L.x[1], e2 = P.eye[2] - L.x[2];
+                            const float dist = sqrtf(e0 * e0 + e1 * e1 + e2 * e2);
+                            const float wc[3] = {e0 / dist, e1 / dist, e2 / dist};
+                            for (int s = 0; s < P.n_spheres; ++s) {
+                                const float len = chord_len(P.spheres[s], L.x, wc, dist);
+                                if (!(len > 0.f)) continue;
+                                const int m = P.spheres[s].medium;
+                                const int mb = P.off_med + m * kMedWords;
+                                const float c = -gv * len;
+                                adj_add(A.Gx, wi(T, mb + MW_PSS), c);
+                                const int nd = wi(T, mb + MW_NDYES);
+                                for (int j = 0; j < nd; ++j)
+                                    adj_add(A.Gx, wi(T, mb + MW_PC + j),
+                                            c * wf(T, P.off_kap + (m * P.kap_stride + j) * P.N + L.lam));
+                            }
+                        }
+                    } else {
+                        lds_count(tally, so.status == 2 ? FPT_T_SPLAT_RR_KILL : FPT_T_SPLAT_MISS);
+                    }
+                }
+            }
+        }
+        pend = PEND_NONE;
+
+        // ---- path end
+        if (alive && exit_code >= 0) {
+            alive = false;
+            lds_count(tally, FPT_T_EXIT0 + exit_code);
+            if constexpr (REC) {
+                fpt_path_record rc;
+                rc.n_vertices = L.v + (exit_code == FPT_EXIT_TRUNC ? 0u : 1u);
+                rc.n_scatter = L.nsc;
+                rc.n_emit = L.nem;
+                rc.exit_code = (uint32_t)exit_code;
+                rc.lambda = L.lam;
+                rc.comp = L.comp;
+                rc.region = L.region;
+                rc.pad = 0;
+                rc.pos[0] = L.x[0]; rc.pos[1] = L.x[1]; rc.pos[2] = L.x[2];
+                rc.dir[0] = L.w[0]; rc.dir[1] = L.w[1]; rc.dir[2] = L.w[2];
+                rc.splat_sum = L.splat_sum;
+                rc.pad2 = 0.f;
+                const uint32_t k = L.pid - P.path_begin;
+                B.rec[k] = rc;
+                if constexpr (ADJ) {
+                    if (B.rec_grad) {
+#pragma unroll
+                        for (int i = 0; i < kMaxNP; ++i)
+                            if (i < P.np) B.rec_grad[(size_t)k * P.np + i] = G[i] + A.Gx[i * 64];
+                    }
+#pragma unroll
+                    for (int i = 0; i < kMaxNP; ++i) {
+                        G[i] = 0.f;
+                        A.Gx[i * 64] = 0.f;
+                    }
+                }
+            }
+        }
+    }
+
+    // ---- flush counters: per-lane -> wave -> block LDS -> global
+    {
+        uint32_t a = cnt.vertices, b = cnt.scatters, c = cnt.splat_hit;
+        for (int off = 32; off > 0; off >>= 1) {
+            a += __shfl_xor(a, off);
+            b += __shfl_xor(b, off);
+            c += __shfl_xor(c, off);
+        }
+        if (lane == 0) {
+            atomicAdd(&tally[FPT_T_VERTICES], a);
+            atomicAdd(&tally[FPT_T_SCATTERS], b);
+            atomicAdd(&tally[FPT_T_SPLAT_HIT], c);
+        }
+    }
+    if constexpr (ADJ && !REC) {
+        // block reduction of the gradient: lanes -> wave (shuffle) -> block (LDS)
+        float* red = reinterpret_cast<float*>(smem + 32 + ((P.table_words + 63) & ~63)) +
+                     (blockDim.x >> 6) * (2 * kMaxNP * 64);
+#pragma unroll
+        for (int i = 0; i < kMaxNP; ++i) {
+            float g = G[i] + A.Gx[i * 64];
+            for (int off = 32; off > 0; off >>= 1) g += __shfl_xor(g, off);
+            if (lane == 0) red[wave * kMaxNP + i] = g;
+        }
+        __syncthreads();
+        if (threadIdx.x < kMaxNP) {
+            float g = 0.f;
+            for (int w = 0; w < (int)(blockDim.x >> 6); ++w) g += red[w * kMaxNP + threadIdx.x];
+            B.partials[blockIdx.x * kMaxNP + threadIdx.x] = g;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < FPT_N_TALLIES && B.tallies) {
+        uint32_t v = tally[threadIdx.x];
+        if (threadIdx.x == FPT_T_PATHS) {
+            v = 0u;
+            for (int e = 0; e < 10; ++e) v += tally[FPT_T_EXIT0 + e];
+        }
+        if (v) atomicAdd(&B.tallies[threadIdx.x], (unsigned long long)v);
+    }
+}
+
+// -------------------------------------------------------------------------
+// Small helper kernels (graph-safe replacements for memset and reductions).
+__global__ void k_zero_u32(uint32_t* p, size_t n) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = 0u;
+}
+
+__global__ void k_zero_u64(unsigned long long* p, size_t n) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = 0ull;
+}
+
+// film[i] += counts[i] * scale (integer escape tallies -> fractions of photons)
+__global__ void k_finalize_counts(const uint32_t* counts, float* film, size_t n, float scale) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const uint32_t c = counts[i];
+        if (c) film[i] += (float)c * scale;
+    }
+}
+
+// grad[i] += sum over blocks of partials[b][i] (fp64 sum)
+__global__ void k_reduce_partials(const float* partials, int nblocks, int np, float* grad) {
+    __shared__ double acc[256];
+    for (int i = 0; i < np; ++i) {
+        double s = 0.0;
+        for (int b = threadIdx.x; b < nblocks; b += blockDim.x) s += (double)partials[b * kMaxNP + i];
+        acc[threadIdx.x] = s;
+        __syncthreads();
+        for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+            if ((int)threadIdx.x < o) acc[threadIdx.x] += acc[threadIdx.x + o];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) grad[i] += (float)acc[0];
+        __syncthreads();
+    }
+}
+
+// -------------------------------------------------------------------------
+// Host-side launchers (called by the C-ABI implementation).
+size_t transport_lds_bytes(const KParams& P, int block_threads, int mode) {
+    size_t words = 32 + ((P.table_words + 63) & ~63);
+    if (mode == MODE_ADJ || mode == MODE_REC_ADJ)
+        words += (size_t)(block_threads / 64) * 2 * kMaxNP * 64 + (size_t)(block_threads / 64) * kMaxNP;
+    return words * 4;
+}
+
+template <int GEOM, int MODE>
+static hipError_t launch_t(const KParams& P, const KBuffers& B, int grid, int block, size_t lds,
+                           hipStream_t s) {
+    hipLaunchKernelGGL((k_transport<GEOM, MODE>), dim3(grid), dim3(block), lds, s, P, B);
+    return hipGetLastError();
+}
+
+template <int MODE>
+static hipError_t launch_m(const KParams& P, const KBuffers& B, int grid, int block, size_t lds,
+                           hipStream_t s) {
+    switch (P.geometry) {
+    case FPT_GEOM_SLAB: return launch_t<FPT_GEOM_SLAB, MODE>(P, B, grid, block, lds, s);
+    case FPT_GEOM_HALFSPACE: return launch_t<FPT_GEOM_HALFSPACE, MODE>(P, B, grid, block, lds, s);
+    case FPT_GEOM_SPHERE: return launch_t<FPT_GEOM_SPHERE, MODE>(P, B, grid, block, lds, s);
+    case FPT_GEOM_INFINITE: return launch_t<FPT_GEOM_INFINITE, MODE>(P, B, grid, block, lds, s);
+    default: return launch_t<FPT_GEOM_BOX, MODE>(P, B, grid, block, lds, s);
+    }
+}
+
+template <int GEOM, int MODE>
+static hipError_t occ_t(const KParams& P, int block, int* n) {
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, reinterpret_cast<const void*>(&k_transport<GEOM, MODE>),
+                                                        block, transport_lds_bytes(P, block, MODE));
+}
+
+template <int MODE>
+static hipError_t occ_m(const KParams& P, int block, int* n) {
+    switch (P.geometry) {
+    case FPT_GEOM_SLAB: return occ_t<FPT_GEOM_SLAB, MODE>(P, block, n);
+    case FPT_GEOM_HALFSPACE: return occ_t<FPT_GEOM_HALFSPACE, MODE>(P, block, n);
+    case FPT_GEOM_SPHERE: return occ_t<FPT_GEOM_SPHERE, MODE>(P, block, n);
+    case FPT_GEOM_INFINITE: return occ_t<FPT_GEOM_INFINITE, MODE>(P, block, n);
+    default: return occ_t<FPT_GEOM_BOX, MODE>(P, block, n);
+    }
+}
+
+hipError_t transport_occupancy(const KParams& P, int mode, int block, int* blocks_per_cu) {
+    switch (mode) {
+    case MODE_FWD: return occ_m<MODE_FWD>(P, block, blocks_per_cu);
+    case MODE_ADJ: return occ_m<MODE_ADJ>(P, block, blocks_per_cu);
+    case MODE_REC: return occ_m<MODE_REC>(P, block, blocks_per_cu);
+    default: return occ_m<MODE_REC_ADJ>(P, block, blocks_per_cu);
+    }
+}
+
+hipError_t launch_transport(const KParams& P, const KBuffers& B, int mode, int grid, int block,
+                            hipStream_t s) {
+    const size_t lds = transport_lds_bytes(P, block, mode);
+    switch (mode) {
+    case MODE_FWD: return launch_m<MODE_FWD>(P, B, grid, block, lds, s);
+    case MODE_ADJ: return launch_m<MODE_ADJ>(P, B, grid, block, lds, s);
+    case MODE_REC: return launch_m<MODE_REC>(P, B, grid, block, lds, s);
+    default: return launch_m<MODE_REC_ADJ>(P, B, grid, block, lds, s);
+    }
+}
+
+hipError_t launch_zero_u32(uint32_t* p, size_t n, hipStream_t s) {
+    if (!n) return hipSuccess;
+    const int grid = (int)std::min<size_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_zero_u32, dim3(grid), dim3(256), 0, s, p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_u64(unsigned long long* p, size_t n, hipStream_t s) {
+    if (!n) return hipSuccess;
+    const int grid = (int)std::min<size_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_zero_u64, dim3(grid), dim3(256), 0, s, p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize_counts(const uint32_t* counts, float* film, size_t n, float scale,
+                                  hipStream_t s) {
+    if (!n) return hipSuccess;
+    const int grid = (int)std::min<size_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_finalize_counts, dim3(grid), dim3(256), 0, s, counts, film, n, scale);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_partials(const float* partials, int nblocks, int np, float* grad,
+                                  hipStream_t s) {
+    hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(256), 0, s, partials, nblocks, np, grad);
+    return hipGetLastError();
+}
+
+}  // namespace fpt

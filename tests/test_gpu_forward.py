@@ -1,0 +1,281 @@
+"""GPU forward path vs the oracle and the closed forms (needs an MI355X).
+
+Replay tests run both sides on identical Philox streams and compare per-path
+records; statistical tests compare films from independent seeds bin by bin;
+pins re-run the oracle's closed-form checks on the HIP path at larger sizes.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import pytest
+
+import closed_forms as cf
+import oracle
+import workloads
+from replay import compare_records
+from stats import batch_z, binom_z, check_z, escape_z, multinomial_z
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    torch.cuda.set_device(0)
+    yield
+    torch.cuda.synchronize()
+
+
+def _fpt():
+    import paper_1706_03024_amd as fpt
+    return fpt
+
+
+def _render(scene, run):
+    import torch
+    fpt = _fpt()
+    sc = fpt.Scene(scene)
+    t = fpt.new_tallies()
+    film = sc.render(run, tallies=t)
+    torch.cuda.synchronize()
+    out = film.cpu().numpy().astype(np.float64), fpt.tallies_dict(t)
+    sc.close()
+    return out
+
+
+def _records(scene, run, max_vertices=0):
+    fpt = _fpt()
+    sc = fpt.Scene(scene)
+    rec, _ = sc.records(run, max_vertices=max_vertices)
+    sc.close()
+    return rec
+
+
+# ------------------------------------------------------------------ tables
+@pytest.mark.parametrize("name", ["slab", "cornell", "large"])
+def test_tables_match_oracle(name):
+    scene = {"slab": lambda: workloads.slab_scene(),
+             "cornell": lambda: workloads.cornell_scene(8, 8),
+             "large": lambda: workloads.large_scene(8, 8)}[name]()
+    sc = _fpt().Scene(scene)
+    g = sc.tables()
+    o = oracle.tables(scene)
+    sc.close()
+    np.testing.assert_allclose(g["sigma_t"], o["sigma_t"].astype(np.float32), rtol=2.4e-7)
+    np.testing.assert_allclose(g["emis_cdf"], o["emis_cdf"].astype(np.float32), rtol=2.4e-7,
+                               atol=1e-30)
+    assert np.all(g["emis_cdf"][:, -1] == 1.0)
+    if scene["geometry"]["kind"] == "box":
+        np.testing.assert_allclose(g["rho"], o["rho"].astype(np.float32), rtol=2.4e-7)
+    np.testing.assert_array_equal(g["line_bin"], o["line_bin"])
+
+
+# ------------------------------------------------------------------ plain slab
+def test_slab_replay_all_paths():
+    """Plain slab, all 2^16 paths: every non-marginal path reproduces the
+    oracle's vertex count, scatters, emissions, exit, wavelength and exit
+    state (fp32 vs fp64, relative 1e-5)."""
+    scene, run = workloads.slab_config()
+    g = _records(scene, run)
+    o = oracle.render(scene, run, records=True)["records"]
+    rep = compare_records(g, o, scale=1.0)
+    print(rep)
+
+
+def test_slab_statistical_parity():
+    """Independent seeds: GPU film (2^20 paths) vs oracle film (2^16 paths),
+    per-bin multinomial z-scores."""
+    scene, run = workloads.slab_config()
+    ng, no = 1 << 20, 1 << 16
+    g, tg = _render(scene, dict(run, seed=101, path_count=ng, total_paths=ng))
+    o = oracle.render(scene, dict(run, seed=202, path_count=no, total_paths=no))
+    check_z(escape_z(g[0], ng, o["film"][0], no), "slab film: GPU vs oracle")
+    assert tg["paths"] == ng
+
+
+def test_slab_same_seed_film_and_tallies():
+    """Same seed: films and tallies agree up to the few marginal paths."""
+    scene, run = workloads.slab_config()
+    g, tg = _render(scene, run)
+    o = oracle.render(scene, run)
+    to = oracle.tallies_dict(o["tallies"])
+    n = run["path_count"]
+    for k in oracle.TALLY_NAMES:
+        assert abs(tg[k] - to[k]) <= max(4, 1e-4 * max(to[k], 1)), (k, tg[k], to[k])
+    assert np.abs(g - o["film"]).max() * n <= 8
+
+
+def test_determinism_and_sharding():
+    """Repeated renders are bit-identical; rendering [0,k) and [k,N) into the
+    same film equals rendering [0,N) (integer escape tallies)."""
+    import torch
+    fpt = _fpt()
+    scene, run = workloads.slab_config()
+    sc = fpt.Scene(scene)
+    t1, t2, t3 = fpt.new_tallies(), fpt.new_tallies(), fpt.new_tallies()
+    f1 = sc.render(run, tallies=t1)
+    f2 = sc.render(run, tallies=t2)
+    k = 12345
+    f3 = sc.render(dict(run, path_count=k), tallies=t3)
+    sc.render(dict(run, path_begin=k, path_count=run["path_count"] - k), film=f3, tallies=t3)
+    torch.cuda.synchronize()
+    assert torch.equal(f1, f2) and torch.equal(t1, t2)
+    assert torch.equal(f1, f3) and torch.equal(t1, t3)
+    sc.set_tune(block_threads=128, refill_lanes=48)
+    t4 = fpt.new_tallies()
+    f4 = sc.render(run, tallies=t4)
+    torch.cuda.synchronize()
+    assert torch.equal(f1, f4) and torch.equal(t1, t4)
+    sc.close()
+
+
+def test_conservation_identities():
+    scene, run = workloads.slab_config()
+    _, t = _render(scene, dict(run, path_count=1 << 18, total_paths=1 << 18))
+    n = 1 << 18
+    assert t["paths"] == n
+    assert sum(t["exit_" + e] for e in oracle.EXIT_NAMES) == n
+    assert t["dye_abs"] == t["emissions"] + t["exit_nonrad"] + t["exit_kcap"]
+    s3 = workloads.t3_conservative_slab()
+    f, t3 = _render(s3, workloads.make_run(n, seed=9))
+    assert t3["exit_esc_r"] + t3["exit_esc_t"] + t3["exit_scap"] == n
+    assert abs(f.sum() - (1 - t3["exit_scap"] / n)) < 1e-5
+
+
+# ------------------------------------------------------------------ closed forms on the GPU
+def test_gpu_beer_lambert_and_single_scatter():
+    n = 1 << 20
+    rec = _records(workloads.t1_beer_lambert(), workloads.make_run(n, seed=3))
+    ballistic = np.sum((rec["exit_code"] == 1) & (rec["n_vertices"] == 2))
+    assert abs(binom_z(ballistic, n, math.exp(-1.0))) < 4.5
+    tau = 0.05
+    rec = _records(workloads.t7_single_scatter(tau), workloads.make_run(n, seed=41))
+    one = rec["n_scatter"] == 1
+    R1, T1 = cf.single_scatter_slab(tau)
+    assert abs(binom_z(np.sum(one & (rec["exit_code"] == 0)), n, R1)) < 4.5
+    assert abs(binom_z(np.sum(one & (rec["exit_code"] == 1)), n, T1)) < 4.5
+
+
+@pytest.mark.parametrize("albedo", [0.5, 0.99])
+def test_gpu_infinite_medium_moments(albedo):
+    n = 1 << 18
+    rec = _records(workloads.t2_infinite(albedo, sigma_t=2.0), workloads.make_run(n, seed=11))
+    ns = rec["n_scatter"].astype(float)
+    assert abs(ns.mean() - albedo / (1 - albedo)) < 4.5 * math.sqrt(albedo) / (1 - albedo) / math.sqrt(n)
+    r2 = (rec["pos"].astype(float) ** 2).sum(1)
+    assert abs(r2.mean() - 2 / (2.0 * 2.0 * (1 - albedo))) < 4.5 * r2.std() / math.sqrt(n)
+
+
+def test_gpu_quantum_yield_and_emission_shape():
+    n = 1 << 18
+    qy = 0.7
+    _, t = _render(workloads.t4_infinite_dye(qy=qy),
+                   workloads.make_run(n, seed=21, max_emissions=workloads.UNLIMITED_EMISSIONS))
+    assert abs(binom_z(t["emissions"], t["dye_abs"], qy)) < 4.5
+    rec = _records(workloads.t4_infinite_dye(qy=0.9), workloads.make_run(n, seed=22))
+    em = rec[rec["n_emit"] == 1]
+    hist = np.bincount(em["lambda"], minlength=101) / len(em)
+    check_z(multinomial_z(hist, len(em), cf.emission_pmf(101, [(560, 30, 1)])),
+            "GPU emission shape")
+
+
+def test_gpu_dye_slab_closed_form():
+    n = 1 << 20
+    lx, d, conc, bg, qy = 490.0, 1.0, 20.0, 0.05, 0.8
+    f, _ = _render(workloads.t6_dye_slab(lambda_x=lx, conc_uM=conc, sigma_a_bg=bg, d=d, qy=qy),
+                   workloads.make_run(n, seed=31))
+    lam = cf.grid_lambda(101)
+    sa = cf.dye_sigma_a(lam, [(490, 20, 1)], 7e4, conc, 101)
+    st = bg + sa
+    R, T = cf.dye_slab_fluorescent_film(d, st[38], sa[38], qy, cf.emission_pmf(101, [(520, 25, 1)]), st)
+    z = np.concatenate([multinomial_z(f[0, 1, 0], n, R), multinomial_z(f[0, 1, 1], n, T)])
+    check_z(z, "GPU dye slab fluorescent film")
+
+
+@pytest.mark.parametrize("albedo", [0.9, 0.99])
+def test_gpu_halfspace_albedo(albedo):
+    n = 1 << 19
+    _, t = _render(workloads.t8_halfspace(albedo), workloads.make_run(n, seed=51))
+    assert abs(binom_z(t["exit_esc_r"], n, cf.halfspace_albedo(albedo))) < 4.5
+
+
+# ------------------------------------------------------------------ sphere body
+def test_sphere_body_replay_and_parity():
+    scene = workloads.sphere_scene()
+    n = 1 << 14
+    run = workloads.make_run(n, seed=5)
+    compare_records(_records(scene, run), oracle.render(scene, run, records=True)["records"],
+                    scale=0.5)
+    ng = 1 << 20
+    g, _ = _render(scene, workloads.make_run(ng, seed=6))
+    o = oracle.render(scene, workloads.make_run(n * 4, seed=7))
+    check_z(escape_z(g[0], ng, o["film"][0], n * 4), "sphere body film")
+
+
+# ------------------------------------------------------------------ camera scenes
+def test_cornell_replay():
+    """Box scene with pinhole splats: per-path replay of 2^15 paths, including
+    the sum of each path's splat values."""
+    scene = workloads.cornell_scene(32, 32)
+    run = workloads.make_run(1 << 15, seed=4)
+    rep = compare_records(_records(scene, run),
+                          oracle.render(scene, run, records=True)["records"], scale=1.0)
+    print(rep)
+
+
+def test_cornell_statistical_parity():
+    """Batch-mean z-scores of the spectral film, independent seeds."""
+    B = 32
+    scene = workloads.cornell_scene(32, 32)
+    g, _ = _render(scene, workloads.make_run(1 << 21, seed=10, parity_batches=B))
+    o = oracle.render(scene, workloads.make_run(1 << 18, seed=11, parity_batches=B))["film"]
+    z = batch_z(g, o)
+    assert z.size > 500
+    check_z(z, "Cornell film: GPU vs oracle", dof=B - 1)
+
+
+def test_cornell_full_size_sampled():
+    """Full 128x128, 2^20-path Cornell render in the benchmark's launch
+    configuration: sampled path ranges replay against the oracle, and the film
+    total equals the sum of every path's deposited values."""
+    import torch
+    fpt = _fpt()
+    scene, run = workloads.cornell_config()
+    sc = fpt.Scene(scene)
+    film = sc.render(run)
+    rec, _ = sc.records(run)
+    torch.cuda.synchronize()
+    total = float(film.double().sum())
+    sc.close()
+    assert abs(total - float(rec["splat_sum"].astype(np.float64).sum())) <= 1e-4 * total
+    N = run["path_count"]
+    for begin in (0, N // 3, N - 4096):
+        sub = dict(run, path_begin=begin, path_count=4096)
+        o = oracle.render(scene, sub, records=True)["records"]
+        compare_records(rec[begin:begin + 4096], o, scale=1.0)
+
+
+def test_large_scene_sampled_replay():
+    """Large 5-sphere scene (301 bins, sigma_s up to 1000/mm): 4096 sampled paths,
+    first 256 vertices, replay against the oracle."""
+    scene, run = workloads.large_config()
+    sub = dict(run, path_begin=123456789, path_count=4096)
+    g = _records(scene, sub, max_vertices=256)
+    o = oracle.render(scene, sub, records=True, max_vertices=256)["records"]
+    rep = compare_records(g, o, scale=1.0, max_marginal_frac=0.01)
+    print(rep)
+
+
+def test_splat_roulette_and_fluorescence_only():
+    """Transmittance roulette keeps the film unbiased; fluorescence_only keeps
+    only the emitted component.  Both match the oracle on the same streams."""
+    scene = workloads.cornell_scene(32, 32)
+    run = workloads.make_run(1 << 14, seed=12, splat_rr=0.05, fluorescence_only=True)
+    compare_records(_records(scene, run), oracle.render(scene, run, records=True)["records"])
+    B = 32
+    g, _ = _render(scene, workloads.make_run(1 << 21, seed=13, parity_batches=B, splat_rr=0.05))
+    o = oracle.render(scene, workloads.make_run(1 << 18, seed=14, parity_batches=B))["film"]
+    check_z(batch_z(g, o), "roulette film vs plain oracle film", dof=B - 1)
