@@ -1,0 +1,227 @@
+"""Benchmark: path vertices/s of the fluorescent path tracer on one MI355X.
+
+Headline workload: the Cornell-style scene (three dye spheres in a diffuse
+box, 128x128 pinhole, 64 spp = 2^20 light paths, 101 bins).  One step = one
+full forward render of that job (fpt_render: every per-vertex stage of the
+walk plus the film splat), inputs resident on the device.  Vertices are
+counted exactly by the device tallies.
+
+The JSON line also carries the roofline of the transport kernel (FP32 FLOPs of
+the algorithm per launch / measured kernel time, against the MI355X FP32
+vector peak), the CPU oracle timed on the host, and the other forms
+(large scene, plain slab, forward+adjoint, batched) as extra fields.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+FP32_PEAK_TFLOPS = 157.3   # MI355X vector FP32 (packed FMA)
+VALU_LANE_OPS = 256 * 64 * 2.4e9  # 256 CUs x 64 lanes x 2.4 GHz issue
+
+
+def flops_model(t, n_spheres, geometry):
+    """Algorithmic FP32 operations of one launch from its event tallies
+    (FMA = 2, transcendental = 1, compare = 1); per-event costs are those of
+    the design notes' table."""
+    scatter = 25.0 if geometry in ("slab", "halfspace", "infinite") else 40.0
+    conn = 40.0 + 20.0 * n_spheres
+    return (t["scatters"] * scatter
+            + t["dye_abs"] * (scatter + 20.0)
+            + (t["crossings"] + t["wall_reflect"] + t["exit_wall"] + t["exit_light"]
+               + t["exit_esc_r"] + t["exit_esc_t"] + t["exit_bg"]) * 15.0
+            + t["paths"] * 15.0
+            + (t["splat_hit"] + t["splat_miss"] + t["splat_rr_kill"]) * conn)
+
+
+def time_renders(sc, run, steps, warmup, film):
+    import torch
+    for _ in range(warmup):
+        sc.render(run, film=film)
+    torch.cuda.synchronize()
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    t0 = time.perf_counter()
+    for k in range(steps):
+        starts[k].record()
+        sc.render(run, film=film)
+        ends[k].record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ev_ms = [s.elapsed_time(e) for s, e in zip(starts, ends)]
+    return wall / steps * 1e3, sum(ev_ms) / len(ev_ms)
+
+
+def count_vertices(sc, run):
+    import torch
+    import paper_1706_03024_amd as fpt
+    t = fpt.new_tallies()
+    sc.render(run, tallies=t)
+    torch.cuda.synchronize()
+    return fpt.tallies_dict(t)
+
+
+def forward_form(scene, run, steps, warmup):
+    import paper_1706_03024_amd as fpt
+    sc = fpt.Scene(scene)
+    film = sc.new_film()
+    tal = count_vertices(sc, run)
+    ms, ev_ms = time_renders(sc, run, steps, warmup, film)
+    geo = scene["geometry"]["kind"]
+    nsph = len(scene["geometry"].get("spheres", [])) if geo == "box" else 0
+    fl = flops_model(tal, nsph, geo)
+    sc.close()
+    return {"vertices": tal["vertices"], "ms_per_step": ms, "kernel_ms": ev_ms,
+            "vertices_per_s": tal["vertices"] / (ms / 1e3), "flops": fl, "tallies": tal}
+
+
+def adjoint_form(steps, warmup):
+    """Forward + path-replay adjoint on the 256x256, 256 spp Cornell job:
+    forward vertices / (t_fwd + t_adj)."""
+    import torch
+    import paper_1706_03024_amd as fpt
+    import workloads
+    scene, run, target, trun = workloads.adjoint_config()
+    sc = fpt.Scene(scene)
+    film = sc.new_film()
+    tal = count_vertices(sc, run)
+    g = torch.ones_like(film)
+    grad = torch.zeros(sc.n_params, device="cuda")
+    for _ in range(warmup):
+        sc.render(run, film=film)
+        sc.render_adjoint(run, g, grad)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        sc.render(run, film=film)
+        sc.render_adjoint(run, g, grad)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / steps * 1e3
+    sc.close()
+    return {"vertices": tal["vertices"], "ms_per_step": ms,
+            "vertices_per_s": tal["vertices"] / (ms / 1e3)}
+
+
+def batched_form(steps, warmup):
+    import torch
+    import paper_1706_03024_amd as fpt
+    import workloads
+    if not hasattr(fpt, "Batch"):
+        return None
+    scenes, runs = workloads.batch_config()
+    b = fpt.Batch(scenes, runs)
+    films = b.new_films()
+    tal = b.count_vertices()
+    for _ in range(warmup):
+        b.render(films)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        b.render(films)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / steps * 1e3
+    b.close()
+    return {"vertices": tal, "ms_per_step": ms, "vertices_per_s": tal / (ms / 1e3),
+            "instances": len(scenes)}
+
+
+def cpu_baseline(scene, run, target_s=12.0):
+    """The oracle as it stands (single thread, fp64) on a bounded sample of the
+    workload: the first paths of the same job, sized to roughly target_s."""
+    import oracle
+    n = 1 << 14
+    t0 = time.perf_counter()
+    o = oracle.render(scene, dict(run, path_count=n))
+    dt = time.perf_counter() - t0
+    verts = int(o["tallies"][1])
+    n2 = int(min(run["path_count"], max(n, n * target_s / max(dt, 1e-3))))
+    t0 = time.perf_counter()
+    o = oracle.render(scene, dict(run, path_count=n2))
+    dt = time.perf_counter() - t0
+    verts = int(o["tallies"][1])
+    return {"value": verts / dt, "unit": "path vertices/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {n2} of {run['total_paths']} light paths of the same job "
+                      f"({verts} vertices, {dt:.1f} s, fp64, 1 thread)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--only-headline", action="store_true",
+                    help="time only the headline render (for profiler runs)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
+              "sharding of this path is a design note, not a measured configuration.",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import workloads
+    torch.cuda.set_device(int(os.environ.get("LOCAL_RANK", 0)))
+    scene, run = workloads.cornell_config()
+    head = forward_form(scene, run, args.steps, args.warmup)
+    if args.only_headline:
+        print(json.dumps({"headline": head}, default=float), flush=True)
+        return
+    value = head["vertices_per_s"]
+    achieved = head["flops"] / (head["kernel_ms"] / 1e3) / 1e12
+    line = {
+        "metric": "path vertices/s on 1 MI355X (fwd, batched, fwd+adjoint) at <=3 s.e. vs oracle",
+        "value": value,
+        "unit": "path vertices/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "cornell box, 3 Gaussian dye spheres, 128x128 pinhole, 64 spp "
+                               "(2^20 light paths), 101 bins, fwd",
+                   "paths": run["path_count"], "vertices_per_step": head["vertices"]},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS, "traffic": None,
+                     "kernel": "fpt::k_transport<BOX, FWD>",
+                     "kernel_ms": head["kernel_ms"],
+                     "flops_per_launch": head["flops"]},
+    }
+    extra = {}
+    if not args.no_extra:
+        s3, r3 = workloads.large_config()
+        big = forward_form(s3, r3, max(2, args.steps // 25), 1)
+        extra["fwd_large"] = {k: big[k] for k in ("vertices", "ms_per_step", "vertices_per_s")}
+        extra["fwd_large"]["fp32_frac"] = big["flops"] / (big["kernel_ms"] / 1e3) / 1e12 / FP32_PEAK_TFLOPS
+        s1, r1 = workloads.slab_config()
+        r1 = dict(r1, path_count=1 << 22, total_paths=1 << 22)
+        sl = forward_form(s1, r1, max(5, args.steps // 5), 2)
+        extra["fwd_slab_2^22"] = {k: sl[k] for k in ("vertices", "ms_per_step", "vertices_per_s")}
+        extra["fwd_slab_2^22"]["fp32_frac"] = sl["flops"] / (sl["kernel_ms"] / 1e3) / 1e12 / FP32_PEAK_TFLOPS
+        try:
+            extra["fwd_adjoint"] = adjoint_form(max(3, args.steps // 10), 1)
+        except Exception as e:  # reported, not hidden
+            extra["fwd_adjoint"] = {"error": str(e)}
+        b = batched_form(max(3, args.steps // 10), 1)
+        if b is not None:
+            extra["batched"] = b
+    line["forms"] = extra
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(scene, run)
+    print(json.dumps(line, default=float), flush=True)
+
+
+if __name__ == "__main__":
+    main()

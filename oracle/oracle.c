@@ -773,6 +773,12 @@ static void run_path(ctx_t* c, uint32_t pid, orc_record* rec, uint32_t max_verti
         if (isfinite(dd)) {
             for (int i = 0; i < 3; ++i) p.x[i] += dd * p.w[i];
             score_path_length(c, &p, dd);
+            /* a point on a planar boundary lies exactly on its plane */
+            if (sc->geom == ORC_GEOM_SLAB) p.x[2] = p.w[2] < 0.0 ? sc->z0 : sc->z1;
+            else if (sc->geom == ORC_GEOM_HALFSPACE) p.x[2] = sc->z0;
+            else if (sc->geom == ORC_GEOM_BOX && (h.kind == SURF_WALL || h.kind == SURF_ESCAPE) &&
+                     h.index >= 0)
+                p.x[h.index / 2] = (h.index % 2) ? sc->box_hi[h.index / 2] : sc->box_lo[h.index / 2];
         }
         if (h.kind == SURF_ESCAPE) {
             int side = p.w[2] < 0.0 ? 0 : 1;

@@ -188,6 +188,24 @@ DEV Hit next_surface(const KParams& P, const Lane& L, bool skip_light) {
     return h;
 }
 
+// A point that reached a planar boundary lies on it: set that coordinate exactly.
+template <int GEOM>
+DEV void snap_to_plane(const KParams& P, Lane& L, const Hit& h) {
+    if constexpr (GEOM == FPT_GEOM_SLAB) {
+        if (h.d < kInf) L.x[2] = L.w[2] < 0.f ? P.z0 : P.z1;
+    } else if constexpr (GEOM == FPT_GEOM_HALFSPACE) {
+        if (h.d < kInf) L.x[2] = P.z0;
+    } else if constexpr (GEOM == FPT_GEOM_BOX) {
+        if ((h.ev == EV_WALL || h.ev == EV_ESC) && h.idx >= 0) {
+            const int ax = h.idx >> 1;
+            const float v = (h.idx & 1) ? P.hi[ax] : P.lo[ax];
+            if (ax == 0) L.x[0] = v;
+            else if (ax == 1) L.x[1] = v;
+            else L.x[2] = v;
+        }
+    }
+}
+
 // Length of the segment x + t wc, t in [0, dist], inside a sphere.
 DEV float chord_len(const KSphere& sp, const float* x, const float* wc, float dist) {
     const float o0 = x[0] - sp.c[0], o1 = x[1] - sp.c[1], o2 = x[2] - sp.c[2];
@@ -461,6 +479,7 @@ __global__ void __launch_bounds__(256) k_transport(const KParams P, const KBuffe
                     L.x[2] += len * L.w[2];
                     score_length<MODE>(P, T, L, A, len);
                 }
+                if (!collide) snap_to_plane<GEOM>(P, L, h);
                 float dir_sin = 0.f, dir_cos = 0.f;  // polar sine/cosine of a new direction
                 int frame = -1;                      // -1 world axes, else wall face
                 if (collide) {

