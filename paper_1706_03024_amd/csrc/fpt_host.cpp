@@ -497,8 +497,12 @@ void fill_run(const fpt_scene* sc, const fpt_run* run, uint32_t B, KParams* P) {
     P->fluo_only = (run->flags & FPT_FLAG_FLUORESCENCE_ONLY) ? 1 : 0;
     P->exc_scatter = (run->flags & FPT_FLAG_NO_EXCITATION_SCATTER) ? 0 : 1;
     P->splat_rr = (float)run->splat_rr;
+    P->inv_splat_rr = run->splat_rr > 0.0 ? (float)(1.0 / run->splat_rr) : 0.f;
     P->max_vertices = 0;
     P->refill_lanes = sc->tune.refill_lanes > 0 ? std::min(64, sc->tune.refill_lanes) : 16;
+    // escape films up to 8192 counters use a per-block LDS histogram
+    const int64_t hw = sc->desc.sensor == FPT_SENSOR_ESCAPE ? film_elems(sc->desc, B) : 0;
+    P->hist_words = hw <= 8192 ? (int)hw : 0;
 }
 
 int32_t ensure_scratch(fpt_scene* sc, size_t counts, size_t partials) {

@@ -62,8 +62,9 @@ struct KParams {
     float wscale;  // batches / total_paths
     uint32_t max_scatter, max_emissions;
     int fluo_only, exc_scatter;
-    float splat_rr;
+    float splat_rr, inv_splat_rr;
     uint32_t max_vertices;
+    int hist_words;  // > 0: escape counts go through a per-block LDS histogram of this size
     int np;
     int refill_lanes;
 };

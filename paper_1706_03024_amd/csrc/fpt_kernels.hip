@@ -21,6 +21,8 @@ namespace fpt {
 
 constexpr float kInf = __builtin_inff();
 constexpr uint32_t kMaxPathVertices = 1u << 28;
+constexpr int kLdsSpheres = 32;                                // word offset of the sphere table
+constexpr int kLdsTable = kLdsSpheres + 8 * FPT_MAX_SPHERES;   // word offset of the table image
 constexpr float kInv4Pi = 0.0795774715459476679f;
 constexpr float kInvPi = 0.318309886183790672f;
 
@@ -56,6 +58,9 @@ DEV float u24(uint32_t x) { return (float)(x >> 8) * 5.9604644775390625e-08f; }
 DEV uint32_t rr_bits(const uint4 r) {
     return ((r.x & 0xFFu) << 16) | ((r.y & 0xFFu) << 8) | (r.z & 0xFFu);
 }
+
+// a / b through the hardware reciprocal (about 1 ulp); b != 0 at every call site.
+DEV float fdiv(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
 
 DEV float wf(const uint32_t* S, int i) { return __uint_as_float(S[i]); }
 DEV int wi(const uint32_t* S, int i) { return (int)S[i]; }
@@ -119,17 +124,16 @@ DEV float sphere_exit(const float* x, const float* w, const float* c, float r2) 
 }
 
 template <int GEOM>
-DEV Hit next_surface(const KParams& P, const Lane& L, bool skip_light) {
+DEV Hit next_surface(const KParams& P, const KSphere* SP, const Lane& L, bool skip_light) {
     Hit h;
     h.d = kInf;
     h.ev = EV_ESC;
     h.idx = -1;
     if constexpr (GEOM == FPT_GEOM_SLAB) {
-        if (L.w[2] > 0.f) h.d = (P.z1 - L.x[2]) / L.w[2];
-        else if (L.w[2] < 0.f) h.d = (P.z0 - L.x[2]) / L.w[2];
+        if (L.w[2] != 0.f) h.d = fdiv((L.w[2] > 0.f ? P.z1 : P.z0) - L.x[2], L.w[2]);
         h.d = fmaxf(h.d, 0.f);
     } else if constexpr (GEOM == FPT_GEOM_HALFSPACE) {
-        if (L.w[2] < 0.f) h.d = fmaxf((P.z0 - L.x[2]) / L.w[2], 0.f);
+        if (L.w[2] < 0.f) h.d = fmaxf(fdiv(P.z0 - L.x[2], L.w[2]), 0.f);
     } else if constexpr (GEOM == FPT_GEOM_SPHERE) {
         h.d = sphere_exit(L.x, L.w, P.bc, P.br2);
     } else if constexpr (GEOM == FPT_GEOM_INFINITE) {
@@ -146,8 +150,11 @@ DEV Hit next_surface(const KParams& P, const Lane& L, bool skip_light) {
         for (int a = 0; a < 3; ++a) {
             float t = kInf;
             int f = -1;
-            if (L.w[a] > 0.f) { t = (P.hi[a] - L.x[a]) / L.w[a]; f = 2 * a + 1; }
-            else if (L.w[a] < 0.f) { t = (P.lo[a] - L.x[a]) / L.w[a]; f = 2 * a; }
+            if (L.w[a] != 0.f) {
+                const bool up = L.w[a] > 0.f;
+                t = fdiv((up ? P.hi[a] : P.lo[a]) - L.x[a], L.w[a]);
+                f = 2 * a + (up ? 1 : 0);
+            }
             t = fmaxf(t, 0.f);
             if (t < h.d) { h.d = t; h.idx = f; }
         }
@@ -157,7 +164,7 @@ DEV Hit next_surface(const KParams& P, const Lane& L, bool skip_light) {
             const float dn = dot3(P.ln, L.w);
             if (dn != 0.f) {
                 const float pc0 = P.lpos[0] - L.x[0], pc1 = P.lpos[1] - L.x[1], pc2 = P.lpos[2] - L.x[2];
-                const float t = (P.ln[0] * pc0 + P.ln[1] * pc1 + P.ln[2] * pc2) / dn;
+                const float t = fdiv(P.ln[0] * pc0 + P.ln[1] * pc1 + P.ln[2] * pc2, dn);
                 if (t > 0.f && t < h.d) {
                     const float q0 = L.x[0] + t * L.w[0] - P.lpos[0];
                     const float q1 = L.x[1] + t * L.w[1] - P.lpos[1];
@@ -174,7 +181,7 @@ DEV Hit next_surface(const KParams& P, const Lane& L, bool skip_light) {
         }
         // sphere entries
         for (int s = 0; s < P.n_spheres; ++s) {
-            const KSphere& sp = P.spheres[s];
+            const KSphere& sp = SP[s];
             const float o0 = L.x[0] - sp.c[0], o1 = L.x[1] - sp.c[1], o2 = L.x[2] - sp.c[2];
             const float b = o0 * L.w[0] + o1 * L.w[1] + o2 * L.w[2];
             if (!(b < 0.f)) continue;
@@ -228,8 +235,8 @@ struct SplatOut {
     int status;  // 0 hit, 1 miss, 2 roulette kill
 };
 
-DEV SplatOut splat_eval(const KParams& P, const uint32_t* S, const Lane& L, int pend,
-                        const float* nrm, uint32_t rrb) {
+DEV SplatOut splat_eval(const KParams& P, const uint32_t* S, const KSphere* SP, const Lane& L,
+                        int pend, const float* nrm, uint32_t rrb) {
     SplatOut o;
     o.v = 0.f;
     o.idx = -1;
@@ -247,32 +254,34 @@ DEV SplatOut splat_eval(const KParams& P, const uint32_t* S, const Lane& L, int 
     }
     const float zc = -(d0 * P.cf[0] + d1 * P.cf[1] + d2 * P.cf[2]);
     if (!(zc > 0.f)) return o;
-    const float izc = 1.f / zc;
+    const float izc = __builtin_amdgcn_rcpf(zc);
     const float xi = -(d0 * P.cr[0] + d1 * P.cr[1] + d2 * P.cr[2]) * izc * P.inv_tanx;
     const float yi = -(d0 * P.cu[0] + d1 * P.cu[1] + d2 * P.cu[2]) * izc * P.inv_tany;
     const float fx = (xi + 1.f) * 0.5f * (float)P.W;
     const float fy = (1.f - yi) * 0.5f * (float)P.H;
     if (!(fx >= 0.f && fx < (float)P.W && fy >= 0.f && fy < (float)P.H)) return o;
     const int px = min((int)fx, P.W - 1), py = min((int)fy, P.H - 1);
-    // visibility: leave the box through the open face
+    // visibility: the segment from x (inside the box) to the eye (outside,
+    // beyond the open face's plane) must cross that plane inside the face
     {
-        float tmin = kInf;
-        int fmin_ = -1;
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            const float da = a == 0 ? d0 : (a == 1 ? d1 : d2);
-            float t = kInf;
-            int fc = -1;
-            if (da > 0.f) { t = (P.hi[a] - L.x[a]) / da; fc = 2 * a + 1; }
-            else if (da < 0.f) { t = (P.lo[a] - L.x[a]) / da; fc = 2 * a; }
-            if (t < tmin) { tmin = t; fmin_ = fc; }
-        }
-        if (fmin_ != P.open_face || !(tmin < 1.f)) return o;
+        const int ax = P.open_face >> 1;
+        const float plane = (P.open_face & 1) ? P.hi[ax] : P.lo[ax];
+        const float xa = ax == 0 ? L.x[0] : (ax == 1 ? L.x[1] : L.x[2]);
+        const float da = ax == 0 ? d0 : (ax == 1 ? d1 : d2);
+        if (da == 0.f) return o;
+        const float t = fdiv(plane - xa, da);
+        if (!(t > 0.f && t < 1.f)) return o;
+        const int a1 = ax == 2 ? 0 : ax + 1, a2 = ax == 0 ? 2 : ax - 1;
+        const float q1 = (a1 == 0 ? L.x[0] : (a1 == 1 ? L.x[1] : L.x[2])) +
+                         t * (a1 == 0 ? d0 : (a1 == 1 ? d1 : d2));
+        const float q2 = (a2 == 0 ? L.x[0] : (a2 == 1 ? L.x[1] : L.x[2])) +
+                         t * (a2 == 0 ? d0 : (a2 == 1 ? d1 : d2));
+        if (!(q1 >= P.lo[a1] && q1 <= P.hi[a1] && q2 >= P.lo[a2] && q2 <= P.hi[a2])) return o;
         if (pend != PEND_SOURCE) {
             const float dn = P.ln[0] * d0 + P.ln[1] * d1 + P.ln[2] * d2;
             if (dn != 0.f) {
                 const float pc0 = P.lpos[0] - L.x[0], pc1 = P.lpos[1] - L.x[1], pc2 = P.lpos[2] - L.x[2];
-                const float t = (P.ln[0] * pc0 + P.ln[1] * pc1 + P.ln[2] * pc2) / dn;
+                const float t = fdiv(P.ln[0] * pc0 + P.ln[1] * pc1 + P.ln[2] * pc2, dn);
                 if (t > 0.f && t < 1.f) {
                     const float q0 = L.x[0] + t * d0 - P.lpos[0];
                     const float q1 = L.x[1] + t * d1 - P.lpos[1];
@@ -287,20 +296,20 @@ DEV SplatOut splat_eval(const KParams& P, const uint32_t* S, const Lane& L, int 
     // transmittance along the connection, through every sphere (eq. 6)
     float tau = 0.f;
     for (int s = 0; s < P.n_spheres; ++s) {
-        const float len = chord_len(P.spheres[s], L.x, wc, dist);
-        if (len > 0.f) tau += wf(S, P.off_st + 2 * (P.spheres[s].medium * P.N + L.lam)) * len;
+        const float len = chord_len(SP[s], L.x, wc, dist);
+        if (len > 0.f) tau += wf(S, P.off_st + 2 * (SP[s].medium * P.N + L.lam)) * len;
     }
     const float tr = __expf(-tau);
     const float cosc = zc * rdist;
-    float v = P.wscale * f * tr * P.splat_norm / (cosc * cosc * cosc * dist2);
+    float v = P.wscale * f * tr * P.splat_norm * __builtin_amdgcn_rcpf(cosc * cosc * cosc * dist2);
     if (P.splat_rr > 0.f && tr < P.splat_rr) {
-        const float q = tr / P.splat_rr;
+        const float q = tr * P.inv_splat_rr;
         const float u = (float)rrb * 5.9604644775390625e-08f;
         if (!(u < q)) {
             o.status = 2;
             return o;
         }
-        v = v / q;
+        v = fdiv(v, q);
     }
     o.v = v;
     o.status = 0;
@@ -345,16 +354,25 @@ __global__ void __launch_bounds__(256) k_transport(const KParams P, const KBuffe
     constexpr bool ADJ = (MODE == MODE_ADJ || MODE == MODE_REC_ADJ);
     constexpr bool REC = (MODE == MODE_REC || MODE == MODE_REC_ADJ);
     extern __shared__ uint32_t smem[];
-    uint32_t* tally = smem;            // FPT_N_TALLIES u32, block-wide
-    const uint32_t* T = smem + 32;     // table image
+    uint32_t* tally = smem;                                          // FPT_N_TALLIES u32
+    KSphere* SPw = reinterpret_cast<KSphere*>(smem + kLdsSpheres);  // sphere table
+    const KSphere* SP = SPw;
+    const uint32_t* T = smem + kLdsTable;                            // table image
+    const int tw = (P.table_words + 63) & ~63;
+    // escape histogram in LDS (FWD, escape sensor, small films), flushed once per block
+    uint32_t* hist = smem + kLdsTable + tw;
+    const bool lds_hist = MODE == MODE_FWD && P.hist_words > 0;
     for (int i = threadIdx.x; i < FPT_N_TALLIES; i += blockDim.x) tally[i] = 0u;
-    for (int i = threadIdx.x; i < P.table_words; i += blockDim.x) smem[32 + i] = B.tables[i];
+    for (int i = threadIdx.x; i < P.table_words; i += blockDim.x) smem[kLdsTable + i] = B.tables[i];
+    for (int i = threadIdx.x; i < P.n_spheres; i += blockDim.x) SPw[i] = P.spheres[i];
+    if (lds_hist)
+        for (int i = threadIdx.x; i < P.hist_words; i += blockDim.x) hist[i] = 0u;
     const int wave = threadIdx.x >> 6;
     const uint32_t lane = lane_id();
     AdjView A;
     float G[ADJ ? kMaxNP : 1];
     if constexpr (ADJ) {
-        float* base = reinterpret_cast<float*>(smem + 32 + ((P.table_words + 63) & ~63)) +
+        float* base = reinterpret_cast<float*>(smem + kLdsTable + tw + P.hist_words) +
                       wave * (2 * kMaxNP * 64) + lane;
         A.S = base;
         A.Gx = base + kMaxNP * 64;
@@ -470,7 +488,7 @@ __global__ void __launch_bounds__(256) k_transport(const KParams P, const KBuffe
                 const float u0 = u24(r.x), u1 = u24(r.y), u2 = u24(r.z), u3 = u24(r.w);
                 // eq. 6: free flight with density sigma_t exp(-sigma_t t)
                 const float tf = (L.inv == kInf) ? kInf : -__logf(1.f - u0) * L.inv;
-                const Hit h = next_surface<GEOM>(P, L, GEOM == FPT_GEOM_BOX && L.v == 1u);
+                const Hit h = next_surface<GEOM>(P, SP, L, GEOM == FPT_GEOM_BOX && L.v == 1u);
                 const bool collide = tf < h.d;
                 const float len = collide ? tf : h.d;
                 if (len < kInf) {
@@ -552,7 +570,10 @@ __global__ void __launch_bounds__(256) k_transport(const KParams P, const KBuffe
                         exit_code = side == 0 ? FPT_EXIT_ESC_R : FPT_EXIT_ESC_T;
                         if (!pinhole && !(P.fluo_only && L.comp == 0)) {
                             const int idx = ((L.batch * 2 + L.comp) * 2 + side) * P.N + L.lam;
-                            if constexpr (MODE == MODE_FWD) atomicAdd(&B.counts[idx], 1u);
+                            if constexpr (MODE == MODE_FWD) {
+                                if (lds_hist) atomicAdd(&hist[idx], 1u);
+                                else atomicAdd(&B.counts[idx], 1u);
+                            }
                             L.splat_sum += P.wscale;
                             if constexpr (ADJ) {
                                 const float g = B.gfilm[idx] * P.wscale;
@@ -581,15 +602,13 @@ __global__ void __launch_bounds__(256) k_transport(const KParams P, const KBuffe
                         if constexpr (GEOM == FPT_GEOM_BOX) {
                             L.region = (ev == EV_ENTER) ? h.idx : -1;
                             L.medium = -1;
-                            // uniform loop + select: no per-lane indexing of kernel arguments
-                            for (int q = 0; q < P.n_spheres; ++q) {
-                                if (q == L.region) {
-                                    L.sc[0] = P.spheres[q].c[0];
-                                    L.sc[1] = P.spheres[q].c[1];
-                                    L.sc[2] = P.spheres[q].c[2];
-                                    L.sr2 = P.spheres[q].r2;
-                                    L.medium = P.spheres[q].medium;
-                                }
+                            if (L.region >= 0) {
+                                const KSphere& sp = SP[L.region];
+                                L.sc[0] = sp.c[0];
+                                L.sc[1] = sp.c[1];
+                                L.sc[2] = sp.c[2];
+                                L.sr2 = sp.r2;
+                                L.medium = sp.medium;
                             }
                             load_medium(P, T, L);
                         }
@@ -624,7 +643,7 @@ __global__ void __launch_bounds__(256) k_transport(const KParams P, const KBuffe
         if constexpr (GEOM == FPT_GEOM_BOX) {
             if (pend != PEND_NONE && alive && exit_code < 0) {
                 if (!(P.fluo_only && L.comp == 0)) {
-                    const SplatOut so = splat_eval(P, T, L, pend, nrm, rrb);
+                    const SplatOut so = splat_eval(P, T, SP, L, pend, nrm, rrb);
                     if (so.status == 0) {
                         cnt.splat_hit++;
                         L.splat_sum += so.v;
@@ -638,11 +657,12 @@ __global__ void __launch_bounds__(256) k_transport(const KParams P, const KBuffe
                             // d v / d theta = -v sum_s chord_s d sigma_t(m_s) / d theta
                             const float e0 = P.eye[0] - L.x[0], e1 = P.eye[1] - L.x[1], e2 = P.eye[2] - L.x[2];
                             const float dist = sqrtf(e0 * e0 + e1 * e1 + e2 * e2);
-                            const float wc[3] = {e0 / dist, e1 / dist, e2 / dist};
+                            const float id = __builtin_amdgcn_rcpf(dist);
+                            const float wc[3] = {e0 * id, e1 * id, e2 * id};
                             for (int s = 0; s < P.n_spheres; ++s) {
-                                const float len = chord_len(P.spheres[s], L.x, wc, dist);
+                                const float len = chord_len(SP[s], L.x, wc, dist);
                                 if (!(len > 0.f)) continue;
-                                const int m = P.spheres[s].medium;
+                                const int m = SP[s].medium;
                                 const int mb = P.off_med + m * kMedWords;
                                 const float c = -gv * len;
                                 adj_add(A.Gx, wi(T, mb + MW_PSS), c);
@@ -712,7 +732,7 @@ __global__ void __launch_bounds__(256) k_transport(const KParams P, const KBuffe
     }
     if constexpr (ADJ && !REC) {
         // block reduction of the gradient: lanes -> wave (shuffle) -> block (LDS)
-        float* red = reinterpret_cast<float*>(smem + 32 + ((P.table_words + 63) & ~63)) +
+        float* red = reinterpret_cast<float*>(smem + kLdsTable + tw + P.hist_words) +
                      (blockDim.x >> 6) * (2 * kMaxNP * 64);
 #pragma unroll
         for (int i = 0; i < kMaxNP; ++i) {
@@ -728,6 +748,9 @@ __global__ void __launch_bounds__(256) k_transport(const KParams P, const KBuffe
         }
     }
     __syncthreads();
+    if (lds_hist)
+        for (int i = threadIdx.x; i < P.hist_words; i += blockDim.x)
+            if (hist[i]) atomicAdd(&B.counts[i], hist[i]);
     if (threadIdx.x < FPT_N_TALLIES && B.tallies) {
         uint32_t v = tally[threadIdx.x];
         if (threadIdx.x == FPT_T_PATHS) {
@@ -778,7 +801,7 @@ __global__ void k_reduce_partials(const float* partials, int nblocks, int np, fl
 // -------------------------------------------------------------------------
 // Host-side launchers (called by the C-ABI implementation).
 size_t transport_lds_bytes(const KParams& P, int block_threads, int mode) {
-    size_t words = 32 + ((P.table_words + 63) & ~63);
+    size_t words = kLdsTable + ((P.table_words + 63) & ~63) + P.hist_words;
     if (mode == MODE_ADJ || mode == MODE_REC_ADJ)
         words += (size_t)(block_threads / 64) * 2 * kMaxNP * 64 + (size_t)(block_threads / 64) * kMaxNP;
     return words * 4;
