@@ -503,6 +503,7 @@ void fill_run(const fpt_scene* sc, const fpt_run* run, uint32_t B, KParams* P) {
     // escape films up to 8192 counters use a per-block LDS histogram
     const int64_t hw = sc->desc.sensor == FPT_SENSOR_ESCAPE ? film_elems(sc->desc, B) : 0;
     P->hist_words = hw <= 8192 ? (int)hw : 0;
+    P->block_min_v = sc->tune.block_min_vertices > 0 ? (uint32_t)sc->tune.block_min_vertices : 48u;
 }
 
 int32_t ensure_scratch(fpt_scene* sc, size_t counts, size_t partials) {

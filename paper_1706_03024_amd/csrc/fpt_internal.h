@@ -67,6 +67,7 @@ struct KParams {
     int hist_words;  // > 0: escape counts go through a per-block LDS histogram of this size
     int np;
     int refill_lanes;
+    uint32_t block_min_v;  // paths with at least this many vertices walk in wave blocks
 };
 
 struct KBuffers {

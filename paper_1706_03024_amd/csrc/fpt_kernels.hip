@@ -348,6 +348,185 @@ DEV void score_length(const KParams& P, const uint32_t* T, const Lane& L, AdjVie
 }
 
 // -------------------------------------------------------------------------
+// Wave-cooperative walk of one long path.  Inside a homogeneous medium at a
+// fixed wavelength the flight lengths, event choices and new directions of the
+// next vertices depend only on their random counters, not on the position; so
+// lane k draws vertex v+1+k, a wave prefix sum of the segment vectors gives the
+// positions, and a ballot finds the first vertex that leaves the medium or is
+// not a scatter.  The scatter vertices before it are committed (and splat) in
+// parallel; that vertex itself is left to the ordinary step.  The arithmetic
+// depends only on the path's state, so results do not depend on scheduling.
+DEV float rl(float x, int j) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), j)); }
+DEV int rli(int x, int j) { return __builtin_amdgcn_readlane(x, j); }
+DEV uint32_t rlu(uint32_t x, int j) { return (uint32_t)__builtin_amdgcn_readlane((int)x, j); }
+
+template <int GEOM>
+DEV float medium_exit(const KParams& P, const float* x, const float* w, const float* sc, float sr2) {
+    if constexpr (GEOM == FPT_GEOM_SLAB) {
+        return w[2] != 0.f ? fmaxf(fdiv((w[2] > 0.f ? P.z1 : P.z0) - x[2], w[2]), 0.f) : kInf;
+    } else if constexpr (GEOM == FPT_GEOM_HALFSPACE) {
+        return w[2] < 0.f ? fmaxf(fdiv(P.z0 - x[2], w[2]), 0.f) : kInf;
+    } else if constexpr (GEOM == FPT_GEOM_SPHERE) {
+        return sphere_exit(x, w, P.bc, P.br2);
+    } else if constexpr (GEOM == FPT_GEOM_INFINITE) {
+        return kInf;
+    } else {
+        return sphere_exit(x, w, sc, sr2);
+    }
+}
+
+template <int GEOM, int MODE>
+DEV void block_walk(const KParams& P, const KBuffers& B, const uint32_t* T, const KSphere* SP,
+                    uint32_t* tally, Lane& L, int j, uint32_t lane, bool pinhole, Counters& cnt,
+                    float* Sw, float* Gxl, float* G) {
+    constexpr bool ADJ = (MODE == MODE_ADJ || MODE == MODE_REC_ADJ);
+    constexpr bool REC = (MODE == MODE_REC || MODE == MODE_REC_ADJ);
+    // the owner's state, uniform across the wave
+    Lane Q;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        Q.x[c] = rl(L.x[c], j);
+        Q.w[c] = rl(L.w[c], j);
+        Q.sc[c] = rl(L.sc[c], j);
+    }
+    Q.sr2 = rl(L.sr2, j);
+    Q.st = rl(L.st, j);
+    Q.inv = rl(L.inv, j);
+    Q.ss = rl(L.ss, j);
+    Q.thr_bg = rl(L.thr_bg, j);
+    Q.ndy = rli(L.ndy, j);
+    Q.lam = rli(L.lam, j);
+    Q.region = rli(L.region, j);
+    Q.medium = rli(L.medium, j);
+    Q.comp = rli(L.comp, j);
+    Q.pid = rlu(L.pid, j);
+    Q.v = rlu(L.v, j);
+    Q.nsc = rlu(L.nsc, j);
+    Q.nem = rlu(L.nem, j);
+    Q.batch = rlu(L.batch, j);
+    Q.splat_sum = 0.f;
+
+    const uint32_t vk = Q.v + 1u + lane;
+    const uint4 r = philox(Q.pid, vk, 0u, 0u, P.key0, P.key1);
+    const float u0 = u24(r.x), u1 = u24(r.y), u2 = u24(r.z), u3 = u24(r.w);
+    const float tk = -__logf(1.f - u0) * Q.inv;
+    const bool scat = u1 * Q.st < Q.ss;
+    float sp, cp;
+    sincospif(2.f * u3, &sp, &cp);
+    const float ct = 1.f - 2.f * u2, stt = 2.f * sqrtf(u2 * (1.f - u2));
+    const float wn[3] = {stt * cp, stt * sp, ct};
+    // incoming direction of segment k: the new direction of vertex k-1
+    float win[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const float up = __shfl_up(wn[c], 1);
+        win[c] = lane == 0 ? Q.w[c] : up;
+    }
+    const float seg[3] = {tk * win[0], tk * win[1], tk * win[2]};
+    float s0 = seg[0], s1 = seg[1], s2 = seg[2], tt = tk;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const float y0 = __shfl_up(s0, d), y1 = __shfl_up(s1, d), y2 = __shfl_up(s2, d);
+        const float yt = __shfl_up(tt, d);
+        if (lane >= (uint32_t)d) { s0 += y0; s1 += y1; s2 += y2; tt += yt; }
+    }
+    // segment k starts at p_k and, if it stays in the medium, ends at q_k
+    const float pk[3] = {Q.x[0] + (s0 - seg[0]), Q.x[1] + (s1 - seg[1]), Q.x[2] + (s2 - seg[2])};
+    const float dif = medium_exit<GEOM>(P, pk, win, Q.sc, Q.sr2);
+    bool stop = !(tk < dif) || !scat || (Q.nsc + lane + 1u > P.max_scatter) ||
+                (vk >= kMaxPathVertices);
+    if (REC && P.max_vertices && vk >= P.max_vertices) stop = true;
+    const uint64_t sm = __ballot(stop);
+    const int kstar = sm ? (__ffsll((unsigned long long)sm) - 1) : 64;
+    if (kstar == 0) return;
+    const bool mine = (int)lane < kstar;
+    Lane Lk = Q;
+    Lk.x[0] = Q.x[0] + s0;
+    Lk.x[1] = Q.x[1] + s1;
+    Lk.x[2] = Q.x[2] + s2;
+    float dep = 0.f;
+    if (mine) {
+        cnt.vertices++;
+        cnt.scatters++;
+    }
+    // score of the path prefix up to vertex k (likelihood ratio of k+1 scatters)
+    int pss = 0;
+    float inv_ss = 0.f;
+    if constexpr (ADJ) {
+        const int mb = P.off_med + Q.medium * kMedWords;
+        pss = wi(T, mb + MW_PSS);
+        inv_ss = wf(T, mb + MW_INV_SS);
+    }
+    if constexpr (GEOM == FPT_GEOM_BOX) {
+        if (pinhole && mine && !(P.fluo_only && Q.comp == 0)) {
+            const float zero3[3] = {0.f, 0.f, 0.f};
+            const SplatOut so = splat_eval(P, T, SP, Lk, PEND_MEDIUM, zero3, rr_bits(r));
+            if (so.status == 0) {
+                cnt.splat_hit++;
+                dep = so.v;
+                if constexpr (MODE == MODE_FWD) unsafeAtomicAdd(&B.film[so.idx], so.v);
+                if constexpr (ADJ) {
+                    const float gv = B.gfilm[so.idx] * so.v;
+                    const int mb = P.off_med + Q.medium * kMedWords;
+#pragma unroll
+                    for (int i = 0; i < kMaxNP; ++i) {
+                        if (i >= P.np) continue;
+                        float Si = Sw[i * 64 + j];
+                        if (i == pss) Si += (float)(lane + 1) * inv_ss - tt;
+                        for (int q = 0; q < Q.ndy; ++q)
+                            if (i == wi(T, mb + MW_PC + q))
+                                Si -= wf(T, P.off_kap + (Q.medium * P.kap_stride + q) * P.N + Q.lam) * tt;
+                        G[i] += gv * Si;
+                    }
+                    const float e0 = P.eye[0] - Lk.x[0], e1 = P.eye[1] - Lk.x[1], e2 = P.eye[2] - Lk.x[2];
+                    const float dist = sqrtf(e0 * e0 + e1 * e1 + e2 * e2);
+                    const float id = __builtin_amdgcn_rcpf(dist);
+                    const float wc[3] = {e0 * id, e1 * id, e2 * id};
+                    for (int s = 0; s < P.n_spheres; ++s) {
+                        const float len = chord_len(SP[s], Lk.x, wc, dist);
+                        if (!(len > 0.f)) continue;
+                        const int m = SP[s].medium;
+                        const int mbs = P.off_med + m * kMedWords;
+                        const float c = -gv * len;
+                        Gxl[wi(T, mbs + MW_PSS) * 64] += c;
+                        const int nd = wi(T, mbs + MW_NDYES);
+                        for (int q = 0; q < nd; ++q)
+                            Gxl[wi(T, mbs + MW_PC + q) * 64] +=
+                                c * wf(T, P.off_kap + (m * P.kap_stride + q) * P.N + Q.lam);
+                    }
+                }
+            } else {
+                lds_count(tally, so.status == 2 ? FPT_T_SPLAT_RR_KILL : FPT_T_SPLAT_MISS);
+            }
+        }
+    }
+    if constexpr (REC) {
+        float dsum = dep;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) dsum += __shfl_xor(dsum, off);
+        if ((int)lane == j) L.splat_sum += dsum;
+    }
+    // the owner takes the state after vertex k*-1
+    const int kl = kstar - 1;
+    const float nx0 = rl(Lk.x[0], kl), nx1 = rl(Lk.x[1], kl), nx2 = rl(Lk.x[2], kl);
+    const float nw0 = rl(wn[0], kl), nw1 = rl(wn[1], kl), nw2 = rl(wn[2], kl);
+    const float tsum = rl(tt, kl);
+    if ((int)lane == j) {
+        L.x[0] = nx0; L.x[1] = nx1; L.x[2] = nx2;
+        L.w[0] = nw0; L.w[1] = nw1; L.w[2] = nw2;
+        L.v += (uint32_t)kstar;
+        L.nsc += (uint32_t)kstar;
+        if constexpr (ADJ) {
+            const int mb = P.off_med + Q.medium * kMedWords;
+            Sw[pss * 64 + j] += (float)kstar * inv_ss - tsum;
+            for (int q = 0; q < Q.ndy; ++q)
+                Sw[wi(T, mb + MW_PC + q) * 64 + j] -=
+                    wf(T, P.off_kap + (Q.medium * P.kap_stride + q) * P.N + Q.lam) * tsum;
+        }
+    }
+}
+
+// -------------------------------------------------------------------------
 // The persistent transport kernel.
 template <int GEOM, int MODE>
 __global__ void __launch_bounds__(256) k_transport(const KParams P, const KBuffers B) {
@@ -453,6 +632,8 @@ __global__ void __launch_bounds__(256) k_transport(const KParams P, const KBuffe
                             }
                         }
                         L.medium = (GEOM == FPT_GEOM_BOX) ? -1 : P.body_medium;
+                        L.sc[0] = L.sc[1] = L.sc[2] = 0.f;
+                        L.sr2 = 0.f;
                         load_medium(P, T, L);
                         cnt.vertices++;
                         if constexpr (ADJ) {
@@ -471,6 +652,18 @@ __global__ void __launch_bounds__(256) k_transport(const KParams P, const KBuffe
         if (__ballot(alive) == 0ull) {
             if (exhausted) break;
             continue;
+        }
+
+        // ---- long paths: wave-cooperative blocks of up to 64 vertices each
+        if constexpr (MODE != MODE_REC_ADJ) {
+            uint64_t elig = __ballot(alive && !fresh && L.v >= P.block_min_v && L.medium >= 0 &&
+                                     L.st > 0.f && (P.exc_scatter || L.nem > 0u));
+            while (elig) {
+                const int j = __ffsll((unsigned long long)elig) - 1;
+                elig &= elig - 1ull;
+                block_walk<GEOM, MODE>(P, B, T, SP, tally, L, j, lane, pinhole, cnt,
+                                       ADJ ? A.S - lane : nullptr, ADJ ? A.Gx : nullptr, G);
+            }
         }
 
         // ---- one segment of the walk for every live lane with no pending splat

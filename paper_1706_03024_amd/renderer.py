@@ -77,8 +77,10 @@ class Scene:
             self._h, None if c is None else c.ctypes.data, None if q is None else q.ctypes.data,
             None if s is None else s.ctypes.data))
 
-    def set_tune(self, block_threads=0, blocks_per_cu=0, refill_lanes=0, chunk_paths=0):
-        t = _abi.Tune(block_threads, blocks_per_cu, refill_lanes, chunk_paths)
+    def set_tune(self, block_threads=0, blocks_per_cu=0, refill_lanes=0, chunk_paths=0,
+                 block_min_vertices=0):
+        t = _abi.Tune(block_threads, blocks_per_cu, refill_lanes, chunk_paths,
+                      block_min_vertices)
         check(lib().fpt_scene_set_tune(self._h, C.byref(t)))
 
     def tables(self):
