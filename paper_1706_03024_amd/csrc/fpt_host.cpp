@@ -26,6 +26,12 @@ hipError_t launch_finalize_counts(const uint32_t* counts, float* film, size_t n,
                                   hipStream_t s);
 hipError_t launch_reduce_partials(const float* partials, int nblocks, int np, float* grad,
                                   hipStream_t s);
+int batch_slot_words(int hist_words, int max_table_words);
+size_t batch_lds_bytes(const KBatch& Bt, int block);
+hipError_t batch_occupancy(const KBatch& Bt, int block, int* n);
+hipError_t launch_batch(const KBatch& Bt, int grid, int block, hipStream_t s);
+hipError_t launch_finalize_batch(const uint32_t* counts, float* films, const float* wscale,
+                                 int hist_words, size_t n, hipStream_t s);
 }  // namespace fpt
 
 using namespace fpt;
@@ -547,6 +553,98 @@ int block_for(const fpt_scene* sc) {
 
 }  // namespace
 
+struct fpt_batch {
+    int n = 0, N = 0, hist_words = 0, max_table_words = 0;
+    int device = 0, n_cu = 256, grid = 1, block = 256;
+    uint64_t total_paths = 0;
+    fpt_tune tune;
+    std::vector<KParams> params;
+    std::vector<double> cost;
+    std::vector<uint32_t> path_counts;
+    std::vector<float> wscale;
+    KParams* d_params = nullptr;
+    uint32_t* d_tables = nullptr;
+    uint32_t* d_toff = nullptr;
+    float* d_wscale = nullptr;
+    uint32_t* d_counts = nullptr;
+    unsigned long long* d_counter = nullptr;
+    KWorkItem* d_items = nullptr;
+    size_t items_cap = 0;
+    KBatch kbatch;
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    float* g_films = nullptr;
+    uint64_t* g_tallies = nullptr;
+};
+
+namespace {
+
+// (Re)builds the work-item queue and launch shape from the batch's tune: items
+// of chunk_paths paths, instances in decreasing expected cost.
+int32_t batch_build_items(fpt_batch* bt) {
+    const uint32_t chunk = bt->tune.chunk_paths > 0 ? (uint32_t)bt->tune.chunk_paths : 4096u;
+    std::vector<int> order((size_t)bt->n);
+    for (int i = 0; i < bt->n; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return bt->cost[a] > bt->cost[b]; });
+    std::vector<KWorkItem> items;
+    for (int i : order) {
+        for (uint32_t lo = 0; lo < bt->path_counts[i]; lo += chunk) {
+            KWorkItem w;
+            w.instance = (uint32_t)i;
+            w.path_lo = lo;
+            w.path_hi = std::min<uint32_t>(bt->path_counts[i], lo + chunk);
+            w.pad = 0;
+            items.push_back(w);
+        }
+    }
+    if (items.size() > bt->items_cap) {
+        if (bt->d_items) (void)hipFree(bt->d_items);
+        bt->d_items = nullptr;
+        bt->items_cap = 0;
+        HIP_TRY(hipMalloc(&bt->d_items, std::max<size_t>(1, items.size()) * sizeof(KWorkItem)), "hipMalloc(items)");
+        bt->items_cap = items.size();
+    }
+    if (!items.empty())
+        HIP_TRY(hipMemcpy(bt->d_items, items.data(), items.size() * sizeof(KWorkItem), hipMemcpyHostToDevice),
+                "upload items");
+    const int refill = bt->tune.refill_lanes > 0 ? std::min(64, bt->tune.refill_lanes) : 16;
+    const uint32_t bmin = bt->tune.block_min_vertices > 0 ? (uint32_t)bt->tune.block_min_vertices : 48u;
+    for (KParams& p : bt->params) {
+        p.refill_lanes = refill;
+        p.block_min_v = bmin;
+    }
+    HIP_TRY(hipMemcpy(bt->d_params, bt->params.data(), sizeof(KParams) * bt->n, hipMemcpyHostToDevice),
+            "upload params");
+    KBatch& K = bt->kbatch;
+    std::memset(&K, 0, sizeof K);
+    K.params = bt->d_params;
+    K.tables = bt->d_tables;
+    K.table_off = bt->d_toff;
+    K.items = bt->d_items;
+    K.n_items = (int)items.size();
+    K.n_instances = bt->n;
+    K.hist_words = bt->hist_words;
+    K.slot_words = batch_slot_words(bt->hist_words, bt->max_table_words);
+    K.counts = bt->d_counts;
+    K.item_counter = bt->d_counter;
+    int b = bt->tune.block_threads > 0 ? bt->tune.block_threads : 256;
+    bt->block = std::max(64, std::min(256, (b / 64) * 64));
+    int per_cu = 0;
+    HIP_TRY(batch_occupancy(K, bt->block, &per_cu), "batch occupancy");
+    if (bt->tune.blocks_per_cu > 0) per_cu = std::min(per_cu, bt->tune.blocks_per_cu);
+    bt->grid = std::max(1, bt->n_cu * std::max(per_cu, 1));
+    // a new launch shape invalidates a captured graph
+    if (bt->exec) (void)hipGraphExecDestroy(bt->exec);
+    if (bt->graph) (void)hipGraphDestroy(bt->graph);
+    bt->exec = nullptr;
+    bt->graph = nullptr;
+    bt->g_films = nullptr;
+    return FPT_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 uint32_t fpt_abi_version(void) { return FPT_ABI_VERSION; }
@@ -753,16 +851,220 @@ int32_t fpt_render_records(fpt_scene* sc, const fpt_run* run, fpt_path_record* r
     return FPT_OK;
 }
 
-int32_t fpt_batch_create(const fpt_scene_desc*, const fpt_run*, int32_t, const fpt_tune*, fpt_batch** out) {
-    if (out) *out = nullptr;
-    return set_err(FPT_E_UNSUPPORTED, "batched form not built yet");
+int32_t fpt_batch_create(const fpt_scene_desc* descs, const fpt_run* runs, int32_t n,
+                         const fpt_tune* tune, fpt_batch** out) {
+    if (!descs || !runs || !out) return set_err(FPT_E_INVALID, "NULL argument");
+    *out = nullptr;
+    if (n < 1 || n > (1 << 20)) return set_err(FPT_E_RANGE, "instance count %d", n);
+    fpt_batch* bt = new (std::nothrow) fpt_batch();
+    if (!bt) return set_err(FPT_E_NOMEM, "host allocation");
+    std::memset(&bt->tune, 0, sizeof bt->tune);
+    if (tune) bt->tune = *tune;
+    bt->n = n;
+    int32_t rc = FPT_OK;
+    std::vector<KParams> params((size_t)n);
+    std::vector<uint32_t> tables, toff((size_t)n);
+    std::vector<float> wscale((size_t)n);
+    std::vector<double> cost((size_t)n);
+    int max_tw = 0;
+    for (int i = 0; i < n && rc == FPT_OK; ++i) {
+        const fpt_scene_desc& d = descs[i];
+        if ((rc = validate(&d)) != FPT_OK) break;
+        if (d.geometry != FPT_GEOM_SLAB && d.geometry != FPT_GEOM_SPHERE) {
+            rc = set_err(FPT_E_UNSUPPORTED, "instance %d: batched instances are slabs or spheres", i);
+            break;
+        }
+        if (d.sensor != FPT_SENSOR_ESCAPE) {
+            rc = set_err(FPT_E_UNSUPPORTED, "instance %d: batched instances use the escape sensor", i);
+            break;
+        }
+        if (i > 0 && d.n_bins != descs[0].n_bins) {
+            rc = set_err(FPT_E_INVALID, "instance %d: all instances need the same n_bins", i);
+            break;
+        }
+        uint32_t B;
+        if ((rc = check_run(nullptr, &runs[i], &B)) != FPT_OK) break;
+        if (B != 1) { rc = set_err(FPT_E_UNSUPPORTED, "batched runs have no parity batches"); break; }
+        if (runs[i].path_count > 0xFFFFFFFFull) { rc = set_err(FPT_E_RANGE, "path_count"); break; }
+        fpt_scene tmp;
+        tmp.desc = d;
+        tmp.tune = bt->tune;
+        if ((rc = build_tables(&tmp)) != FPT_OK) break;
+        fill_run(&tmp, &runs[i], 1, &params[i]);
+        params[i].hist_words = 4 * d.n_bins;
+        toff[i] = (uint32_t)tables.size();
+        tables.insert(tables.end(), tmp.image.begin(), tmp.image.end());
+        while (tables.size() % 4) tables.push_back(0u);
+        max_tw = std::max(max_tw, params[i].table_words);
+        wscale[i] = params[i].wscale;
+        // expected work: paths x (1 + scattering optical size), for longest-first ordering
+        const fpt_medium& md = d.media[d.body_medium];
+        const double size = d.geometry == FPT_GEOM_SLAB ? d.slab_z1 - d.slab_z0 : 2.0 * d.body_radius;
+        cost[i] = (double)runs[i].path_count * (1.0 + md.sigma_s_mm * size);
+        bt->total_paths += runs[i].path_count;
+    }
+    if (rc != FPT_OK) {
+        delete bt;
+        return rc;
+    }
+    bt->N = descs[0].n_bins;
+    bt->hist_words = 4 * bt->N;
+    bt->params = params;
+    bt->cost = cost;
+    bt->path_counts.resize((size_t)n);
+    for (int i = 0; i < n; ++i) bt->path_counts[i] = (uint32_t)runs[i].path_count;
+    bt->wscale = wscale;
+    bt->max_table_words = max_tw;
+    hipError_t e = hipGetDevice(&bt->device);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&bt->n_cu, hipDeviceAttributeMultiprocessorCount, bt->device);
+    if (e == hipSuccess) e = hipMalloc(&bt->d_params, sizeof(KParams) * n);
+    if (e == hipSuccess) e = hipMalloc(&bt->d_tables, std::max<size_t>(4, tables.size() * 4));
+    if (e == hipSuccess) e = hipMalloc(&bt->d_toff, 4 * (size_t)n);
+    if (e == hipSuccess) e = hipMalloc(&bt->d_wscale, 4 * (size_t)n);
+    if (e == hipSuccess) e = hipMalloc(&bt->d_counts, 4 * (size_t)n * bt->hist_words);
+    if (e == hipSuccess) e = hipMalloc(&bt->d_counter, 64);
+    if (e == hipSuccess) e = hipMemcpy(bt->d_params, params.data(), sizeof(KParams) * n, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(bt->d_tables, tables.data(), tables.size() * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(bt->d_toff, toff.data(), 4 * (size_t)n, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(bt->d_wscale, wscale.data(), 4 * (size_t)n, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&bt->cap_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        fpt_batch_destroy(bt);
+        return hip_err(e, "batch setup");
+    }
+    if ((rc = batch_build_items(bt)) != FPT_OK) {
+        fpt_batch_destroy(bt);
+        return rc;
+    }
+    *out = bt;
+    return FPT_OK;
 }
-int32_t fpt_batch_render(fpt_batch*, float*, uint64_t*, void*) {
-    return set_err(FPT_E_UNSUPPORTED, "batched form not built yet");
+
+int32_t fpt_batch_render(fpt_batch* bt, float* films, uint64_t* tallies, void* stream) {
+    if (!bt || !films) return set_err(FPT_E_INVALID, "NULL argument");
+    hipStream_t s = (hipStream_t)stream;
+    if (!bt->exec || bt->g_films != films || bt->g_tallies != tallies) {
+        if (bt->exec) (void)hipGraphExecDestroy(bt->exec);
+        if (bt->graph) (void)hipGraphDestroy(bt->graph);
+        bt->exec = nullptr;
+        bt->graph = nullptr;
+        KBatch K = bt->kbatch;
+        K.tallies = reinterpret_cast<unsigned long long*>(tallies);
+        const size_t nc = (size_t)bt->n * bt->hist_words;
+        HIP_TRY(hipStreamBeginCapture(bt->cap_stream, hipStreamCaptureModeThreadLocal), "begin capture");
+        hipError_t e = launch_zero_u32(bt->d_counts, nc, bt->cap_stream);
+        if (e == hipSuccess) e = launch_zero_u64(bt->d_counter, 1, bt->cap_stream);
+        if (e == hipSuccess) e = launch_batch(K, bt->grid, bt->block, bt->cap_stream);
+        if (e == hipSuccess) e = launch_finalize_batch(bt->d_counts, films, bt->d_wscale, bt->hist_words, nc, bt->cap_stream);
+        hipGraph_t g = nullptr;
+        hipError_t e2 = hipStreamEndCapture(bt->cap_stream, &g);
+        if (e != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return hip_err(e, "batch capture");
+        }
+        if (e2 != hipSuccess) return hip_err(e2, "end capture");
+        bt->graph = g;
+        HIP_TRY(hipGraphInstantiate(&bt->exec, bt->graph, nullptr, nullptr, 0), "graph instantiate");
+        bt->g_films = films;
+        bt->g_tallies = tallies;
+    }
+    HIP_TRY(hipGraphLaunch(bt->exec, s), "graph launch");
+    return FPT_OK;
 }
-void fpt_batch_destroy(fpt_batch*) {}
-int32_t fpt_autotune(fpt_scene*, const fpt_run*, fpt_batch*, fpt_tune*, float*) {
-    return set_err(FPT_E_UNSUPPORTED, "autotuner not built yet");
+
+void fpt_batch_destroy(fpt_batch* bt) {
+    if (!bt) return;
+    if (bt->exec) (void)hipGraphExecDestroy(bt->exec);
+    if (bt->graph) (void)hipGraphDestroy(bt->graph);
+    if (bt->cap_stream) (void)hipStreamDestroy(bt->cap_stream);
+    if (bt->d_params) (void)hipFree(bt->d_params);
+    if (bt->d_tables) (void)hipFree(bt->d_tables);
+    if (bt->d_toff) (void)hipFree(bt->d_toff);
+    if (bt->d_wscale) (void)hipFree(bt->d_wscale);
+    if (bt->d_counts) (void)hipFree(bt->d_counts);
+    if (bt->d_counter) (void)hipFree(bt->d_counter);
+    if (bt->d_items) (void)hipFree(bt->d_items);
+    delete bt;
+}
+
+int32_t fpt_autotune(fpt_scene* sc, const fpt_run* run, fpt_batch* bt, fpt_tune* out, float* best_ms) {
+    if (!out || (!sc && !bt) || (sc && !run)) return set_err(FPT_E_INVALID, "NULL argument");
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0), "event");
+    HIP_TRY(hipEventCreate(&e1), "event");
+    float* film = nullptr;
+    size_t film_n = 0;
+    if (sc) {
+        uint32_t B;
+        int32_t rc = check_run(sc, run, &B);
+        if (rc != FPT_OK) return rc;
+        film_n = (size_t)film_elems(sc->desc, B);
+    } else {
+        film_n = (size_t)bt->n * bt->hist_words;
+    }
+    HIP_TRY(hipMalloc(&film, film_n * 4), "hipMalloc(tune film)");
+    const fpt_tune saved = sc ? sc->tune : bt->tune;
+    std::vector<fpt_tune> cand;
+    const int blocks[2] = {128, 256};
+    const int refills[3] = {8, 16, 32};
+    const int bmins[4] = {16, 32, 64, 128};
+    const int chunks[3] = {1024, 4096, 16384};
+    for (int b : blocks)
+        for (int r : refills)
+            for (int m : bmins) {
+                if (sc) {
+                    fpt_tune t = {b, 0, r, 0, m};
+                    cand.push_back(t);
+                } else {
+                    for (int c : chunks) {
+                        fpt_tune t = {b, 0, r, c, m};
+                        cand.push_back(t);
+                    }
+                }
+            }
+    float best = 1e30f;
+    fpt_tune best_t = saved;
+    int32_t rc = FPT_OK;
+    for (const fpt_tune& t : cand) {
+        if (sc) {
+            sc->tune = t;
+        } else {
+            bt->tune = t;
+            if ((rc = batch_build_items(bt)) != FPT_OK) break;
+        }
+        float ms_sum = 0.f;
+        for (int rep = 0; rep < 3 && rc == FPT_OK; ++rep) {
+            if (sc) rc = fpt_render(sc, run, film, nullptr, nullptr);
+            else rc = fpt_batch_render(bt, film, nullptr, nullptr);
+            if (rc != FPT_OK) break;
+            if (hipEventRecord(e0, nullptr) != hipSuccess) { rc = set_err(FPT_E_DEVICE, "event record"); break; }
+            if (sc) rc = fpt_render(sc, run, film, nullptr, nullptr);
+            else rc = fpt_batch_render(bt, film, nullptr, nullptr);
+            if (rc != FPT_OK) break;
+            (void)hipEventRecord(e1, nullptr);
+            (void)hipEventSynchronize(e1);
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            ms_sum += ms;
+        }
+        if (rc != FPT_OK) break;
+        if (ms_sum / 3 < best) {
+            best = ms_sum / 3;
+            best_t = t;
+        }
+    }
+    if (sc) sc->tune = saved;
+    else {
+        bt->tune = saved;
+        (void)batch_build_items(bt);
+    }
+    (void)hipFree(film);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != FPT_OK) return rc;
+    *out = best_t;
+    if (best_ms) *best_ms = best;
+    return FPT_OK;
 }
 
 }  // extern "C"

@@ -84,38 +84,24 @@ struct KBuffers {
 
 // Batched form: one work item = a path range of one instance.
 struct KWorkItem {
-    uint32_t instance;   // index into the instance arrays
-    uint32_t path_lo;    // first path index (relative to the instance's path_begin)
+    uint32_t instance;  // index into the instance arrays
+    uint32_t path_lo;   // path indices [path_lo, path_hi) relative to the instance's path_begin
     uint32_t path_hi;
     uint32_t pad;
 };
 
-struct KInstance {
-    uint32_t key0, key1;
-    uint32_t path_begin;
-    float wscale;
-    int geometry;        // FPT_GEOM_SLAB or FPT_GEOM_SPHERE
-    float z0, z1;
-    float bc[3], br2;
-    float lpos[3], ldir[3];
-    float line_cum[FPT_MAX_LINES];
-    int line_bin[FPT_MAX_LINES];
-    int n_lines;
-    uint32_t table_offset;  // word offset of this instance's table image
-    uint32_t table_words;
-    uint32_t max_scatter, max_emissions;
-    int exc_scatter;
-    int pad[2];
-};
-
-struct KBatchParams {
-    int N;
+struct KBatch {
+    const KParams* params;          // [n_instances] complete per-instance launch parameters
+    const uint32_t* tables;         // concatenated table images
+    const uint32_t* table_off;      // [n_instances] word offset of each image
+    const KWorkItem* items;         // [n_items], largest expected cost first
     int n_items;
     int n_instances;
-    int max_table_words;  // LDS words per wave slot
-    int cum_stride, kap_stride;
-    int off_med, off_dye, off_st, off_cum, off_cdf;
-    int refill_lanes;
+    int slot_words;                 // LDS words per wave: params | tally | histogram | table
+    int hist_words;                 // 4 * n_bins
+    uint32_t* counts;               // [n_instances][hist_words] escape counts
+    unsigned long long* tallies;    // [n_instances][FPT_N_TALLIES] or null
+    unsigned long long* item_counter;
 };
 
 }  // namespace fpt

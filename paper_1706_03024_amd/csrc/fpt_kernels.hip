@@ -527,6 +527,400 @@ DEV void block_walk(const KParams& P, const KBuffers& B, const uint32_t* T, cons
 }
 
 // -------------------------------------------------------------------------
+// Per-wave context and per-lane walk state, shared by the single-scene and the
+// batched persistent kernels.
+struct WaveCtx {
+    const uint32_t* T;   // table image (LDS)
+    const KSphere* SP;   // sphere table (LDS)
+    uint32_t* tally;     // u32[FPT_N_TALLIES] event counters (LDS)
+    uint32_t* hist;      // escape histogram (LDS) when lds_hist
+    bool lds_hist;
+    bool pinhole;
+    uint32_t lane;
+};
+
+struct WalkState {
+    Lane L;
+    bool alive, fresh;
+    int pend;
+    float nrm[3];
+    uint32_t rrb;
+    Counters cnt;
+};
+
+// Vertex 0 of path `pid`: the light (eq. 12: light point and excitation
+// wavelength are sampled), then the source splat is left pending.
+template <int GEOM, int MODE>
+DEV void start_path(const KParams& P, const WaveCtx& C, WalkState& W, AdjView& A, uint32_t pid) {
+    constexpr bool ADJ = (MODE == MODE_ADJ || MODE == MODE_REC_ADJ);
+    constexpr bool REC = (MODE == MODE_REC || MODE == MODE_REC_ADJ);
+    (void)ADJ;
+    (void)REC;
+    Lane& L = W.L;
+    bool& alive = W.alive;
+    bool& fresh = W.fresh;
+    int& pend = W.pend;
+    float* nrm = W.nrm;
+    uint32_t& rrb = W.rrb;
+    Counters& cnt = W.cnt;
+    const uint32_t* T = C.T;
+    const KSphere* SP = C.SP;
+    uint32_t* tally = C.tally;
+    uint32_t* hist = C.hist;
+    const bool lds_hist = C.lds_hist;
+    const bool pinhole = C.pinhole;
+    const uint32_t lane = C.lane;
+    (void)SP;
+    (void)hist;
+    (void)lds_hist;
+    (void)pinhole;
+    (void)tally;
+    (void)lane;
+    L.pid = pid;
+    // ---- vertex 0: the light (eq. 12: light point, excitation wavelength)
+    alive = true;
+    fresh = true;
+    L.v = 0;
+    L.nsc = 0;
+    L.nem = 0;
+    L.comp = 0;
+    L.batch = L.pid % P.batches;
+    L.splat_sum = 0.f;
+    const uint4 r = philox(L.pid, 0u, 0u, 0u, P.key0, P.key1);
+    const float u = u24(r.x);
+    int line = 0;
+    for (; line < P.n_lines - 1; ++line)
+        if (u < P.line_cum[line]) break;
+    L.lam = P.line_bin[line];
+    if (P.light == FPT_LIGHT_BEAM) {
+        L.x[0] = P.lpos[0]; L.x[1] = P.lpos[1]; L.x[2] = P.lpos[2];
+        L.w[0] = P.ldir[0]; L.w[1] = P.ldir[1]; L.w[2] = P.ldir[2];
+        L.region = 0;
+    } else {
+        const uint4 r1 = philox(L.pid, 0u, 1u, 0u, P.key0, P.key1);
+        const float ua = u24(r1.x), ub = u24(r1.y);
+        float sp, cp;
+        sincospif(2.f * ub, &sp, &cp);
+        if (P.light == FPT_LIGHT_POINT) {
+            L.x[0] = P.lpos[0]; L.x[1] = P.lpos[1]; L.x[2] = P.lpos[2];
+            const float ct = 1.f - 2.f * ua;
+            const float st = 2.f * sqrtf(ua * (1.f - ua));
+            L.w[0] = st * cp; L.w[1] = st * sp; L.w[2] = ct;
+            L.region = 0;
+        } else {
+            const float a = u24(r.y), b = u24(r.z);
+            const float sr = sqrtf(ua), cz = sqrtf(1.f - ua);
+            const float lx = sr * cp, ly = sr * sp;
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                L.x[i] = P.lpos[i] + a * P.lu[i] + b * P.lv[i];
+                L.w[i] = lx * P.lt1[i] + ly * P.lt2[i] + cz * P.ln[i];
+            }
+            L.region = -1;
+        }
+    }
+    L.medium = (GEOM == FPT_GEOM_BOX) ? -1 : P.body_medium;
+    L.sc[0] = L.sc[1] = L.sc[2] = 0.f;
+    L.sr2 = 0.f;
+    load_medium(P, T, L);
+    cnt.vertices++;
+    if constexpr (ADJ) {
+#pragma unroll
+        for (int i = 0; i < kMaxNP; ++i) A.S[i * 64] = 0.f;
+    }
+    if (pinhole && P.light == FPT_LIGHT_QUAD) {
+        pend = PEND_SOURCE;
+        nrm[0] = P.ln[0]; nrm[1] = P.ln[1]; nrm[2] = P.ln[2];
+        rrb = rr_bits(r);
+    }
+}
+
+// One iteration of the walk for every live lane: wave-cooperative blocks for
+// long paths, one segment of the walk, the convergent splat section and the
+// bookkeeping of paths that ended.
+template <int GEOM, int MODE>
+DEV void advance(const KParams& P, const KBuffers& B, const WaveCtx& C, WalkState& W, AdjView& A,
+                 float* G) {
+    constexpr bool ADJ = (MODE == MODE_ADJ || MODE == MODE_REC_ADJ);
+    constexpr bool REC = (MODE == MODE_REC || MODE == MODE_REC_ADJ);
+    (void)ADJ;
+    (void)REC;
+    Lane& L = W.L;
+    bool& alive = W.alive;
+    bool& fresh = W.fresh;
+    int& pend = W.pend;
+    float* nrm = W.nrm;
+    uint32_t& rrb = W.rrb;
+    Counters& cnt = W.cnt;
+    const uint32_t* T = C.T;
+    const KSphere* SP = C.SP;
+    uint32_t* tally = C.tally;
+    uint32_t* hist = C.hist;
+    const bool lds_hist = C.lds_hist;
+    const bool pinhole = C.pinhole;
+    const uint32_t lane = C.lane;
+    (void)SP;
+    (void)hist;
+    (void)lds_hist;
+    (void)pinhole;
+    (void)tally;
+    (void)lane;
+    // ---- long paths: wave-cooperative blocks of up to 64 vertices each
+    if constexpr (MODE != MODE_REC_ADJ) {
+        uint64_t elig = __ballot(alive && !fresh && L.v >= P.block_min_v && L.medium >= 0 &&
+                                 L.st > 0.f && (P.exc_scatter || L.nem > 0u));
+        while (elig) {
+            const int j = __ffsll((unsigned long long)elig) - 1;
+            elig &= elig - 1ull;
+            block_walk<GEOM, MODE>(P, B, T, SP, tally, L, j, lane, pinhole, cnt,
+                                   ADJ ? A.S - lane : nullptr, ADJ ? A.Gx : nullptr, G);
+        }
+    }
+
+    // ---- one segment of the walk for every live lane with no pending splat
+    int ev = EV_NONE;
+    int exit_code = -1;
+    if (alive && !(fresh && pend != PEND_NONE)) {
+        L.v++;
+        if (REC && P.max_vertices && L.v >= P.max_vertices) {
+            exit_code = FPT_EXIT_TRUNC;
+        } else if (L.v >= kMaxPathVertices) {
+            exit_code = FPT_EXIT_SCAP;  // hard bound: every wave's loop terminates
+        } else {
+            cnt.vertices++;
+            const uint4 r = philox(L.pid, L.v, 0u, 0u, P.key0, P.key1);
+            const float u0 = u24(r.x), u1 = u24(r.y), u2 = u24(r.z), u3 = u24(r.w);
+            // eq. 6: free flight with density sigma_t exp(-sigma_t t)
+            const float tf = (L.inv == kInf) ? kInf : -__logf(1.f - u0) * L.inv;
+            const Hit h = next_surface<GEOM>(P, SP, L, GEOM == FPT_GEOM_BOX && L.v == 1u);
+            const bool collide = tf < h.d;
+            const float len = collide ? tf : h.d;
+            if (len < kInf) {
+                L.x[0] += len * L.w[0];
+                L.x[1] += len * L.w[1];
+                L.x[2] += len * L.w[2];
+                score_length<MODE>(P, T, L, A, len);
+            }
+            if (!collide) snap_to_plane<GEOM>(P, L, h);
+            float dir_sin = 0.f, dir_cos = 0.f;  // polar sine/cosine of a new direction
+            int frame = -1;                      // -1 world axes, else wall face
+            if (collide) {
+                const float s = u1 * L.st;
+                if (s < L.ss) {
+                    // elastic scattering, isotropic phase function (eq. 2)
+                    ev = EV_SCATTER;
+                    if constexpr (ADJ)
+                        adj_add(A.S, wi(T, P.off_med + L.medium * kMedWords + MW_PSS),
+                                wf(T, P.off_med + L.medium * kMedWords + MW_INV_SS));
+                    L.nsc++;
+                    cnt.scatters++;
+                    if (!P.exc_scatter && L.nem == 0u) exit_code = FPT_EXIT_EXCSCAT;
+                    else if (L.nsc > P.max_scatter) exit_code = FPT_EXIT_SCAP;
+                    else {
+                        dir_cos = 1.f - 2.f * u2;
+                        dir_sin = 2.f * sqrtf(u2 * (1.f - u2));
+                        pend = PEND_MEDIUM;
+                    }
+                } else if (s < L.thr_bg || L.ndy == 0) {
+                    ev = EV_BG;
+                    exit_code = FPT_EXIT_BG;
+                } else {
+                    // a fluorescent particle: which dye slot (sec. 4.1)
+                    ev = EV_DYE;
+                    int j = 0;
+                    const int cb = P.off_cum + L.medium * P.cum_stride * P.N + L.lam;
+                    for (; j < L.ndy - 1; ++j)
+                        if (s < wf(T, cb + j * P.N)) break;
+                    const int mb = P.off_med + L.medium * kMedWords;
+                    if constexpr (ADJ) adj_add(A.S, wi(T, mb + MW_PC + j), wf(T, mb + MW_INV_C + j));
+                    lds_count(tally, FPT_T_DYE_ABS);
+                    if (L.nem >= P.max_emissions) {
+                        exit_code = FPT_EXIT_KCAP;
+                    } else {
+                        const int dye = wi(T, mb + MW_DYE + j);
+                        const int db = P.off_dye + dye * kDyeWords;
+                        const uint4 r1 = philox(L.pid, L.v, 1u, 0u, P.key0, P.key1);
+                        const float uq = u24(r1.x);
+                        if (!(uq < wf(T, db + DW_QY))) {
+                            if constexpr (ADJ) adj_add(A.S, wi(T, db + DW_PQ), -wf(T, db + DW_INV_1MQY));
+                            exit_code = FPT_EXIT_NONRAD;
+                        } else {
+                            if constexpr (ADJ) adj_add(A.S, wi(T, db + DW_PQ), wf(T, db + DW_INV_QY));
+                            // eq. 10: emitted wavelength from the emission CDF,
+                            // independent of the excitation wavelength (sec. 2.1)
+                            const float ul = u24(r1.y);
+                            const uint32_t* cdf = T + P.off_cdf + dye * P.N;
+                            int lo = 0, hi = P.N - 1;
+                            while (lo < hi) {
+                                const int mid = (lo + hi) >> 1;
+                                if (ul < __uint_as_float(cdf[mid])) hi = mid;
+                                else lo = mid + 1;
+                            }
+                            L.lam = lo;
+                            load_sigma(P, T, L);
+                            L.nem++;
+                            L.comp = 1;
+                            lds_count(tally, FPT_T_EMISSIONS);
+                            dir_cos = 1.f - 2.f * u2;
+                            dir_sin = 2.f * sqrtf(u2 * (1.f - u2));
+                            pend = PEND_MEDIUM;
+                        }
+                    }
+                }
+            } else {
+                ev = h.ev;
+                if (ev == EV_ESC || ev == EV_INF) {
+                    const int side = L.w[2] < 0.f ? 0 : 1;
+                    exit_code = side == 0 ? FPT_EXIT_ESC_R : FPT_EXIT_ESC_T;
+                    if (!pinhole && !(P.fluo_only && L.comp == 0)) {
+                        const int idx = ((L.batch * 2 + L.comp) * 2 + side) * P.N + L.lam;
+                        if constexpr (MODE == MODE_FWD) {
+                            if (lds_hist) atomicAdd(&hist[idx], 1u);
+                            else atomicAdd(&B.counts[idx], 1u);
+                        }
+                        L.splat_sum += P.wscale;
+                        if constexpr (ADJ) {
+                            const float g = B.gfilm[idx] * P.wscale;
+#pragma unroll
+                            for (int i = 0; i < kMaxNP; ++i)
+                                if (i < P.np) G[i] += g * A.S[i * 64];
+                        }
+                    }
+                } else if (ev == EV_LIGHT) {
+                    exit_code = FPT_EXIT_LIGHT;
+                } else if (ev == EV_WALL) {
+                    const float rho = h.idx >= 0 ? wf(T, P.off_rho + h.idx * P.N + L.lam) : 0.f;
+                    if (!(u1 < rho)) {
+                        exit_code = FPT_EXIT_WALL;
+                    } else {
+                        // Lambertian reflection about the wall's inward normal
+                        lds_count(tally, FPT_T_WALL_REFLECT);
+                        dir_sin = sqrtf(u2);
+                        dir_cos = sqrtf(1.f - u2);
+                        frame = h.idx;
+                        pend = PEND_SURFACE;
+                    }
+                } else {
+                    // index-matched interface: change medium, keep direction
+                    lds_count(tally, FPT_T_CROSSINGS);
+                    if constexpr (GEOM == FPT_GEOM_BOX) {
+                        L.region = (ev == EV_ENTER) ? h.idx : -1;
+                        L.medium = -1;
+                        if (L.region >= 0) {
+                            const KSphere& sp = SP[L.region];
+                            L.sc[0] = sp.c[0];
+                            L.sc[1] = sp.c[1];
+                            L.sc[2] = sp.c[2];
+                            L.sr2 = sp.r2;
+                            L.medium = sp.medium;
+                        }
+                        load_medium(P, T, L);
+                    }
+                }
+            }
+            if (pend != PEND_NONE && exit_code < 0) {
+                float sp, cp;
+                sincospif(2.f * u3, &sp, &cp);
+                const float a = dir_sin * cp, b = dir_sin * sp;
+                if (frame < 0) {
+                    L.w[0] = a; L.w[1] = b; L.w[2] = dir_cos;
+                } else {
+                    // wall frame: normal n = sg e_ax, tangents e_(ax+1), sg e_(ax+2)
+                    const int ax = frame >> 1;
+                    const float sg = (frame & 1) ? -1.f : 1.f;
+                    const float c = sg * dir_cos, bb = sg * b;
+                    L.w[0] = ax == 0 ? c : (ax == 1 ? bb : a);
+                    L.w[1] = ax == 0 ? a : (ax == 1 ? c : bb);
+                    L.w[2] = ax == 0 ? bb : (ax == 1 ? a : c);
+                    nrm[0] = ax == 0 ? sg : 0.f;
+                    nrm[1] = ax == 1 ? sg : 0.f;
+                    nrm[2] = ax == 2 ? sg : 0.f;
+                }
+                rrb = rr_bits(r);
+            } else {
+                pend = PEND_NONE;
+            }
+        }
+    }
+
+    // ---- convergent splat section
+    if constexpr (GEOM == FPT_GEOM_BOX) {
+        if (pend != PEND_NONE && alive && exit_code < 0) {
+            if (!(P.fluo_only && L.comp == 0)) {
+                const SplatOut so = splat_eval(P, T, SP, L, pend, nrm, rrb);
+                if (so.status == 0) {
+                    cnt.splat_hit++;
+                    L.splat_sum += so.v;
+                    if constexpr (MODE == MODE_FWD) unsafeAtomicAdd(&B.film[so.idx], so.v);
+                    if constexpr (ADJ) {
+                        const float g = B.gfilm[so.idx];
+                        const float gv = g * so.v;
+#pragma unroll
+                        for (int i = 0; i < kMaxNP; ++i)
+                            if (i < P.np) G[i] += gv * A.S[i * 64];
+                        // d v / d theta = -v sum_s chord_s d sigma_t(m_s) / d theta
+                        const float e0 = P.eye[0] - L.x[0], e1 = P.eye[1] - L.x[1], e2 = P.eye[2] - L.x[2];
+                        const float dist = sqrtf(e0 * e0 + e1 * e1 + e2 * e2);
+                        const float id = __builtin_amdgcn_rcpf(dist);
+                        const float wc[3] = {e0 * id, e1 * id, e2 * id};
+                        for (int s = 0; s < P.n_spheres; ++s) {
+                            const float len = chord_len(SP[s], L.x, wc, dist);
+                            if (!(len > 0.f)) continue;
+                            const int m = SP[s].medium;
+                            const int mb = P.off_med + m * kMedWords;
+                            const float c = -gv * len;
+                            adj_add(A.Gx, wi(T, mb + MW_PSS), c);
+                            const int nd = wi(T, mb + MW_NDYES);
+                            for (int j = 0; j < nd; ++j)
+                                adj_add(A.Gx, wi(T, mb + MW_PC + j),
+                                        c * wf(T, P.off_kap + (m * P.kap_stride + j) * P.N + L.lam));
+                        }
+                    }
+                } else {
+                    lds_count(tally, so.status == 2 ? FPT_T_SPLAT_RR_KILL : FPT_T_SPLAT_MISS);
+                }
+            }
+        }
+    }
+    pend = PEND_NONE;
+
+    // ---- path end
+    if (alive && exit_code >= 0) {
+        alive = false;
+        lds_count(tally, FPT_T_EXIT0 + exit_code);
+        if constexpr (REC) {
+            fpt_path_record rc;
+            rc.n_vertices = L.v + (exit_code == FPT_EXIT_TRUNC ? 0u : 1u);
+            rc.n_scatter = L.nsc;
+            rc.n_emit = L.nem;
+            rc.exit_code = (uint32_t)exit_code;
+            rc.lambda = L.lam;
+            rc.comp = L.comp;
+            rc.region = L.region;
+            rc.pad = 0;
+            rc.pos[0] = L.x[0]; rc.pos[1] = L.x[1]; rc.pos[2] = L.x[2];
+            rc.dir[0] = L.w[0]; rc.dir[1] = L.w[1]; rc.dir[2] = L.w[2];
+            rc.splat_sum = L.splat_sum;
+            rc.pad2 = 0.f;
+            const uint32_t k = L.pid - P.path_begin;
+            B.rec[k] = rc;
+            if constexpr (ADJ) {
+                if (B.rec_grad) {
+#pragma unroll
+                    for (int i = 0; i < kMaxNP; ++i)
+                        if (i < P.np) B.rec_grad[(size_t)k * P.np + i] = G[i] + A.Gx[i * 64];
+                }
+#pragma unroll
+                for (int i = 0; i < kMaxNP; ++i) {
+                    G[i] = 0.f;
+                    A.Gx[i * 64] = 0.f;
+                }
+            }
+        }
+    }
+}
+
+// -------------------------------------------------------------------------
 // The persistent transport kernel.
 template <int GEOM, int MODE>
 __global__ void __launch_bounds__(256) k_transport(const KParams P, const KBuffers B) {
@@ -564,354 +958,51 @@ __global__ void __launch_bounds__(256) k_transport(const KParams P, const KBuffe
     }
     __syncthreads();
 
-    const bool pinhole = (GEOM == FPT_GEOM_BOX) && P.sensor == FPT_SENSOR_PINHOLE;
-    Counters cnt = {0u, 0u, 0u};
-    Lane L;
-    L.pid = 0;
-    bool alive = false;
+    WaveCtx C;
+    C.T = T;
+    C.SP = SP;
+    C.tally = tally;
+    C.hist = hist;
+    C.lds_hist = lds_hist;
+    C.pinhole = (GEOM == FPT_GEOM_BOX) && P.sensor == FPT_SENSOR_PINHOLE;
+    C.lane = lane;
+    WalkState W;
+    W.cnt = {0u, 0u, 0u};
+    W.L.pid = 0;
+    W.alive = false;
+    W.pend = PEND_NONE;
+    W.nrm[0] = W.nrm[1] = W.nrm[2] = 0.f;
+    W.rrb = 0;
     bool exhausted = false;
-    int pend = PEND_NONE;
-    float nrm[3] = {0.f, 0.f, 0.f};
-    uint32_t rrb = 0;
 
     for (;;) {
         // ---- refill dead lanes from the path queue (one atomic per wave)
-        bool fresh = false;
+        W.fresh = false;
         if (!exhausted) {
-            const uint64_t dead = __ballot(!alive);
+            const uint64_t dead = __ballot(!W.alive);
             const int ndead = __popcll(dead);
             if (ndead >= P.refill_lanes || ndead == 64) {
                 unsigned long long base = 0;
                 if (lane == 0) base = atomicAdd(B.counter, (unsigned long long)ndead);
                 base = __shfl(base, 0);
                 if (base + (unsigned long long)ndead >= (unsigned long long)P.path_count) exhausted = true;
-                if (!alive) {
+                if (!W.alive) {
                     const unsigned long long idx = base + mbcnt(dead);
-                    if (idx < (unsigned long long)P.path_count) {
-                        // ---- vertex 0: the light (eq. 12: light point, excitation wavelength)
-                        alive = true;
-                        fresh = true;
-                        L.pid = P.path_begin + (uint32_t)idx;
-                        L.v = 0;
-                        L.nsc = 0;
-                        L.nem = 0;
-                        L.comp = 0;
-                        L.batch = L.pid % P.batches;
-                        L.splat_sum = 0.f;
-                        const uint4 r = philox(L.pid, 0u, 0u, 0u, P.key0, P.key1);
-                        const float u = u24(r.x);
-                        int line = 0;
-                        for (; line < P.n_lines - 1; ++line)
-                            if (u < P.line_cum[line]) break;
-                        L.lam = P.line_bin[line];
-                        if (P.light == FPT_LIGHT_BEAM) {
-                            L.x[0] = P.lpos[0]; L.x[1] = P.lpos[1]; L.x[2] = P.lpos[2];
-                            L.w[0] = P.ldir[0]; L.w[1] = P.ldir[1]; L.w[2] = P.ldir[2];
-                            L.region = 0;
-                        } else {
-                            const uint4 r1 = philox(L.pid, 0u, 1u, 0u, P.key0, P.key1);
-                            const float ua = u24(r1.x), ub = u24(r1.y);
-                            float sp, cp;
-                            sincospif(2.f * ub, &sp, &cp);
-                            if (P.light == FPT_LIGHT_POINT) {
-                                L.x[0] = P.lpos[0]; L.x[1] = P.lpos[1]; L.x[2] = P.lpos[2];
-                                const float ct = 1.f - 2.f * ua;
-                                const float st = 2.f * sqrtf(ua * (1.f - ua));
-                                L.w[0] = st * cp; L.w[1] = st * sp; L.w[2] = ct;
-                                L.region = 0;
-                            } else {
-                                const float a = u24(r.y), b = u24(r.z);
-                                const float sr = sqrtf(ua), cz = sqrtf(1.f - ua);
-                                const float lx = sr * cp, ly = sr * sp;
-#pragma unroll
-                                for (int i = 0; i < 3; ++i) {
-                                    L.x[i] = P.lpos[i] + a * P.lu[i] + b * P.lv[i];
-                                    L.w[i] = lx * P.lt1[i] + ly * P.lt2[i] + cz * P.ln[i];
-                                }
-                                L.region = -1;
-                            }
-                        }
-                        L.medium = (GEOM == FPT_GEOM_BOX) ? -1 : P.body_medium;
-                        L.sc[0] = L.sc[1] = L.sc[2] = 0.f;
-                        L.sr2 = 0.f;
-                        load_medium(P, T, L);
-                        cnt.vertices++;
-                        if constexpr (ADJ) {
-#pragma unroll
-                            for (int i = 0; i < kMaxNP; ++i) A.S[i * 64] = 0.f;
-                        }
-                        if (pinhole && P.light == FPT_LIGHT_QUAD) {
-                            pend = PEND_SOURCE;
-                            nrm[0] = P.ln[0]; nrm[1] = P.ln[1]; nrm[2] = P.ln[2];
-                            rrb = rr_bits(r);
-                        }
-                    }
+                    if (idx < (unsigned long long)P.path_count)
+                        start_path<GEOM, MODE>(P, C, W, A, P.path_begin + (uint32_t)idx);
                 }
             }
         }
-        if (__ballot(alive) == 0ull) {
+        if (__ballot(W.alive) == 0ull) {
             if (exhausted) break;
             continue;
         }
-
-        // ---- long paths: wave-cooperative blocks of up to 64 vertices each
-        if constexpr (MODE != MODE_REC_ADJ) {
-            uint64_t elig = __ballot(alive && !fresh && L.v >= P.block_min_v && L.medium >= 0 &&
-                                     L.st > 0.f && (P.exc_scatter || L.nem > 0u));
-            while (elig) {
-                const int j = __ffsll((unsigned long long)elig) - 1;
-                elig &= elig - 1ull;
-                block_walk<GEOM, MODE>(P, B, T, SP, tally, L, j, lane, pinhole, cnt,
-                                       ADJ ? A.S - lane : nullptr, ADJ ? A.Gx : nullptr, G);
-            }
-        }
-
-        // ---- one segment of the walk for every live lane with no pending splat
-        int ev = EV_NONE;
-        int exit_code = -1;
-        if (alive && !(fresh && pend != PEND_NONE)) {
-            L.v++;
-            if (REC && P.max_vertices && L.v >= P.max_vertices) {
-                exit_code = FPT_EXIT_TRUNC;
-            } else if (L.v >= kMaxPathVertices) {
-                exit_code = FPT_EXIT_SCAP;  // hard bound: every wave's loop terminates
-            } else {
-                cnt.vertices++;
-                const uint4 r = philox(L.pid, L.v, 0u, 0u, P.key0, P.key1);
-                const float u0 = u24(r.x), u1 = u24(r.y), u2 = u24(r.z), u3 = u24(r.w);
-                // eq. 6: free flight with density sigma_t exp(-sigma_t t)
-                const float tf = (L.inv == kInf) ? kInf : -__logf(1.f - u0) * L.inv;
-                const Hit h = next_surface<GEOM>(P, SP, L, GEOM == FPT_GEOM_BOX && L.v == 1u);
-                const bool collide = tf < h.d;
-                const float len = collide ? tf : h.d;
-                if (len < kInf) {
-                    L.x[0] += len * L.w[0];
-                    L.x[1] += len * L.w[1];
-                    L.x[2] += len * L.w[2];
-                    score_length<MODE>(P, T, L, A, len);
-                }
-                if (!collide) snap_to_plane<GEOM>(P, L, h);
-                float dir_sin = 0.f, dir_cos = 0.f;  // polar sine/cosine of a new direction
-                int frame = -1;                      // -1 world axes, else wall face
-                if (collide) {
-                    const float s = u1 * L.st;
-                    if (s < L.ss) {
-                        // elastic scattering, isotropic phase function (eq. 2)
-                        ev = EV_SCATTER;
-                        if constexpr (ADJ)
-                            adj_add(A.S, wi(T, P.off_med + L.medium * kMedWords + MW_PSS),
-                                    wf(T, P.off_med + L.medium * kMedWords + MW_INV_SS));
-                        L.nsc++;
-                        cnt.scatters++;
-                        if (!P.exc_scatter && L.nem == 0u) exit_code = FPT_EXIT_EXCSCAT;
-                        else if (L.nsc > P.max_scatter) exit_code = FPT_EXIT_SCAP;
-                        else {
-                            dir_cos = 1.f - 2.f * u2;
-                            dir_sin = 2.f * sqrtf(u2 * (1.f - u2));
-                            pend = PEND_MEDIUM;
-                        }
-                    } else if (s < L.thr_bg || L.ndy == 0) {
-                        ev = EV_BG;
-                        exit_code = FPT_EXIT_BG;
-                    } else {
-                        // a fluorescent particle: which dye slot (sec. 4.1)
-                        ev = EV_DYE;
-                        int j = 0;
-                        const int cb = P.off_cum + L.medium * P.cum_stride * P.N + L.lam;
-                        for (; j < L.ndy - 1; ++j)
-                            if (s < wf(T, cb + j * P.N)) break;
-                        const int mb = P.off_med + L.medium * kMedWords;
-                        if constexpr (ADJ) adj_add(A.S, wi(T, mb + MW_PC + j), wf(T, mb + MW_INV_C + j));
-                        lds_count(tally, FPT_T_DYE_ABS);
-                        if (L.nem >= P.max_emissions) {
-                            exit_code = FPT_EXIT_KCAP;
-                        } else {
-                            const int dye = wi(T, mb + MW_DYE + j);
-                            const int db = P.off_dye + dye * kDyeWords;
-                            const uint4 r1 = philox(L.pid, L.v, 1u, 0u, P.key0, P.key1);
-                            const float uq = u24(r1.x);
-                            if (!(uq < wf(T, db + DW_QY))) {
-                                if constexpr (ADJ) adj_add(A.S, wi(T, db + DW_PQ), -wf(T, db + DW_INV_1MQY));
-                                exit_code = FPT_EXIT_NONRAD;
-                            } else {
-                                if constexpr (ADJ) adj_add(A.S, wi(T, db + DW_PQ), wf(T, db + DW_INV_QY));
-                                // eq. 10: emitted wavelength from the emission CDF,
-                                // independent of the excitation wavelength (sec. 2.1)
-                                const float ul = u24(r1.y);
-                                const uint32_t* cdf = T + P.off_cdf + dye * P.N;
-                                int lo = 0, hi = P.N - 1;
-                                while (lo < hi) {
-                                    const int mid = (lo + hi) >> 1;
-                                    if (ul < __uint_as_float(cdf[mid])) hi = mid;
-                                    else lo = mid + 1;
-                                }
-                                L.lam = lo;
-                                load_sigma(P, T, L);
-                                L.nem++;
-                                L.comp = 1;
-                                lds_count(tally, FPT_T_EMISSIONS);
-                                dir_cos = 1.f - 2.f * u2;
-                                dir_sin = 2.f * sqrtf(u2 * (1.f - u2));
-                                pend = PEND_MEDIUM;
-                            }
-                        }
-                    }
-                } else {
-                    ev = h.ev;
-                    if (ev == EV_ESC || ev == EV_INF) {
-                        const int side = L.w[2] < 0.f ? 0 : 1;
-                        exit_code = side == 0 ? FPT_EXIT_ESC_R : FPT_EXIT_ESC_T;
-                        if (!pinhole && !(P.fluo_only && L.comp == 0)) {
-                            const int idx = ((L.batch * 2 + L.comp) * 2 + side) * P.N + L.lam;
-                            if constexpr (MODE == MODE_FWD) {
-                                if (lds_hist) atomicAdd(&hist[idx], 1u);
-                                else atomicAdd(&B.counts[idx], 1u);
-                            }
-                            L.splat_sum += P.wscale;
-                            if constexpr (ADJ) {
-                                const float g = B.gfilm[idx] * P.wscale;
-#pragma unroll
-                                for (int i = 0; i < kMaxNP; ++i)
-                                    if (i < P.np) G[i] += g * A.S[i * 64];
-                            }
-                        }
-                    } else if (ev == EV_LIGHT) {
-                        exit_code = FPT_EXIT_LIGHT;
-                    } else if (ev == EV_WALL) {
-                        const float rho = h.idx >= 0 ? wf(T, P.off_rho + h.idx * P.N + L.lam) : 0.f;
-                        if (!(u1 < rho)) {
-                            exit_code = FPT_EXIT_WALL;
-                        } else {
-                            // Lambertian reflection about the wall's inward normal
-                            lds_count(tally, FPT_T_WALL_REFLECT);
-                            dir_sin = sqrtf(u2);
-                            dir_cos = sqrtf(1.f - u2);
-                            frame = h.idx;
-                            pend = PEND_SURFACE;
-                        }
-                    } else {
-                        // index-matched interface: change medium, keep direction
-                        lds_count(tally, FPT_T_CROSSINGS);
-                        if constexpr (GEOM == FPT_GEOM_BOX) {
-                            L.region = (ev == EV_ENTER) ? h.idx : -1;
-                            L.medium = -1;
-                            if (L.region >= 0) {
-                                const KSphere& sp = SP[L.region];
-                                L.sc[0] = sp.c[0];
-                                L.sc[1] = sp.c[1];
-                                L.sc[2] = sp.c[2];
-                                L.sr2 = sp.r2;
-                                L.medium = sp.medium;
-                            }
-                            load_medium(P, T, L);
-                        }
-                    }
-                }
-                if (pend != PEND_NONE && exit_code < 0) {
-                    float sp, cp;
-                    sincospif(2.f * u3, &sp, &cp);
-                    const float a = dir_sin * cp, b = dir_sin * sp;
-                    if (frame < 0) {
-                        L.w[0] = a; L.w[1] = b; L.w[2] = dir_cos;
-                    } else {
-                        // wall frame: normal n = sg e_ax, tangents e_(ax+1), sg e_(ax+2)
-                        const int ax = frame >> 1;
-                        const float sg = (frame & 1) ? -1.f : 1.f;
-                        const float c = sg * dir_cos, bb = sg * b;
-                        L.w[0] = ax == 0 ? c : (ax == 1 ? bb : a);
-                        L.w[1] = ax == 0 ? a : (ax == 1 ? c : bb);
-                        L.w[2] = ax == 0 ? bb : (ax == 1 ? a : c);
-                        nrm[0] = ax == 0 ? sg : 0.f;
-                        nrm[1] = ax == 1 ? sg : 0.f;
-                        nrm[2] = ax == 2 ? sg : 0.f;
-                    }
-                    rrb = rr_bits(r);
-                } else {
-                    pend = PEND_NONE;
-                }
-            }
-        }
-
-        // ---- convergent splat section
-        if constexpr (GEOM == FPT_GEOM_BOX) {
-            if (pend != PEND_NONE && alive && exit_code < 0) {
-                if (!(P.fluo_only && L.comp == 0)) {
-                    const SplatOut so = splat_eval(P, T, SP, L, pend, nrm, rrb);
-                    if (so.status == 0) {
-                        cnt.splat_hit++;
-                        L.splat_sum += so.v;
-                        if constexpr (MODE == MODE_FWD) unsafeAtomicAdd(&B.film[so.idx], so.v);
-                        if constexpr (ADJ) {
-                            const float g = B.gfilm[so.idx];
-                            const float gv = g * so.v;
-#pragma unroll
-                            for (int i = 0; i < kMaxNP; ++i)
-                                if (i < P.np) G[i] += gv * A.S[i * 64];
-                            // d v / d theta = -v sum_s chord_s d sigma_t(m_s) / d theta
-                            const float e0 = P.eye[0] - L.x[0], e1 = P.eye[1] - L.x[1], e2 = P.eye[2] - L.x[2];
-                            const float dist = sqrtf(e0 * e0 + e1 * e1 + e2 * e2);
-                            const float id = __builtin_amdgcn_rcpf(dist);
-                            const float wc[3] = {e0 * id, e1 * id, e2 * id};
-                            for (int s = 0; s < P.n_spheres; ++s) {
-                                const float len = chord_len(SP[s], L.x, wc, dist);
-                                if (!(len > 0.f)) continue;
-                                const int m = SP[s].medium;
-                                const int mb = P.off_med + m * kMedWords;
-                                const float c = -gv * len;
-                                adj_add(A.Gx, wi(T, mb + MW_PSS), c);
-                                const int nd = wi(T, mb + MW_NDYES);
-                                for (int j = 0; j < nd; ++j)
-                                    adj_add(A.Gx, wi(T, mb + MW_PC + j),
-                                            c * wf(T, P.off_kap + (m * P.kap_stride + j) * P.N + L.lam));
-                            }
-                        }
-                    } else {
-                        lds_count(tally, so.status == 2 ? FPT_T_SPLAT_RR_KILL : FPT_T_SPLAT_MISS);
-                    }
-                }
-            }
-        }
-        pend = PEND_NONE;
-
-        // ---- path end
-        if (alive && exit_code >= 0) {
-            alive = false;
-            lds_count(tally, FPT_T_EXIT0 + exit_code);
-            if constexpr (REC) {
-                fpt_path_record rc;
-                rc.n_vertices = L.v + (exit_code == FPT_EXIT_TRUNC ? 0u : 1u);
-                rc.n_scatter = L.nsc;
-                rc.n_emit = L.nem;
-                rc.exit_code = (uint32_t)exit_code;
-                rc.lambda = L.lam;
-                rc.comp = L.comp;
-                rc.region = L.region;
-                rc.pad = 0;
-                rc.pos[0] = L.x[0]; rc.pos[1] = L.x[1]; rc.pos[2] = L.x[2];
-                rc.dir[0] = L.w[0]; rc.dir[1] = L.w[1]; rc.dir[2] = L.w[2];
-                rc.splat_sum = L.splat_sum;
-                rc.pad2 = 0.f;
-                const uint32_t k = L.pid - P.path_begin;
-                B.rec[k] = rc;
-                if constexpr (ADJ) {
-                    if (B.rec_grad) {
-#pragma unroll
-                        for (int i = 0; i < kMaxNP; ++i)
-                            if (i < P.np) B.rec_grad[(size_t)k * P.np + i] = G[i] + A.Gx[i * 64];
-                    }
-#pragma unroll
-                    for (int i = 0; i < kMaxNP; ++i) {
-                        G[i] = 0.f;
-                        A.Gx[i * 64] = 0.f;
-                    }
-                }
-            }
-        }
+        advance<GEOM, MODE>(P, B, C, W, A, G);
     }
 
     // ---- flush counters: per-lane -> wave -> block LDS -> global
     {
-        uint32_t a = cnt.vertices, b = cnt.scatters, c = cnt.splat_hit;
+        uint32_t a = W.cnt.vertices, b = W.cnt.scatters, c = W.cnt.splat_hit;
         for (int off = 32; off > 0; off >>= 1) {
             a += __shfl_xor(a, off);
             b += __shfl_xor(b, off);
@@ -952,6 +1043,187 @@ __global__ void __launch_bounds__(256) k_transport(const KParams P, const KBuffe
         }
         if (v) atomicAdd(&B.tallies[threadIdx.x], (unsigned long long)v);
     }
+}
+
+// -------------------------------------------------------------------------
+// Batched form: many independent escape-sensor instances in one persistent
+// launch.  Each wave owns an LDS slot holding its current instance's launch
+// parameters, event tally, escape histogram and tables; it claims (instance,
+// path range) items from a device queue, prefetching the next item so that
+// ranges of the same instance merge without draining the lanes; a new instance
+// is staged only once every lane has finished, and the slot's histogram and
+// tally are flushed to that instance's global counters.
+constexpr int kParamWords = ((int)sizeof(KParams) + 15) / 16 * 4;
+
+DEV void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    asm volatile("" ::: "memory");
+}
+
+DEV void batch_flush(const KBatch& Bt, int inst, uint32_t* tally, uint32_t* hist, Counters& cnt,
+                     uint32_t lane) {
+    uint32_t a = cnt.vertices, b = cnt.scatters, c = cnt.splat_hit;
+    for (int off = 32; off > 0; off >>= 1) {
+        a += __shfl_xor(a, off);
+        b += __shfl_xor(b, off);
+        c += __shfl_xor(c, off);
+    }
+    cnt = {0u, 0u, 0u};
+    if (lane == 0) {
+        tally[FPT_T_VERTICES] += a;
+        tally[FPT_T_SCATTERS] += b;
+        tally[FPT_T_SPLAT_HIT] += c;
+    }
+    wave_sync();
+    uint32_t* dst = Bt.counts + (size_t)inst * Bt.hist_words;
+    for (int i = lane; i < Bt.hist_words; i += 64)
+        if (hist[i]) atomicAdd(&dst[i], hist[i]);
+    if (Bt.tallies && lane < FPT_N_TALLIES) {
+        uint32_t v = tally[lane];
+        if (lane == FPT_T_PATHS) {
+            v = 0u;
+            for (int e = 0; e < 10; ++e) v += tally[FPT_T_EXIT0 + e];
+        }
+        if (v) atomicAdd(&Bt.tallies[(size_t)inst * FPT_N_TALLIES + lane], (unsigned long long)v);
+    }
+    wave_sync();
+}
+
+__global__ void __launch_bounds__(256) k_batch(const KBatch Bt) {
+    extern __shared__ uint32_t smem[];
+    const int wave = threadIdx.x >> 6;
+    const uint32_t lane = lane_id();
+    uint32_t* slot = smem + (size_t)wave * Bt.slot_words;
+    const KParams& P = *reinterpret_cast<const KParams*>(slot);
+    uint32_t* tally = slot + kParamWords;
+    uint32_t* hist = tally + 32;
+    uint32_t* table = hist + ((Bt.hist_words + 3) & ~3);
+    WaveCtx C;
+    C.T = table;
+    C.SP = nullptr;
+    C.tally = tally;
+    C.hist = hist;
+    C.lds_hist = true;
+    C.pinhole = false;
+    C.lane = lane;
+    WalkState W;
+    W.cnt = {0u, 0u, 0u};
+    W.L.pid = 0;
+    W.alive = false;
+    W.pend = PEND_NONE;
+    W.nrm[0] = W.nrm[1] = W.nrm[2] = 0.f;
+    W.rrb = 0;
+    AdjView A;
+    A.S = nullptr;
+    A.Gx = nullptr;
+    float G[1] = {0.f};
+    KBuffers Bd;
+    Bd.tables = nullptr;
+    Bd.film = nullptr;
+    Bd.counts = nullptr;
+    Bd.tallies = nullptr;
+    Bd.counter = nullptr;
+    Bd.gfilm = nullptr;
+    Bd.partials = nullptr;
+    Bd.rec = nullptr;
+    Bd.rec_grad = nullptr;
+    int cur = -1, pending = -1;
+    bool done = false;
+    uint32_t lo = 0, hi = 0;
+    for (;;) {
+        if (lo >= hi) {
+            if (pending < 0 && !done) {
+                unsigned long long it = 0;
+                if (lane == 0) it = atomicAdd(Bt.item_counter, 1ull);
+                it = __shfl(it, 0);
+                if (it < (unsigned long long)Bt.n_items) pending = (int)it;
+                else done = true;
+            }
+            if (pending >= 0) {
+                const KWorkItem item = Bt.items[pending];
+                if ((int)item.instance == cur) {
+                    lo = item.path_lo;
+                    hi = item.path_hi;
+                    pending = -1;
+                } else if (__ballot(W.alive) == 0ull) {
+                    if (cur >= 0) batch_flush(Bt, cur, tally, hist, W.cnt, lane);
+                    // stage the new instance: parameters, zeroed counters, tables
+                    const uint32_t* src = reinterpret_cast<const uint32_t*>(Bt.params + item.instance);
+                    for (int i = lane; i < (int)(sizeof(KParams) / 4); i += 64) slot[i] = src[i];
+                    for (int i = lane; i < 32; i += 64) tally[i] = 0u;
+                    for (int i = lane; i < Bt.hist_words; i += 64) hist[i] = 0u;
+                    const uint32_t* tsrc = Bt.tables + Bt.table_off[item.instance];
+                    const int tw = Bt.params[item.instance].table_words;
+                    for (int i = lane; i < tw; i += 64) table[i] = tsrc[i];
+                    wave_sync();
+                    cur = (int)item.instance;
+                    lo = item.path_lo;
+                    hi = item.path_hi;
+                    pending = -1;
+                }
+            }
+        }
+        W.fresh = false;
+        if (lo < hi) {
+            const uint64_t dead = __ballot(!W.alive);
+            const int ndead = __popcll(dead);
+            if (ndead >= P.refill_lanes || ndead == 64) {
+                const uint32_t base = lo;
+                lo = min(hi, lo + (uint32_t)ndead);
+                if (!W.alive) {
+                    const uint32_t idx = base + mbcnt(dead);
+                    if (idx < hi) {
+                        if (P.geometry == FPT_GEOM_SLAB)
+                            start_path<FPT_GEOM_SLAB, MODE_FWD>(P, C, W, A, P.path_begin + idx);
+                        else
+                            start_path<FPT_GEOM_SPHERE, MODE_FWD>(P, C, W, A, P.path_begin + idx);
+                    }
+                }
+            }
+        }
+        if (__ballot(W.alive) == 0ull) {
+            if (done && pending < 0 && lo >= hi) break;
+            continue;
+        }
+        if (P.geometry == FPT_GEOM_SLAB) advance<FPT_GEOM_SLAB, MODE_FWD>(P, Bd, C, W, A, G);
+        else advance<FPT_GEOM_SPHERE, MODE_FWD>(P, Bd, C, W, A, G);
+    }
+    if (cur >= 0) batch_flush(Bt, cur, tally, hist, W.cnt, lane);
+}
+
+// films[i] += counts[i] * wscale[instance of i]
+__global__ void k_finalize_batch(const uint32_t* counts, float* films, const float* wscale,
+                                 int hist_words, size_t n) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const uint32_t c = counts[i];
+        if (c) films[i] += (float)c * wscale[i / hist_words];
+    }
+}
+
+size_t batch_lds_bytes(const KBatch& Bt, int block) { return (size_t)(block / 64) * Bt.slot_words * 4; }
+
+int batch_slot_words(int hist_words, int max_table_words) {
+    return kParamWords + 32 + ((hist_words + 3) & ~3) + ((max_table_words + 3) & ~3);
+}
+
+hipError_t batch_occupancy(const KBatch& Bt, int block, int* n) {
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, reinterpret_cast<const void*>(&k_batch), block,
+                                                        batch_lds_bytes(Bt, block));
+}
+
+hipError_t launch_batch(const KBatch& Bt, int grid, int block, hipStream_t s) {
+    hipLaunchKernelGGL(k_batch, dim3(grid), dim3(block), batch_lds_bytes(Bt, block), s, Bt);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize_batch(const uint32_t* counts, float* films, const float* wscale,
+                                 int hist_words, size_t n, hipStream_t s) {
+    if (!n) return hipSuccess;
+    const int grid = (int)std::min<size_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_finalize_batch, dim3(grid), dim3(256), 0, s, counts, films, wscale, hist_words, n);
+    return hipGetLastError();
 }
 
 // -------------------------------------------------------------------------

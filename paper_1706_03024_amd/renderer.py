@@ -168,3 +168,64 @@ def render(scene_desc: dict, run: dict):
     finally:
         torch.cuda.synchronize()
         sc.close()
+
+
+class Batch:
+    """Batched form (fpt_batch_create): many escape-sensor slab/sphere instances
+    rendered by one persistent launch replayed from a hipGraph."""
+
+    def __init__(self, scenes, runs, tune=None):
+        n = len(scenes)
+        if n != len(runs) or n == 0:
+            raise ValueError("scenes and runs must be non-empty and of equal length")
+        self.scenes = scenes
+        self.runs = runs
+        self.n = n
+        self.n_bins = scenes[0]["grid"]["n_bins"]
+        self._descs = (_abi.SceneDesc * n)(*[_abi.scene_desc(s) for s in scenes])
+        self._runs = (_abi.Run * n)(*[_abi.run_struct(r) for r in runs])
+        t = None
+        if tune is not None:
+            t = _abi.Tune(tune.get("block_threads", 0), tune.get("blocks_per_cu", 0),
+                          tune.get("refill_lanes", 0), tune.get("chunk_paths", 0),
+                          tune.get("block_min_vertices", 0))
+        h = C.c_void_p()
+        check(lib().fpt_batch_create(self._descs, self._runs, n, None if t is None else C.byref(t),
+                                     C.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().fpt_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    def new_films(self, device="cuda"):
+        return torch.zeros((self.n, 2, 2, self.n_bins), dtype=torch.float32, device=device)
+
+    def render(self, films, tallies=None):
+        _require_cuda(films, torch.float32, "films")
+        if films.numel() != self.n * 4 * self.n_bins:
+            raise ValueError("films has the wrong size")
+        if tallies is not None:
+            _require_cuda(tallies, torch.int64, "tallies")
+            if tallies.numel() != self.n * _abi.N_TALLIES:
+                raise ValueError("tallies has the wrong size")
+        check(lib().fpt_batch_render(self._h, _ptr(films), _ptr(tallies), _stream()))
+        return films
+
+    def count_vertices(self):
+        films = self.new_films()
+        t = new_tallies(self.n)
+        self.render(films, t)
+        torch.cuda.synchronize()
+        return int(t[:, 1].sum().item())
