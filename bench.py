@@ -152,6 +152,47 @@ def cpu_baseline(scene, run, target_s=12.0):
                       f"({verts} vertices, {dt:.1f} s, fp64, 1 thread)"}
 
 
+COPY_BYTES = 256 << 20
+
+
+def profile_run(name, steps):
+    """Kernels for a profiler: a plain device copy of COPY_BYTES (reads and
+    writes that many bytes; calibrates FETCH_SIZE / WRITE_SIZE) and `steps`
+    renders of one workload."""
+    import torch
+    import paper_1706_03024_amd as fpt
+    import workloads
+    a = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    if name == "batched":
+        scenes, runs = workloads.batch_config()
+        bt = fpt.Batch(scenes, runs)
+        films = bt.new_films()
+        for _ in range(steps):
+            bt.render(films)
+        torch.cuda.synchronize()
+        bt.close()
+        print(f"profiled {steps} batched renders", flush=True)
+        return
+    scene, run = {"cornell": workloads.cornell_config, "large": workloads.large_config,
+                  "slab": workloads.slab_config,
+                  "adjoint": lambda: workloads.adjoint_config()[:2]}[name]()
+    if name == "slab":
+        run = dict(run, path_count=1 << 22, total_paths=1 << 22)
+    sc = fpt.Scene(scene)
+    film = sc.new_film()
+    g = torch.ones_like(film) if name == "adjoint" else None
+    for _ in range(steps):
+        sc.render(run, film=film)
+        if g is not None:
+            sc.render_adjoint(run, g)
+    torch.cuda.synchronize()
+    sc.close()
+    print(f"profiled {steps} {name} renders", flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -161,6 +202,9 @@ def main():
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--only-headline", action="store_true",
                     help="time only the headline render (for profiler runs)")
+    ap.add_argument("--profile", choices=["cornell", "large", "slab", "batched", "adjoint"],
+                    help="profiler run: one 256 MiB device copy (traffic calibration) and "
+                         "--steps renders of the named workload, nothing else")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
@@ -170,6 +214,9 @@ def main():
     import torch
     import workloads
     torch.cuda.set_device(int(os.environ.get("LOCAL_RANK", 0)))
+    if args.profile:
+        profile_run(args.profile, args.steps)
+        return
     scene, run = workloads.cornell_config()
     head = forward_form(scene, run, args.steps, args.warmup)
     if args.only_headline:

@@ -188,7 +188,7 @@ typedef struct {
     int32_t blocks_per_cu;  /* persistent blocks per compute unit */
     int32_t refill_lanes;   /* a wave refills dead lanes once this many are dead (1..64) */
     int32_t chunk_paths;    /* batched: paths per work item */
-    int32_t block_min_vertices; /* paths this long walk in wave-wide blocks (default 48) */
+    int32_t block_min_vertices; /* paths this long walk in wave-wide blocks (default 16) */
 } fpt_tune;
 
 /* Per-path replay record (fp32 path state at exit). */

@@ -509,7 +509,7 @@ void fill_run(const fpt_scene* sc, const fpt_run* run, uint32_t B, KParams* P) {
     // escape films up to 8192 counters use a per-block LDS histogram
     const int64_t hw = sc->desc.sensor == FPT_SENSOR_ESCAPE ? film_elems(sc->desc, B) : 0;
     P->hist_words = hw <= 8192 ? (int)hw : 0;
-    P->block_min_v = sc->tune.block_min_vertices > 0 ? (uint32_t)sc->tune.block_min_vertices : 48u;
+    P->block_min_v = sc->tune.block_min_vertices > 0 ? (uint32_t)sc->tune.block_min_vertices : 16u;
 }
 
 int32_t ensure_scratch(fpt_scene* sc, size_t counts, size_t partials) {
@@ -609,7 +609,7 @@ int32_t batch_build_items(fpt_batch* bt) {
         HIP_TRY(hipMemcpy(bt->d_items, items.data(), items.size() * sizeof(KWorkItem), hipMemcpyHostToDevice),
                 "upload items");
     const int refill = bt->tune.refill_lanes > 0 ? std::min(64, bt->tune.refill_lanes) : 16;
-    const uint32_t bmin = bt->tune.block_min_vertices > 0 ? (uint32_t)bt->tune.block_min_vertices : 48u;
+    const uint32_t bmin = bt->tune.block_min_vertices > 0 ? (uint32_t)bt->tune.block_min_vertices : 16u;
     for (KParams& p : bt->params) {
         p.refill_lanes = refill;
         p.block_min_v = bmin;

@@ -21,6 +21,7 @@ namespace fpt {
 
 constexpr float kInf = __builtin_inff();
 constexpr uint32_t kMaxPathVertices = 1u << 28;
+constexpr float kTauZero = 110.f;  // exp(-110) = 1.7e-48 rounds to 0 in fp32
 constexpr int kLdsSpheres = 32;                                // word offset of the sphere table
 constexpr int kLdsTable = kLdsSpheres + 8 * FPT_MAX_SPHERES;   // word offset of the table image
 constexpr float kInv4Pi = 0.0795774715459476679f;
@@ -57,6 +58,14 @@ DEV uint4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0
 DEV float u24(uint32_t x) { return (float)(x >> 8) * 5.9604644775390625e-08f; }
 DEV uint32_t rr_bits(const uint4 r) {
     return ((r.x & 0xFFu) << 16) | ((r.y & 0xFFu) << 8) | (r.z & 0xFFu);
+}
+
+// Hardware square root (about 1 ulp) and sin/cos of 2 pi u: v_sin_f32 and
+// v_cos_f32 take their argument in revolutions.
+DEV float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+DEV void sincos_rev(float u, float* s, float* c) {
+    *s = __builtin_amdgcn_sinf(u);
+    *c = __builtin_amdgcn_cosf(u);
 }
 
 // a / b through the hardware reciprocal (about 1 ulp); b != 0 at every call site.
@@ -120,7 +129,7 @@ DEV float sphere_exit(const float* x, const float* w, const float* c, float r2) 
     const float b = o0 * w[0] + o1 * w[1] + o2 * w[2];
     const float cc = o0 * o0 + o1 * o1 + o2 * o2 - r2;
     const float disc = b * b - cc;
-    return fmaxf(0.f, -b + sqrtf(fmaxf(disc, 0.f)));
+    return fmaxf(0.f, -b + fsqrt(fmaxf(disc, 0.f)));
 }
 
 template <int GEOM>
@@ -188,7 +197,7 @@ DEV Hit next_surface(const KParams& P, const KSphere* SP, const Lane& L, bool sk
             const float cc = o0 * o0 + o1 * o1 + o2 * o2 - sp.r2;
             const float disc = b * b - cc;
             if (!(disc > 0.f)) continue;
-            const float t = fmaxf(-b - sqrtf(disc), 0.f);
+            const float t = fmaxf(-b - fsqrt(disc), 0.f);
             if (t < h.d) { h.d = t; h.ev = EV_ENTER; h.idx = s; }
         }
     }
@@ -220,7 +229,7 @@ DEV float chord_len(const KSphere& sp, const float* x, const float* wc, float di
     const float cc = o0 * o0 + o1 * o1 + o2 * o2 - sp.r2;
     const float disc = b * b - cc;
     if (!(disc > 0.f)) return 0.f;
-    const float sq = sqrtf(disc);
+    const float sq = fsqrt(disc);
     const float lo = fmaxf(-b - sq, 0.f), hi = fminf(-b + sq, dist);
     return fmaxf(hi - lo, 0.f);
 }
@@ -243,7 +252,7 @@ DEV SplatOut splat_eval(const KParams& P, const uint32_t* S, const KSphere* SP, 
     o.status = 1;
     const float d0 = P.eye[0] - L.x[0], d1 = P.eye[1] - L.x[1], d2 = P.eye[2] - L.x[2];
     const float dist2 = d0 * d0 + d1 * d1 + d2 * d2;
-    const float rdist = rsqrtf(dist2);
+    const float rdist = __builtin_amdgcn_rsqf(dist2);
     const float dist = dist2 * rdist;
     const float wc[3] = {d0 * rdist, d1 * rdist, d2 * rdist};
     float f = kInv4Pi;
@@ -293,13 +302,14 @@ DEV SplatOut splat_eval(const KParams& P, const uint32_t* S, const KSphere* SP, 
             }
         }
     }
-    // transmittance along the connection, through every sphere (eq. 6)
+    // transmittance along the connection, through every sphere (eq. 6); past
+    // an optical depth of 110 it is exactly 0 in fp32, so the rest is skipped
     float tau = 0.f;
-    for (int s = 0; s < P.n_spheres; ++s) {
+    for (int s = 0; s < P.n_spheres && tau < kTauZero; ++s) {
         const float len = chord_len(SP[s], L.x, wc, dist);
         if (len > 0.f) tau += wf(S, P.off_st + 2 * (SP[s].medium * P.N + L.lam)) * len;
     }
-    const float tr = __expf(-tau);
+    const float tr = tau < kTauZero ? __expf(-tau) : 0.f;
     const float cosc = zc * rdist;
     float v = P.wscale * f * tr * P.splat_norm * __builtin_amdgcn_rcpf(cosc * cosc * cosc * dist2);
     if (P.splat_rr > 0.f && tr < P.splat_rr) {
@@ -412,8 +422,8 @@ DEV void block_walk(const KParams& P, const KBuffers& B, const uint32_t* T, cons
     const float tk = -__logf(1.f - u0) * Q.inv;
     const bool scat = u1 * Q.st < Q.ss;
     float sp, cp;
-    sincospif(2.f * u3, &sp, &cp);
-    const float ct = 1.f - 2.f * u2, stt = 2.f * sqrtf(u2 * (1.f - u2));
+    sincos_rev(u3, &sp, &cp);
+    const float ct = 1.f - 2.f * u2, stt = 2.f * fsqrt(u2 * (1.f - u2));
     const float wn[3] = {stt * cp, stt * sp, ct};
     // incoming direction of segment k: the new direction of vertex k-1
     float win[3];
@@ -464,7 +474,8 @@ DEV void block_walk(const KParams& P, const KBuffers& B, const uint32_t* T, cons
             if (so.status == 0) {
                 cnt.splat_hit++;
                 dep = so.v;
-                if constexpr (MODE == MODE_FWD) unsafeAtomicAdd(&B.film[so.idx], so.v);
+                if constexpr (MODE == MODE_FWD)
+                    if (so.v != 0.f) unsafeAtomicAdd(&B.film[so.idx], so.v);  // +0 changes nothing
                 if constexpr (ADJ) {
                     const float gv = B.gfilm[so.idx] * so.v;
                     const int mb = P.off_med + Q.medium * kMedWords;
@@ -479,7 +490,7 @@ DEV void block_walk(const KParams& P, const KBuffers& B, const uint32_t* T, cons
                         G[i] += gv * Si;
                     }
                     const float e0 = P.eye[0] - Lk.x[0], e1 = P.eye[1] - Lk.x[1], e2 = P.eye[2] - Lk.x[2];
-                    const float dist = sqrtf(e0 * e0 + e1 * e1 + e2 * e2);
+                    const float dist = fsqrt(e0 * e0 + e1 * e1 + e2 * e2);
                     const float id = __builtin_amdgcn_rcpf(dist);
                     const float wc[3] = {e0 * id, e1 * id, e2 * id};
                     for (int s = 0; s < P.n_spheres; ++s) {
@@ -600,16 +611,16 @@ DEV void start_path(const KParams& P, const WaveCtx& C, WalkState& W, AdjView& A
         const uint4 r1 = philox(L.pid, 0u, 1u, 0u, P.key0, P.key1);
         const float ua = u24(r1.x), ub = u24(r1.y);
         float sp, cp;
-        sincospif(2.f * ub, &sp, &cp);
+        sincos_rev(ub, &sp, &cp);
         if (P.light == FPT_LIGHT_POINT) {
             L.x[0] = P.lpos[0]; L.x[1] = P.lpos[1]; L.x[2] = P.lpos[2];
             const float ct = 1.f - 2.f * ua;
-            const float st = 2.f * sqrtf(ua * (1.f - ua));
+            const float st = 2.f * fsqrt(ua * (1.f - ua));
             L.w[0] = st * cp; L.w[1] = st * sp; L.w[2] = ct;
             L.region = 0;
         } else {
             const float a = u24(r.y), b = u24(r.z);
-            const float sr = sqrtf(ua), cz = sqrtf(1.f - ua);
+            const float sr = fsqrt(ua), cz = fsqrt(1.f - ua);
             const float lx = sr * cp, ly = sr * sp;
 #pragma unroll
             for (int i = 0; i < 3; ++i) {
@@ -718,7 +729,7 @@ DEV void advance(const KParams& P, const KBuffers& B, const WaveCtx& C, WalkStat
                     else if (L.nsc > P.max_scatter) exit_code = FPT_EXIT_SCAP;
                     else {
                         dir_cos = 1.f - 2.f * u2;
-                        dir_sin = 2.f * sqrtf(u2 * (1.f - u2));
+                        dir_sin = 2.f * fsqrt(u2 * (1.f - u2));
                         pend = PEND_MEDIUM;
                     }
                 } else if (s < L.thr_bg || L.ndy == 0) {
@@ -762,7 +773,7 @@ DEV void advance(const KParams& P, const KBuffers& B, const WaveCtx& C, WalkStat
                             L.comp = 1;
                             lds_count(tally, FPT_T_EMISSIONS);
                             dir_cos = 1.f - 2.f * u2;
-                            dir_sin = 2.f * sqrtf(u2 * (1.f - u2));
+                            dir_sin = 2.f * fsqrt(u2 * (1.f - u2));
                             pend = PEND_MEDIUM;
                         }
                     }
@@ -795,8 +806,8 @@ DEV void advance(const KParams& P, const KBuffers& B, const WaveCtx& C, WalkStat
                     } else {
                         // Lambertian reflection about the wall's inward normal
                         lds_count(tally, FPT_T_WALL_REFLECT);
-                        dir_sin = sqrtf(u2);
-                        dir_cos = sqrtf(1.f - u2);
+                        dir_sin = fsqrt(u2);
+                        dir_cos = fsqrt(1.f - u2);
                         frame = h.idx;
                         pend = PEND_SURFACE;
                     }
@@ -820,7 +831,7 @@ DEV void advance(const KParams& P, const KBuffers& B, const WaveCtx& C, WalkStat
             }
             if (pend != PEND_NONE && exit_code < 0) {
                 float sp, cp;
-                sincospif(2.f * u3, &sp, &cp);
+                sincos_rev(u3, &sp, &cp);
                 const float a = dir_sin * cp, b = dir_sin * sp;
                 if (frame < 0) {
                     L.w[0] = a; L.w[1] = b; L.w[2] = dir_cos;
@@ -851,7 +862,8 @@ DEV void advance(const KParams& P, const KBuffers& B, const WaveCtx& C, WalkStat
                 if (so.status == 0) {
                     cnt.splat_hit++;
                     L.splat_sum += so.v;
-                    if constexpr (MODE == MODE_FWD) unsafeAtomicAdd(&B.film[so.idx], so.v);
+                    if constexpr (MODE == MODE_FWD)
+                    if (so.v != 0.f) unsafeAtomicAdd(&B.film[so.idx], so.v);  // +0 changes nothing
                     if constexpr (ADJ) {
                         const float g = B.gfilm[so.idx];
                         const float gv = g * so.v;
@@ -860,7 +872,7 @@ DEV void advance(const KParams& P, const KBuffers& B, const WaveCtx& C, WalkStat
                             if (i < P.np) G[i] += gv * A.S[i * 64];
                         // d v / d theta = -v sum_s chord_s d sigma_t(m_s) / d theta
                         const float e0 = P.eye[0] - L.x[0], e1 = P.eye[1] - L.x[1], e2 = P.eye[2] - L.x[2];
-                        const float dist = sqrtf(e0 * e0 + e1 * e1 + e2 * e2);
+                        const float dist = fsqrt(e0 * e0 + e1 * e1 + e2 * e2);
                         const float id = __builtin_amdgcn_rcpf(dist);
                         const float wc[3] = {e0 * id, e1 * id, e2 * id};
                         for (int s = 0; s < P.n_spheres; ++s) {
