@@ -69,9 +69,11 @@ def count_vertices(sc, run):
     return fpt.tallies_dict(t)
 
 
-def forward_form(scene, run, steps, warmup):
+def forward_form(scene, run, steps, warmup, tune_name=None):
     import paper_1706_03024_amd as fpt
+    from paper_1706_03024_amd import autotune
     sc = fpt.Scene(scene)
+    tune = autotune.autotune(tune_name, scene=sc, run=run) if tune_name else None
     film = sc.new_film()
     tal = count_vertices(sc, run)
     ms, ev_ms = time_renders(sc, run, steps, warmup, film)
@@ -80,7 +82,8 @@ def forward_form(scene, run, steps, warmup):
     fl = flops_model(tal, nsph, geo)
     sc.close()
     return {"vertices": tal["vertices"], "ms_per_step": ms, "kernel_ms": ev_ms,
-            "vertices_per_s": tal["vertices"] / (ms / 1e3), "flops": fl, "tallies": tal}
+            "vertices_per_s": tal["vertices"] / (ms / 1e3), "flops": fl, "tallies": tal,
+            "tune": tune}
 
 
 def adjoint_form(steps, warmup):
@@ -116,8 +119,12 @@ def batched_form(steps, warmup):
     import workloads
     if not hasattr(fpt, "Batch"):
         return None
+    from paper_1706_03024_amd import autotune
     scenes, runs = workloads.batch_config()
     b = fpt.Batch(scenes, runs)
+    tune = autotune.autotune("batched-1024", batch=b)
+    b.close()
+    b = fpt.Batch(scenes, runs, tune={k: v for k, v in tune.items() if k != "ms"})
     films = b.new_films()
     tal = b.count_vertices()
     for _ in range(warmup):
@@ -130,7 +137,7 @@ def batched_form(steps, warmup):
     ms = (time.perf_counter() - t0) / steps * 1e3
     b.close()
     return {"vertices": tal, "ms_per_step": ms, "vertices_per_s": tal / (ms / 1e3),
-            "instances": len(scenes)}
+            "instances": len(scenes), "tune": tune}
 
 
 def cpu_baseline(scene, run, target_s=12.0):
@@ -218,7 +225,7 @@ def main():
         profile_run(args.profile, args.steps)
         return
     scene, run = workloads.cornell_config()
-    head = forward_form(scene, run, args.steps, args.warmup)
+    head = forward_form(scene, run, args.steps, args.warmup, tune_name="cornell-128-64spp")
     if args.only_headline:
         print(json.dumps({"headline": head}, default=float), flush=True)
         return
@@ -239,7 +246,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "cornell box, 3 Gaussian dye spheres, 128x128 pinhole, 64 spp "
                                "(2^20 light paths), 101 bins, fwd",
-                   "paths": run["path_count"], "vertices_per_step": head["vertices"]},
+                   "paths": run["path_count"], "vertices_per_step": head["vertices"],
+                   "launch": head["tune"]},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS, "traffic": None,
                      "kernel": "fpt::k_transport<BOX, FWD>",
@@ -254,7 +262,7 @@ def main():
         extra["fwd_large"]["fp32_frac"] = big["flops"] / (big["kernel_ms"] / 1e3) / 1e12 / FP32_PEAK_TFLOPS
         s1, r1 = workloads.slab_config()
         r1 = dict(r1, path_count=1 << 22, total_paths=1 << 22)
-        sl = forward_form(s1, r1, max(5, args.steps // 5), 2)
+        sl = forward_form(s1, r1, max(5, args.steps // 5), 2, tune_name="slab-2^22")
         extra["fwd_slab_2^22"] = {k: sl[k] for k in ("vertices", "ms_per_step", "vertices_per_s")}
         extra["fwd_slab_2^22"]["fp32_frac"] = sl["flops"] / (sl["kernel_ms"] / 1e3) / 1e12 / FP32_PEAK_TFLOPS
         try:

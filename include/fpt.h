@@ -189,6 +189,7 @@ typedef struct {
     int32_t refill_lanes;   /* a wave refills dead lanes once this many are dead (1..64) */
     int32_t chunk_paths;    /* batched: paths per work item */
     int32_t block_min_vertices; /* paths this long walk in wave-wide blocks (default 16) */
+    int32_t block_segments; /* long paths per block round: 1, 2 or 4 (default 4 with a camera, else 1) */
 } fpt_tune;
 
 /* Per-path replay record (fp32 path state at exit). */

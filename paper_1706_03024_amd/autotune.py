@@ -17,7 +17,8 @@ from . import _abi
 from ._abi import check, lib
 
 DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_cache.json")
-FIELDS = ("block_threads", "blocks_per_cu", "refill_lanes", "chunk_paths", "block_min_vertices")
+FIELDS = ("block_threads", "blocks_per_cu", "refill_lanes", "chunk_paths", "block_min_vertices",
+          "block_segments")
 
 
 def _key(name):

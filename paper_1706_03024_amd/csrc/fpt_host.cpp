@@ -510,6 +510,8 @@ void fill_run(const fpt_scene* sc, const fpt_run* run, uint32_t B, KParams* P) {
     const int64_t hw = sc->desc.sensor == FPT_SENSOR_ESCAPE ? film_elems(sc->desc, B) : 0;
     P->hist_words = hw <= 8192 ? (int)hw : 0;
     P->block_min_v = sc->tune.block_min_vertices > 0 ? (uint32_t)sc->tune.block_min_vertices : 16u;
+    P->max_segments = sc->tune.block_segments > 0 ? sc->tune.block_segments
+                                                  : (sc->desc.sensor == FPT_SENSOR_PINHOLE ? 4 : 1);
 }
 
 int32_t ensure_scratch(fpt_scene* sc, size_t counts, size_t partials) {
@@ -609,10 +611,12 @@ int32_t batch_build_items(fpt_batch* bt) {
         HIP_TRY(hipMemcpy(bt->d_items, items.data(), items.size() * sizeof(KWorkItem), hipMemcpyHostToDevice),
                 "upload items");
     const int refill = bt->tune.refill_lanes > 0 ? std::min(64, bt->tune.refill_lanes) : 16;
-    const uint32_t bmin = bt->tune.block_min_vertices > 0 ? (uint32_t)bt->tune.block_min_vertices : 16u;
+    const uint32_t bmin = bt->tune.block_min_vertices > 0 ? (uint32_t)bt->tune.block_min_vertices : 64u;
+    const int segs = bt->tune.block_segments > 0 ? bt->tune.block_segments : 1;
     for (KParams& p : bt->params) {
         p.refill_lanes = refill;
         p.block_min_v = bmin;
+        p.max_segments = segs;
     }
     HIP_TRY(hipMemcpy(bt->d_params, bt->params.data(), sizeof(KParams) * bt->n, hipMemcpyHostToDevice),
             "upload params");
@@ -750,6 +754,9 @@ int32_t fpt_scene_set_tune(fpt_scene* sc, const fpt_tune* tune) {
         return set_err(FPT_E_RANGE, "block_threads must be 64..256 in steps of 64");
     if (tune->refill_lanes < 0 || tune->refill_lanes > 64) return set_err(FPT_E_RANGE, "refill_lanes 0..64");
     if (tune->blocks_per_cu < 0) return set_err(FPT_E_RANGE, "blocks_per_cu >= 0");
+    if (tune->block_segments != 0 && tune->block_segments != 1 && tune->block_segments != 2 &&
+        tune->block_segments != 4)
+        return set_err(FPT_E_RANGE, "block_segments must be 0, 1, 2 or 4");
     sc->tune = *tune;
     return FPT_OK;
 }
@@ -1007,17 +1014,19 @@ int32_t fpt_autotune(fpt_scene* sc, const fpt_run* run, fpt_batch* bt, fpt_tune*
     std::vector<fpt_tune> cand;
     const int blocks[2] = {128, 256};
     const int refills[3] = {8, 16, 32};
-    const int bmins[4] = {16, 32, 64, 128};
+    const int bmins[4] = {8, 16, 32, 64};
     const int chunks[3] = {1024, 4096, 16384};
     for (int b : blocks)
         for (int r : refills)
             for (int m : bmins) {
                 if (sc) {
-                    fpt_tune t = {b, 0, r, 0, m};
-                    cand.push_back(t);
+                    for (int g : {1, 4}) {
+                        fpt_tune t = {b, 0, r, 0, m, g};
+                        cand.push_back(t);
+                    }
                 } else {
                     for (int c : chunks) {
-                        fpt_tune t = {b, 0, r, c, m};
+                        fpt_tune t = {b, 0, r, c, m, 1};
                         cand.push_back(t);
                     }
                 }

@@ -21,6 +21,7 @@ namespace fpt {
 
 constexpr float kInf = __builtin_inff();
 constexpr uint32_t kMaxPathVertices = 1u << 28;
+constexpr int kBlockPasses = 4;   // block passes per iteration for paths that never stop
 constexpr float kTauZero = 110.f;  // exp(-110) = 1.7e-48 rounds to 0 in fp32
 constexpr int kLdsSpheres = 32;                                // word offset of the sphere table
 constexpr int kLdsTable = kLdsSpheres + 8 * FPT_MAX_SPHERES;   // word offset of the table image
@@ -358,14 +359,15 @@ DEV void score_length(const KParams& P, const uint32_t* T, const Lane& L, AdjVie
 }
 
 // -------------------------------------------------------------------------
-// Wave-cooperative walk of one long path.  Inside a homogeneous medium at a
-// fixed wavelength the flight lengths, event choices and new directions of the
-// next vertices depend only on their random counters, not on the position; so
-// lane k draws vertex v+1+k, a wave prefix sum of the segment vectors gives the
-// positions, and a ballot finds the first vertex that leaves the medium or is
-// not a scatter.  The scatter vertices before it are committed (and splat) in
-// parallel; that vertex itself is left to the ordinary step.  The arithmetic
-// depends only on the path's state, so results do not depend on scheduling.
+// Wave-cooperative walk of long paths.  Inside a homogeneous medium at a fixed
+// wavelength the flight lengths, event choices and new directions of the next
+// vertices depend only on their random counters, not on the position; so lane
+// k of a segment draws vertex v+1+k of the segment's path, a segmented prefix
+// sum of the segment vectors gives the positions, and a ballot finds the first
+// vertex that leaves the medium or is not a scatter.  The scatter vertices
+// before it are committed (and splat) in parallel; that vertex itself is left
+// to the ordinary step.  A round serves one path with 64 lanes, two with 32 or
+// four with 16.  The result depends on the path's state and the segment width.
 DEV float rl(float x, int j) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), j)); }
 DEV int rli(int x, int j) { return __builtin_amdgcn_readlane(x, j); }
 DEV uint32_t rlu(uint32_t x, int j) { return (uint32_t)__builtin_amdgcn_readlane((int)x, j); }
@@ -387,36 +389,77 @@ DEV float medium_exit(const KParams& P, const float* x, const float* w, const fl
 
 template <int GEOM, int MODE>
 DEV void block_walk(const KParams& P, const KBuffers& B, const uint32_t* T, const KSphere* SP,
-                    uint32_t* tally, Lane& L, int j, uint32_t lane, bool pinhole, Counters& cnt,
-                    float* Sw, float* Gxl, float* G) {
+                    uint32_t* tally, Lane& L, uint64_t& elig, uint32_t lane, bool pinhole,
+                    Counters& cnt, float* Sw, float* Gxl, float* G, bool& full) {
     constexpr bool ADJ = (MODE == MODE_ADJ || MODE == MODE_REC_ADJ);
     constexpr bool REC = (MODE == MODE_REC || MODE == MODE_REC_ADJ);
-    // the owner's state, uniform across the wave
-    Lane Q;
+    // segment width: one path per 64 lanes, two per 32, or four per 16
+    const int ne = __popcll(elig);
+    const int W = (ne >= 3 && P.max_segments >= 4) ? 16 : ((ne >= 2 && P.max_segments >= 2) ? 32 : 64);
+    const int nseg = 64 / W;
+    int own[4] = {-1, -1, -1, -1};
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        Q.x[c] = rl(L.x[c], j);
-        Q.w[c] = rl(L.w[c], j);
-        Q.sc[c] = rl(L.sc[c], j);
+    for (int g = 0; g < 4; ++g) {
+        if (g < nseg && elig) {
+            own[g] = __ffsll((unsigned long long)elig) - 1;
+            elig &= elig - 1ull;
+        }
     }
-    Q.sr2 = rl(L.sr2, j);
-    Q.st = rl(L.st, j);
-    Q.inv = rl(L.inv, j);
-    Q.ss = rl(L.ss, j);
-    Q.thr_bg = rl(L.thr_bg, j);
-    Q.ndy = rli(L.ndy, j);
-    Q.lam = rli(L.lam, j);
-    Q.region = rli(L.region, j);
-    Q.medium = rli(L.medium, j);
-    Q.comp = rli(L.comp, j);
-    Q.pid = rlu(L.pid, j);
-    Q.v = rlu(L.v, j);
-    Q.nsc = rlu(L.nsc, j);
-    Q.nem = rlu(L.nem, j);
-    Q.batch = rlu(L.batch, j);
+    const int seg = (int)lane / W;
+    const uint32_t pos = lane % (uint32_t)W;
+    const int j = seg == 0 ? own[0] : (seg == 1 ? own[1] : (seg == 2 ? own[2] : own[3]));
+    const bool active = j >= 0;
+    const int js = active ? j : 0;
+    // the segment owner's state: uniform (scalar) when one path takes the whole wave
+    Lane Q;
+    if (W == 64) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            Q.x[c] = rl(L.x[c], js);
+            Q.w[c] = rl(L.w[c], js);
+            Q.sc[c] = rl(L.sc[c], js);
+        }
+        Q.sr2 = rl(L.sr2, js);
+        Q.st = rl(L.st, js);
+        Q.inv = rl(L.inv, js);
+        Q.ss = rl(L.ss, js);
+        Q.thr_bg = rl(L.thr_bg, js);
+        Q.ndy = rli(L.ndy, js);
+        Q.lam = rli(L.lam, js);
+        Q.region = rli(L.region, js);
+        Q.medium = rli(L.medium, js);
+        Q.comp = rli(L.comp, js);
+        Q.pid = rlu(L.pid, js);
+        Q.v = rlu(L.v, js);
+        Q.nsc = rlu(L.nsc, js);
+        Q.nem = rlu(L.nem, js);
+        Q.batch = rlu(L.batch, js);
+    } else {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            Q.x[c] = __shfl(L.x[c], js);
+            Q.w[c] = __shfl(L.w[c], js);
+            Q.sc[c] = __shfl(L.sc[c], js);
+        }
+        Q.sr2 = __shfl(L.sr2, js);
+        Q.st = __shfl(L.st, js);
+        Q.inv = __shfl(L.inv, js);
+        Q.ss = __shfl(L.ss, js);
+        Q.thr_bg = __shfl(L.thr_bg, js);
+        Q.ndy = __shfl(L.ndy, js);
+        Q.lam = __shfl(L.lam, js);
+        Q.region = __shfl(L.region, js);
+        Q.medium = __shfl(L.medium, js);
+        Q.comp = __shfl(L.comp, js);
+        Q.pid = (uint32_t)__shfl((int)L.pid, js);
+        Q.v = (uint32_t)__shfl((int)L.v, js);
+        Q.nsc = (uint32_t)__shfl((int)L.nsc, js);
+        Q.nem = (uint32_t)__shfl((int)L.nem, js);
+        Q.batch = (uint32_t)__shfl((int)L.batch, js);
+    }
     Q.splat_sum = 0.f;
 
-    const uint32_t vk = Q.v + 1u + lane;
+    const uint32_t vk = Q.v + 1u + pos;
     const uint4 r = philox(Q.pid, vk, 0u, 0u, P.key0, P.key1);
     const float u0 = u24(r.x), u1 = u24(r.y), u2 = u24(r.z), u3 = u24(r.w);
     const float tk = -__logf(1.f - u0) * Q.inv;
@@ -429,31 +472,45 @@ DEV void block_walk(const KParams& P, const KBuffers& B, const uint32_t* T, cons
     float win[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        const float up = __shfl_up(wn[c], 1);
-        win[c] = lane == 0 ? Q.w[c] : up;
+        const float up = __shfl_up(wn[c], 1, W);
+        win[c] = pos == 0 ? Q.w[c] : up;
     }
-    const float seg[3] = {tk * win[0], tk * win[1], tk * win[2]};
-    float s0 = seg[0], s1 = seg[1], s2 = seg[2], tt = tk;
+    const float seg3[3] = {tk * win[0], tk * win[1], tk * win[2]};
+    // positions are built from 16-vertex chunks: an inclusive scan within the
+    // chunk, then the chunk totals chained in order, exactly as consecutive
+    // 16-wide rounds would add them, so every segment width gives the same bits
+    float s0 = seg3[0], s1 = seg3[1], s2 = seg3[2], tt = tk;
 #pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const float y0 = __shfl_up(s0, d), y1 = __shfl_up(s1, d), y2 = __shfl_up(s2, d);
-        const float yt = __shfl_up(tt, d);
-        if (lane >= (uint32_t)d) { s0 += y0; s1 += y1; s2 += y2; tt += yt; }
+    for (int d = 1; d < 16; d <<= 1) {
+        const float y0 = __shfl_up(s0, d, 16), y1 = __shfl_up(s1, d, 16), y2 = __shfl_up(s2, d, 16);
+        const float yt = __shfl_up(tt, d, 16);
+        if ((pos & 15u) >= (uint32_t)d) { s0 += y0; s1 += y1; s2 += y2; tt += yt; }
     }
+    float b0 = Q.x[0], b1 = Q.x[1], b2 = Q.x[2], bt = 0.f;
+    const int chunk = (int)(pos >> 4);
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc) {
+        const int srcl = seg * W + cc * 16 + 15;
+        const float t0 = __shfl(s0, srcl), t1 = __shfl(s1, srcl), t2 = __shfl(s2, srcl);
+        const float t3 = __shfl(tt, srcl);
+        if (cc < chunk) { b0 += t0; b1 += t1; b2 += t2; bt += t3; }
+    }
+    tt += bt;
     // segment k starts at p_k and, if it stays in the medium, ends at q_k
-    const float pk[3] = {Q.x[0] + (s0 - seg[0]), Q.x[1] + (s1 - seg[1]), Q.x[2] + (s2 - seg[2])};
+    const float pk[3] = {b0 + (s0 - seg3[0]), b1 + (s1 - seg3[1]), b2 + (s2 - seg3[2])};
     const float dif = medium_exit<GEOM>(P, pk, win, Q.sc, Q.sr2);
-    bool stop = !(tk < dif) || !scat || (Q.nsc + lane + 1u > P.max_scatter) ||
+    bool stop = !active || !(tk < dif) || !scat || (Q.nsc + pos + 1u > P.max_scatter) ||
                 (vk >= kMaxPathVertices);
     if (REC && P.max_vertices && vk >= P.max_vertices) stop = true;
     const uint64_t sm = __ballot(stop);
-    const int kstar = sm ? (__ffsll((unsigned long long)sm) - 1) : 64;
-    if (kstar == 0) return;
-    const bool mine = (int)lane < kstar;
+    const uint64_t segmask = W == 64 ? ~0ull : ((1ull << W) - 1ull);
+    const uint64_t mybits = (sm >> (seg * W)) & segmask;
+    const int kstar = mybits ? (__ffsll((unsigned long long)mybits) - 1) : W;
+    const bool mine = active && (int)pos < kstar;
     Lane Lk = Q;
-    Lk.x[0] = Q.x[0] + s0;
-    Lk.x[1] = Q.x[1] + s1;
-    Lk.x[2] = Q.x[2] + s2;
+    Lk.x[0] = b0 + s0;
+    Lk.x[1] = b1 + s1;
+    Lk.x[2] = b2 + s2;
     float dep = 0.f;
     if (mine) {
         cnt.vertices++;
@@ -482,8 +539,8 @@ DEV void block_walk(const KParams& P, const KBuffers& B, const uint32_t* T, cons
 #pragma unroll
                     for (int i = 0; i < kMaxNP; ++i) {
                         if (i >= P.np) continue;
-                        float Si = Sw[i * 64 + j];
-                        if (i == pss) Si += (float)(lane + 1) * inv_ss - tt;
+                        float Si = Sw[i * 64 + js];
+                        if (i == pss) Si += (float)(pos + 1) * inv_ss - tt;
                         for (int q = 0; q < Q.ndy; ++q)
                             if (i == wi(T, mb + MW_PC + q))
                                 Si -= wf(T, P.off_kap + (Q.medium * P.kap_stride + q) * P.N + Q.lam) * tt;
@@ -511,28 +568,43 @@ DEV void block_walk(const KParams& P, const KBuffers& B, const uint32_t* T, cons
             }
         }
     }
-    if constexpr (REC) {
-        float dsum = dep;
+    // every owner takes the state after its segment's vertex k*-1
+    int myseg = -1;
 #pragma unroll
-        for (int off = 32; off > 0; off >>= 1) dsum += __shfl_xor(dsum, off);
-        if ((int)lane == j) L.splat_sum += dsum;
+    for (int g = 0; g < 4; ++g)
+        if ((int)lane == own[g]) myseg = g;
+    const int ks_of = [&] {
+        // k* of segment `myseg`, from the uniform ballot
+        if (myseg < 0) return 0;
+        const uint64_t bits = (sm >> (myseg * W)) & segmask;
+        return bits ? (__ffsll((unsigned long long)bits) - 1) : W;
+    }();
+    const int src = myseg < 0 ? 0 : myseg * W + (ks_of > 0 ? ks_of - 1 : 0);
+    const float nx0 = __shfl(Lk.x[0], src), nx1 = __shfl(Lk.x[1], src), nx2 = __shfl(Lk.x[2], src);
+    const float nw0 = __shfl(wn[0], src), nw1 = __shfl(wn[1], src), nw2 = __shfl(wn[2], src);
+    const float tsum = __shfl(tt, src);
+    float dsum = 0.f;
+    if constexpr (REC) {
+        dsum = dep;
+        for (int off = W >> 1; off > 0; off >>= 1) dsum += __shfl_xor(dsum, off, W);
+        dsum = __shfl(dsum, myseg < 0 ? 0 : myseg * W);
     }
-    // the owner takes the state after vertex k*-1
-    const int kl = kstar - 1;
-    const float nx0 = rl(Lk.x[0], kl), nx1 = rl(Lk.x[1], kl), nx2 = rl(Lk.x[2], kl);
-    const float nw0 = rl(wn[0], kl), nw1 = rl(wn[1], kl), nw2 = rl(wn[2], kl);
-    const float tsum = rl(tt, kl);
-    if ((int)lane == j) {
+    // a path that committed the whole width without stopping continues with
+    // another round instead of an ordinary step, whatever the width was
+    if (myseg >= 0) full = ks_of == W;
+    if (myseg >= 0 && ks_of > 0) {
         L.x[0] = nx0; L.x[1] = nx1; L.x[2] = nx2;
         L.w[0] = nw0; L.w[1] = nw1; L.w[2] = nw2;
-        L.v += (uint32_t)kstar;
-        L.nsc += (uint32_t)kstar;
+        L.v += (uint32_t)ks_of;
+        L.nsc += (uint32_t)ks_of;
+        if constexpr (REC) L.splat_sum += dsum;
         if constexpr (ADJ) {
-            const int mb = P.off_med + Q.medium * kMedWords;
-            Sw[pss * 64 + j] += (float)kstar * inv_ss - tsum;
-            for (int q = 0; q < Q.ndy; ++q)
-                Sw[wi(T, mb + MW_PC + q) * 64 + j] -=
-                    wf(T, P.off_kap + (Q.medium * P.kap_stride + q) * P.N + Q.lam) * tsum;
+            const int mb = P.off_med + L.medium * kMedWords;
+            const int mpss = wi(T, mb + MW_PSS);
+            Sw[mpss * 64 + lane] += (float)ks_of * wf(T, mb + MW_INV_SS) - tsum;
+            for (int q = 0; q < L.ndy; ++q)
+                Sw[wi(T, mb + MW_PC + q) * 64 + lane] -=
+                    wf(T, P.off_kap + (L.medium * P.kap_stride + q) * P.N + L.lam) * tsum;
         }
     }
 }
@@ -677,21 +749,25 @@ DEV void advance(const KParams& P, const KBuffers& B, const WaveCtx& C, WalkStat
     (void)tally;
     (void)lane;
     // ---- long paths: wave-cooperative blocks of up to 64 vertices each
+    bool full = false;
     if constexpr (MODE != MODE_REC_ADJ) {
-        uint64_t elig = __ballot(alive && !fresh && L.v >= P.block_min_v && L.medium >= 0 &&
-                                 L.st > 0.f && (P.exc_scatter || L.nem > 0u));
-        while (elig) {
-            const int j = __ffsll((unsigned long long)elig) - 1;
-            elig &= elig - 1ull;
-            block_walk<GEOM, MODE>(P, B, T, SP, tally, L, j, lane, pinhole, cnt,
-                                   ADJ ? A.S - lane : nullptr, ADJ ? A.Gx : nullptr, G);
+        // paths whose last block ran its full width without stopping go again,
+        // up to kBlockPasses passes per iteration
+        for (int pass = 0; pass < kBlockPasses; ++pass) {
+            uint64_t elig = __ballot(alive && !fresh && L.v >= P.block_min_v && L.medium >= 0 &&
+                                     L.st > 0.f && (P.exc_scatter || L.nem > 0u) &&
+                                     (pass == 0 || full));
+            if (!elig) break;
+            while (elig)  // each round takes up to four long paths off `elig`
+                block_walk<GEOM, MODE>(P, B, T, SP, tally, L, elig, lane, pinhole, cnt,
+                                       ADJ ? A.S - lane : nullptr, ADJ ? A.Gx : nullptr, G, full);
         }
     }
 
     // ---- one segment of the walk for every live lane with no pending splat
     int ev = EV_NONE;
     int exit_code = -1;
-    if (alive && !(fresh && pend != PEND_NONE)) {
+    if (alive && !(fresh && pend != PEND_NONE) && !full) {
         L.v++;
         if (REC && P.max_vertices && L.v >= P.max_vertices) {
             exit_code = FPT_EXIT_TRUNC;

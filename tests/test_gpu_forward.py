@@ -281,3 +281,33 @@ def test_splat_roulette_and_fluorescence_only():
     g, _ = _render(scene, workloads.make_run(1 << 21, seed=13, parity_batches=B, splat_rr=0.05))
     o = oracle.render(scene, workloads.make_run(1 << 18, seed=14, parity_batches=B))["film"]
     check_z(batch_z(g, o), "roulette film vs plain oracle film", dof=B - 1)
+
+
+@pytest.mark.parametrize("scene_name", ["slab", "box"])
+def test_block_rounds_are_width_independent(scene_name):
+    """Long paths walk in wave blocks of 64, 32 or 16 lanes depending on how
+    many share a wave; the arithmetic is defined in 16-vertex chunks, so every
+    launch shape and segment count gives bit-identical integer tallies."""
+    import torch
+    fpt = _fpt()
+    if scene_name == "slab":
+        scene, run = workloads.slab_config()
+        run = dict(run, path_count=1 << 18, total_paths=1 << 18)
+    else:
+        scene = workloads.cornell_scene(8, 8)
+        scene["sensor"] = {"kind": "escape"}
+        run = workloads.make_run(1 << 18, seed=3)
+    sc = fpt.Scene(scene)
+    outs = []
+    for tune in ({"block_segments": 1}, {"block_segments": 4},
+                 {"block_segments": 2, "block_threads": 64, "refill_lanes": 1},
+                 {"block_segments": 4, "block_threads": 128, "refill_lanes": 40}):
+        sc.set_tune(**tune)
+        t = fpt.new_tallies()
+        f = sc.render(run, tallies=t)
+        torch.cuda.synchronize()
+        outs.append((f.clone(), t.clone()))
+    sc.close()
+    for f, t in outs[1:]:
+        assert torch.equal(t, outs[0][1])
+        assert torch.equal(f, outs[0][0])
