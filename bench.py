@@ -160,6 +160,31 @@ def cpu_baseline(scene, run, target_s=12.0):
 
 
 COPY_BYTES = 256 << 20
+TRAFFIC_JSON = os.path.join(ROOT, "profiles", "traffic.json")
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("fpt_kernels.hip", "fpt_internal.h"):
+        with open(os.path.join(ROOT, "paper_1706_03024_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload):
+    """HBM bytes per launch of the transport kernel from the recorded
+    FETCH_SIZE / WRITE_SIZE counter runs, or None when the kernel source has
+    changed since they were taken."""
+    try:
+        with open(TRAFFIC_JSON) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_source") != kernel_source_hash():
+        return None
+    w = rec.get("workloads", {}).get(workload)
+    return None if w is None else w["bytes_per_launch"]
 
 
 def profile_run(name, steps):
@@ -173,9 +198,15 @@ def profile_run(name, steps):
     b = torch.empty_like(a)
     b.copy_(a)
     torch.cuda.synchronize()
+    from paper_1706_03024_amd import autotune
     if name == "batched":
         scenes, runs = workloads.batch_config()
         bt = fpt.Batch(scenes, runs)
+        tune = autotune.autotune("batched-1024", batch=bt, measure=False)
+        print(f"launch shape: {tune} (device {autotune.device_tag()})", flush=True)
+        if tune is not None:
+            bt.close()
+            bt = fpt.Batch(scenes, runs, tune={k: v for k, v in tune.items() if k != "ms"})
         films = bt.new_films()
         for _ in range(steps):
             bt.render(films)
@@ -189,6 +220,10 @@ def profile_run(name, steps):
     if name == "slab":
         run = dict(run, path_count=1 << 22, total_paths=1 << 22)
     sc = fpt.Scene(scene)
+    tune_name = {"cornell": "cornell-128-64spp", "slab": "slab-2^22"}.get(name)
+    if tune_name:
+        print(f"launch shape: {autotune.autotune(tune_name, scene=sc, run=run, measure=False)} "
+              f"(device {autotune.device_tag()})", flush=True)
     film = sc.new_film()
     g = torch.ones_like(film) if name == "adjoint" else None
     for _ in range(steps):
@@ -249,7 +284,8 @@ def main():
                    "paths": run["path_count"], "vertices_per_step": head["vertices"],
                    "launch": head["tune"]},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / FP32_PEAK_TFLOPS,
+                     "traffic": measured_traffic("cornell"),
                      "kernel": "fpt::k_transport<BOX, FWD>",
                      "kernel_ms": head["kernel_ms"],
                      "flops_per_launch": head["flops"]},

@@ -3,7 +3,7 @@
 fpt_autotune times candidate shapes (block size, refill threshold, wave-block
 trigger, and for batches the work-item size) on the device and returns the
 fastest; results never depend on the shape.  The cache is keyed by the
-workload's name and the device name.
+workload's name and the device's architecture and compute-unit count.
 """
 from __future__ import annotations
 
@@ -21,8 +21,15 @@ FIELDS = ("block_threads", "blocks_per_cu", "refill_lanes", "chunk_paths", "bloc
           "block_segments")
 
 
+def device_tag():
+    """Architecture and compute-unit count of the current device (the
+    marketing name is not always reported, e.g. under a profiler)."""
+    p = torch.cuda.get_device_properties(torch.cuda.current_device())
+    return f"{p.gcnArchName.split(':')[0]}x{p.multi_processor_count}cu"
+
+
 def _key(name):
-    return f"{name}@{torch.cuda.get_device_name()}"
+    return f"{name}@{device_tag()}"
 
 
 def _load(path):
@@ -33,13 +40,17 @@ def _load(path):
         return {}
 
 
-def autotune(name, scene=None, run=None, batch=None, cache_path=DEFAULT_CACHE, force=False):
-    """Returns the tune dict for `name`, measuring it if the cache lacks it, and
+def autotune(name, scene=None, run=None, batch=None, cache_path=DEFAULT_CACHE, force=False,
+             measure=True):
+    """Returns the tune dict for `name`, measuring it if the cache lacks it
+    (unless measure=False: then the library defaults, returned as None), and
     applies it to `scene` (plain render) or returns it for a new Batch."""
     cache = _load(cache_path)
     key = _key(name)
     if key in cache and not force:
         best = cache[key]
+    elif not measure:
+        return None
     else:
         out = _abi.Tune()
         ms = C.c_float()
