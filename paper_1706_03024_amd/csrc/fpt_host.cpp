@@ -24,6 +24,7 @@ hipError_t launch_zero_u32(uint32_t* p, size_t n, hipStream_t s);
 hipError_t launch_zero_u64(unsigned long long* p, size_t n, hipStream_t s);
 hipError_t launch_finalize_counts(const uint32_t* counts, float* film, size_t n, float scale,
                                   hipStream_t s);
+hipError_t launch_splat_jobs(const KParams& P, const KBuffers& B, int grid, hipStream_t s);
 hipError_t launch_reduce_partials(const float* partials, int nblocks, int np, float* grad,
                                   hipStream_t s);
 int batch_slot_words(int hist_words, int max_table_words);
@@ -124,6 +125,9 @@ struct fpt_scene {
     unsigned long long* d_tally = nullptr;  // scratch tallies when the caller passes none
     float* d_partials = nullptr;
     size_t partials_cap = 0;
+    uint32_t* d_sjobs = nullptr;  // deferred pinhole connections, kSjobSlice entries per wave
+    size_t sjob_waves = 0;        // waves d_sjobs has slices for
+    uint32_t* d_sjob_counts = nullptr;
     fpt_tune tune;
     std::vector<float> h_st, h_cdf, h_rho;
     std::vector<int> h_line_bin;
@@ -410,11 +414,26 @@ int32_t build_tables(fpt_scene* sc) {
         P.hi[a] = (float)d.box_hi[a];
     }
     P.open_face = d.open_face;
+    if (d.geometry == FPT_GEOM_BOX) {
+        const int ax = d.open_face >> 1;
+        const int a1 = ax == 2 ? 0 : ax + 1, a2 = ax == 0 ? 2 : ax - 1;
+        for (int c = 0; c < 3; ++c) {
+            P.vis_e[0][c] = c == ax ? 1.f : 0.f;
+            P.vis_e[1][c] = c == a1 ? 1.f : 0.f;
+            P.vis_e[2][c] = c == a2 ? 1.f : 0.f;
+        }
+        P.vis_plane = (d.open_face & 1) ? P.hi[ax] : P.lo[ax];
+        P.vis_lo1 = P.lo[a1];
+        P.vis_hi1 = P.hi[a1];
+        P.vis_lo2 = P.lo[a2];
+        P.vis_hi2 = P.hi[a2];
+    }
     P.n_spheres = d.geometry == FPT_GEOM_BOX ? d.n_spheres : 0;
     for (int s = 0; s < P.n_spheres; ++s) {
         for (int a = 0; a < 3; ++a) P.spheres[s].c[a] = (float)d.spheres[s].center[a];
         P.spheres[s].r2 = (float)(d.spheres[s].radius * d.spheres[s].radius);
         P.spheres[s].medium = d.spheres[s].medium;
+        P.spheres[s].st_row = P.off_st + 2 * d.spheres[s].medium * N;
     }
     double dir[3] = {d.light_dir[0], d.light_dir[1], d.light_dir[2]};
     if (d.light == FPT_LIGHT_BEAM) norm3(dir);
@@ -497,6 +516,9 @@ void fill_run(const fpt_scene* sc, const fpt_run* run, uint32_t B, KParams* P) {
     P->path_begin = (uint32_t)run->path_begin;
     P->path_count = (uint32_t)std::min<uint64_t>(run->path_count, 0xFFFFFFFFull);
     P->batches = B;
+    // film element indices below 2^32 - 1: deposits merge per wave
+    P->film_u32 = sc->desc.sensor == FPT_SENSOR_PINHOLE &&
+                  (int64_t)B * 2 * sc->desc.height * (int64_t)sc->desc.width * sc->desc.n_bins < 0xFFFFFFFFll;
     P->wscale = (float)((double)B / (double)run->total_paths);
     P->max_scatter = run->max_scatter;
     P->max_emissions = run->max_emissions;
@@ -533,6 +555,9 @@ int32_t ensure_scratch(fpt_scene* sc, size_t counts, size_t partials) {
     }
     return FPT_OK;
 }
+
+// Deferred-connection entries per transport wave (20 bytes each).
+constexpr uint32_t kSjobSlice = 2048;
 
 // Grid for a persistent launch: fill every CU at the kernel's occupancy, but
 // never more lanes than paths.
@@ -701,6 +726,8 @@ void fpt_scene_destroy(fpt_scene* sc) {
     if (sc->d_counter) (void)hipFree(sc->d_counter);
     if (sc->d_tally) (void)hipFree(sc->d_tally);
     if (sc->d_partials) (void)hipFree(sc->d_partials);
+    if (sc->d_sjobs) (void)hipFree(sc->d_sjobs);
+    if (sc->d_sjob_counts) (void)hipFree(sc->d_sjob_counts);
     delete sc;
 }
 
@@ -793,9 +820,27 @@ int32_t fpt_render(fpt_scene* sc, const fpt_run* run, float* film, uint64_t* tal
     Bf.counts = sc->d_counts;
     Bf.tallies = tallies ? reinterpret_cast<unsigned long long*>(tallies) : nullptr;
     Bf.counter = sc->d_counter;
+    const bool defer = sc->desc.sensor == FPT_SENSOR_PINHOLE;
+    const size_t waves = (size_t)grid * (block / 64);
+    if (defer) {
+        if (waves > sc->sjob_waves) {
+            if (sc->d_sjobs) (void)hipFree(sc->d_sjobs);
+            if (sc->d_sjob_counts) (void)hipFree(sc->d_sjob_counts);
+            sc->d_sjobs = nullptr;
+            sc->d_sjob_counts = nullptr;
+            sc->sjob_waves = 0;
+            HIP_TRY(hipMalloc(&sc->d_sjobs, waves * 5 * kSjobSlice * 4), "hipMalloc(deferred splats)");
+            HIP_TRY(hipMalloc(&sc->d_sjob_counts, waves * 4), "hipMalloc(deferred splat counts)");
+            sc->sjob_waves = waves;
+        }
+        Bf.sjobs = sc->d_sjobs;
+        Bf.sjob_counts = sc->d_sjob_counts;
+        Bf.sjob_slice = kSjobSlice;
+    }
     HIP_TRY(launch_zero_u64(sc->d_counter, 1, s), "zero queue");
     if (escape) HIP_TRY(launch_zero_u32(sc->d_counts, n_counts, s), "zero counts");
     HIP_TRY(launch_transport(P, Bf, MODE_FWD, grid, block, s), "transport launch");
+    if (defer) HIP_TRY(launch_splat_jobs(P, Bf, (int)waves, s), "deferred splats");
     if (escape) HIP_TRY(launch_finalize_counts(sc->d_counts, film, n_counts, P.wscale, s), "finalize");
     return FPT_OK;
 }

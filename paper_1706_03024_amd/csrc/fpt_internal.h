@@ -24,7 +24,8 @@ struct KSphere {
     float c[3];
     float r2;
     int medium;
-    int pad[3];
+    int st_row;  // word offset of the medium's (sigma_t, 1/sigma_t) row in the table image
+    int pad[2];
 };
 
 // Everything a launch needs that is uniform across the grid (kernel argument).
@@ -49,12 +50,17 @@ struct KParams {
     float bc[3], br2;
     float lo[3], hi[3];
     int open_face;
+    // the open face's plane: unit vectors of its axis and of the two others
+    // (one-hot), the plane's coordinate and the face's extent along the others
+    float vis_e[3][3];
+    float vis_plane, vis_lo1, vis_hi1, vis_lo2, vis_hi2;
     float lpos[3], ldir[3], lu[3], lv[3], ln[3], lt1[3], lt2[3];
     float lu_inv2, lv_inv2;
     float eye[3], cf[3], cr[3], cu[3];
     float inv_tanx, inv_tany;
     int W, H;
     float splat_norm;  // N_pix / A_img
+    int film_u32;      // film element indices fit 32 bits (deposits merge per wave)
     // run
     uint32_t key0, key1;
     uint32_t path_begin, path_count;
@@ -81,6 +87,9 @@ struct KBuffers {
     float* partials;               // adjoint: [grid blocks][kMaxNP]
     fpt_path_record* rec;          // records mode
     float* rec_grad;               // records mode, [path_count][np]
+    uint32_t* sjobs;               // deferred pinhole connections: per wave [5][sjob_slice] words, or null
+    uint32_t* sjob_counts;         // entries written per wave
+    uint32_t sjob_slice;
 };
 
 // Batched form: one work item = a path range of one instance.

@@ -229,11 +229,11 @@ DEV float chord_len(const KSphere& sp, const float* x, const float* wc, float di
     const float b = o0 * wc[0] + o1 * wc[1] + o2 * wc[2];
     const float cc = o0 * o0 + o1 * o1 + o2 * o2 - sp.r2;
     const float disc = b * b - cc;
-    if (!(disc > 0.f)) return 0.f;
-    const float sq = fsqrt(disc);
+    const float sq = fsqrt(fmaxf(disc, 0.f));
     const float lo = fmaxf(-b - sq, 0.f), hi = fminf(-b + sq, dist);
-    return fmaxf(hi - lo, 0.f);
+    return disc > 0.f ? fmaxf(hi - lo, 0.f) : 0.f;
 }
+
 
 // -------------------------------------------------------------------------
 // Pinhole splat at a realised vertex (eqs. 3-6).  Returns the deposited value
@@ -245,86 +245,72 @@ struct SplatOut {
     int status;  // 0 hit, 1 miss, 2 roulette kill
 };
 
-DEV SplatOut splat_eval(const KParams& P, const uint32_t* S, const KSphere* SP, const Lane& L,
-                        int pend, const float* nrm, uint32_t rrb) {
-    SplatOut o;
-    o.v = 0.f;
-    o.idx = -1;
-    o.status = 1;
-    const float d0 = P.eye[0] - L.x[0], d1 = P.eye[1] - L.x[1], d2 = P.eye[2] - L.x[2];
-    const float dist2 = d0 * d0 + d1 * d1 + d2 * d2;
+DEV SplatOut splat_eval(const KParams& P, const uint32_t* S, const KSphere* SP, const float* x, int lam,
+                        int comp, uint32_t batch, int pend, const float* nrm, uint32_t rrb) {
+    // Every test is evaluated and folded into `ok`, so the lanes of a wave stay
+    // together; a rejected connection deposits nothing.
+    const float d[3] = {P.eye[0] - x[0], P.eye[1] - x[1], P.eye[2] - x[2]};
+    const float dist2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
     const float rdist = __builtin_amdgcn_rsqf(dist2);
     const float dist = dist2 * rdist;
-    const float wc[3] = {d0 * rdist, d1 * rdist, d2 * rdist};
-    float f = kInv4Pi;
-    if (pend != PEND_MEDIUM) {
-        const float cs = dot3(nrm, wc);
-        if (!(cs > 0.f)) return o;
-        f = cs * kInvPi;
-    }
-    const float zc = -(d0 * P.cf[0] + d1 * P.cf[1] + d2 * P.cf[2]);
-    if (!(zc > 0.f)) return o;
+    const float wc[3] = {d[0] * rdist, d[1] * rdist, d[2] * rdist};
+    const bool surf = pend != PEND_MEDIUM;
+    const float cs = dot3(nrm, wc);
+    const float f = surf ? cs * kInvPi : kInv4Pi;
+    bool ok = !surf || cs > 0.f;
+    // pinhole projection
+    const float zc = -(d[0] * P.cf[0] + d[1] * P.cf[1] + d[2] * P.cf[2]);
+    ok = ok && zc > 0.f;
     const float izc = __builtin_amdgcn_rcpf(zc);
-    const float xi = -(d0 * P.cr[0] + d1 * P.cr[1] + d2 * P.cr[2]) * izc * P.inv_tanx;
-    const float yi = -(d0 * P.cu[0] + d1 * P.cu[1] + d2 * P.cu[2]) * izc * P.inv_tany;
+    const float xi = -(d[0] * P.cr[0] + d[1] * P.cr[1] + d[2] * P.cr[2]) * izc * P.inv_tanx;
+    const float yi = -(d[0] * P.cu[0] + d[1] * P.cu[1] + d[2] * P.cu[2]) * izc * P.inv_tany;
     const float fx = (xi + 1.f) * 0.5f * (float)P.W;
     const float fy = (1.f - yi) * 0.5f * (float)P.H;
-    if (!(fx >= 0.f && fx < (float)P.W && fy >= 0.f && fy < (float)P.H)) return o;
-    const int px = min((int)fx, P.W - 1), py = min((int)fy, P.H - 1);
+    ok = ok && fx >= 0.f && fx < (float)P.W && fy >= 0.f && fy < (float)P.H;
     // visibility: the segment from x (inside the box) to the eye (outside,
     // beyond the open face's plane) must cross that plane inside the face
     {
-        const int ax = P.open_face >> 1;
-        const float plane = (P.open_face & 1) ? P.hi[ax] : P.lo[ax];
-        const float xa = ax == 0 ? L.x[0] : (ax == 1 ? L.x[1] : L.x[2]);
-        const float da = ax == 0 ? d0 : (ax == 1 ? d1 : d2);
-        if (da == 0.f) return o;
-        const float t = fdiv(plane - xa, da);
-        if (!(t > 0.f && t < 1.f)) return o;
-        const int a1 = ax == 2 ? 0 : ax + 1, a2 = ax == 0 ? 2 : ax - 1;
-        const float q1 = (a1 == 0 ? L.x[0] : (a1 == 1 ? L.x[1] : L.x[2])) +
-                         t * (a1 == 0 ? d0 : (a1 == 1 ? d1 : d2));
-        const float q2 = (a2 == 0 ? L.x[0] : (a2 == 1 ? L.x[1] : L.x[2])) +
-                         t * (a2 == 0 ? d0 : (a2 == 1 ? d1 : d2));
-        if (!(q1 >= P.lo[a1] && q1 <= P.hi[a1] && q2 >= P.lo[a2] && q2 <= P.hi[a2])) return o;
-        if (pend != PEND_SOURCE) {
-            const float dn = P.ln[0] * d0 + P.ln[1] * d1 + P.ln[2] * d2;
-            if (dn != 0.f) {
-                const float pc0 = P.lpos[0] - L.x[0], pc1 = P.lpos[1] - L.x[1], pc2 = P.lpos[2] - L.x[2];
-                const float t = fdiv(P.ln[0] * pc0 + P.ln[1] * pc1 + P.ln[2] * pc2, dn);
-                if (t > 0.f && t < 1.f) {
-                    const float q0 = L.x[0] + t * d0 - P.lpos[0];
-                    const float q1 = L.x[1] + t * d1 - P.lpos[1];
-                    const float q2 = L.x[2] + t * d2 - P.lpos[2];
-                    const float a = (q0 * P.lu[0] + q1 * P.lu[1] + q2 * P.lu[2]) * P.lu_inv2;
-                    const float b = (q0 * P.lv[0] + q1 * P.lv[1] + q2 * P.lv[2]) * P.lv_inv2;
-                    if (a >= 0.f && a <= 1.f && b >= 0.f && b <= 1.f) return o;
-                }
-            }
-        }
+        // one-hot axis vectors: the dot products pick coordinates exactly
+        const float xa = dot3(P.vis_e[0], x), da = dot3(P.vis_e[0], d);
+        const float t = fdiv(P.vis_plane - xa, da);
+        ok = ok && da != 0.f && t > 0.f && t < 1.f;
+        const float q1 = dot3(P.vis_e[1], x) + t * dot3(P.vis_e[1], d);
+        const float q2 = dot3(P.vis_e[2], x) + t * dot3(P.vis_e[2], d);
+        ok = ok && q1 >= P.vis_lo1 && q1 <= P.vis_hi1 && q2 >= P.vis_lo2 && q2 <= P.vis_hi2;
     }
-    // transmittance along the connection, through every sphere (eq. 6); past
-    // an optical depth of 110 it is exactly 0 in fp32, so the rest is skipped
+    // and must not pass through the (opaque) light quad, unless x is on it
+    if (pend != PEND_SOURCE) {
+        const float dn = P.ln[0] * d[0] + P.ln[1] * d[1] + P.ln[2] * d[2];
+        const float pc0 = P.lpos[0] - x[0], pc1 = P.lpos[1] - x[1], pc2 = P.lpos[2] - x[2];
+        const float t = fdiv(P.ln[0] * pc0 + P.ln[1] * pc1 + P.ln[2] * pc2, dn);
+        const float q0 = x[0] + t * d[0] - P.lpos[0];
+        const float q1 = x[1] + t * d[1] - P.lpos[1];
+        const float q2 = x[2] + t * d[2] - P.lpos[2];
+        const float a = (q0 * P.lu[0] + q1 * P.lu[1] + q2 * P.lu[2]) * P.lu_inv2;
+        const float b = (q0 * P.lv[0] + q1 * P.lv[1] + q2 * P.lv[2]) * P.lv_inv2;
+        const bool blocked = dn != 0.f && t > 0.f && t < 1.f && a >= 0.f && a <= 1.f && b >= 0.f && b <= 1.f;
+        ok = ok && !blocked;
+    }
+    // transmittance along the connection, through every sphere (eq. 6); past an
+    // optical depth of 110 it is exactly 0 in fp32
     float tau = 0.f;
-    for (int s = 0; s < P.n_spheres && tau < kTauZero; ++s) {
-        const float len = chord_len(SP[s], L.x, wc, dist);
-        if (len > 0.f) tau += wf(S, P.off_st + 2 * (SP[s].medium * P.N + L.lam)) * len;
-    }
+#pragma unroll
+    for (int s = 0; s < FPT_MAX_SPHERES; ++s)
+        if (s < P.n_spheres) tau += wf(S, SP[s].st_row + 2 * lam) * chord_len(SP[s], x, wc, dist);
     const float tr = tau < kTauZero ? __expf(-tau) : 0.f;
     const float cosc = zc * rdist;
     float v = P.wscale * f * tr * P.splat_norm * __builtin_amdgcn_rcpf(cosc * cosc * cosc * dist2);
-    if (P.splat_rr > 0.f && tr < P.splat_rr) {
+    SplatOut o;
+    o.status = ok ? 0 : 1;
+    if (ok && P.splat_rr > 0.f && tr < P.splat_rr) {
         const float q = tr * P.inv_splat_rr;
         const float u = (float)rrb * 5.9604644775390625e-08f;
-        if (!(u < q)) {
-            o.status = 2;
-            return o;
-        }
+        if (!(u < q)) o.status = 2;
         v = fdiv(v, q);
     }
-    o.v = v;
-    o.status = 0;
-    o.idx = ((((long long)L.batch * 2 + L.comp) * P.H + py) * P.W + px) * (long long)P.N + L.lam;
+    o.v = o.status == 0 ? v : 0.f;
+    const int px = min((int)(ok ? fx : 0.f), P.W - 1), py = min((int)(ok ? fy : 0.f), P.H - 1);
+    o.idx = ((long long)((int)batch * 2 + comp) * (P.H * P.W) + (py * P.W + px)) * P.N + lam;
     return o;
 }
 
@@ -334,6 +320,176 @@ struct Counters {
 };
 
 DEV void lds_count(uint32_t* tally, int slot) { atomicAdd(&tally[slot], 1u); }
+
+DEV void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    asm volatile("" ::: "memory");
+}
+
+// -------------------------------------------------------------------------
+// Deferred pinhole splats (forward renders).  A vertex that needs a camera
+// connection is appended to its wave's LDS ring; whenever 64 are queued the
+// wave evaluates them with every lane busy, instead of with only the lanes
+// whose path happened to produce a vertex this step.  The film is a sum, so
+// the order of the deposits is immaterial (up to fp32 rounding of the
+// atomics, which is unordered anyway).  Entry: position, and two packed
+// words: rr bits (24) | pend (2) << 24 | wall face (3) << 26 | component << 29,
+// and wavelength bin | parity batch << 16.  head and count are wave-uniform.
+constexpr int kSqCap = 128;             // entries per wave, a power of two >= 2 * 64
+constexpr int kSqWords = 5 * kSqCap;    // x, y, z, packed a, packed b (structure of arrays)
+
+struct SplatQ {
+    uint32_t* base;  // this wave's ring: [5][kSqCap] words
+    uint32_t* agg;   // this wave's deposit-merging table: kAggWords words
+    int head, count;
+    uint32_t* slice;  // this wave's slice of the deferred-connection buffer, or null
+    int sj_n;         // entries written to it
+};
+
+DEV uint32_t sq_word_a(uint32_t rrb, int pend, int face, int comp) {
+    return (rrb & 0xFFFFFFu) | ((uint32_t)pend << 24) | ((uint32_t)face << 26) | ((uint32_t)comp << 29);
+}
+
+// Appends one entry per lane with `want`; at most 64, so count stays below
+// kSqCap when it was below 64 before.
+DEV void sq_push(SplatQ& q, bool want, const float* x, uint32_t wa, uint32_t wb) {
+    const uint64_t m = __ballot(want);
+    if (want) {
+        const int k = (q.head + q.count + (int)mbcnt(m)) & (kSqCap - 1);
+        q.base[k] = __float_as_uint(x[0]);
+        q.base[kSqCap + k] = __float_as_uint(x[1]);
+        q.base[2 * kSqCap + k] = __float_as_uint(x[2]);
+        q.base[3 * kSqCap + k] = wa;
+        q.base[4 * kSqCap + k] = wb;
+    }
+    q.count += __popcll(m);
+}
+
+// Film deposits of one wave, merged per film element before they go out.
+// Consecutive vertices of a long path deep in a dense medium often project
+// to the same pixel at the same wavelength, and a device atomic instruction
+// whose lanes hit one address is executed lane by lane at the memory side;
+// so the lanes first add their values into a small per-wave LDS hash table
+// keyed by film index (linear probing, at most 64 keys in kAggSlots slots),
+// and each occupied slot then issues one device atomic.  The table is empty
+// (keys kAggEmpty, values 0) between calls.  Film indices must fit 32 bits
+// below kAggEmpty (P.film_u32); larger films go out lane by lane.
+constexpr int kAggSlots = 128;
+constexpr int kAggWords = 2 * kAggSlots;  // keys, then values
+constexpr uint32_t kAggEmpty = 0xFFFFFFFFu;
+
+struct Deposit {
+    bool has;
+    long long idx;
+    float v;
+};
+
+DEV void film_add_merged(const KParams& P, float* film, uint32_t* agg, const Deposit& d, uint32_t lane) {
+    if (!P.film_u32) {
+        if (d.has) unsafeAtomicAdd(&film[d.idx], d.v);
+        return;
+    }
+    uint32_t* keys = agg;
+    float* vals = reinterpret_cast<float*>(agg + kAggSlots);
+    if (d.has) {
+        const uint32_t key = (uint32_t)d.idx;
+        uint32_t h = (key * 0x9E3779B1u) >> 25;  // 7 bits: kAggSlots = 128
+        for (;;) {
+            const uint32_t old = atomicCAS(&keys[h], kAggEmpty, key);
+            if (old == kAggEmpty || old == key) break;
+            h = (h + 1u) & (uint32_t)(kAggSlots - 1);
+        }
+        atomicAdd(&vals[h], d.v);
+    }
+    wave_sync();
+#pragma unroll
+    for (int j = 0; j < kAggSlots / 64; ++j) {
+        const int sl = j * 64 + (int)lane;
+        const uint32_t k = keys[sl];
+        if (k != kAggEmpty) {
+            unsafeAtomicAdd(&film[k], vals[sl]);
+            keys[sl] = kAggEmpty;
+            vals[sl] = 0.f;
+        }
+    }
+    wave_sync();
+}
+
+// One queued connection: decode and evaluate; the deposit is returned.
+DEV Deposit splat_entry(const KParams& P, const uint32_t* T, const KSphere* SP, uint32_t* tally,
+                        Counters& cnt, const float* x, uint32_t wa, uint32_t wb) {
+    const int pend = (int)((wa >> 24) & 3u), face = (int)((wa >> 26) & 7u), comp = (int)((wa >> 29) & 1u);
+    // surface normal: the light's for its own vertex, a wall's inward normal otherwise
+    const int ax = face >> 1;
+    const float sg = (face & 1) ? -1.f : 1.f;
+    float nrm[3];
+    nrm[0] = pend == PEND_SOURCE ? P.ln[0] : (ax == 0 ? sg : 0.f);
+    nrm[1] = pend == PEND_SOURCE ? P.ln[1] : (ax == 1 ? sg : 0.f);
+    nrm[2] = pend == PEND_SOURCE ? P.ln[2] : (ax == 2 ? sg : 0.f);
+    const SplatOut so = splat_eval(P, T, SP, x, (int)(wb & 0xFFFFu), comp, wb >> 16, pend, nrm, wa & 0xFFFFFFu);
+    Deposit d;
+    d.has = so.status == 0 && so.v != 0.f;  // +0 changes nothing
+    d.idx = so.idx;
+    d.v = so.v;
+    if (so.status == 0) cnt.splat_hit++;
+    else lds_count(tally, so.status == 2 ? FPT_T_SPLAT_RR_KILL : FPT_T_SPLAT_MISS);
+    return d;
+}
+
+// Evaluates the oldest n <= 64 entries, lane i taking entry head + i.
+DEV void sq_flush(const KParams& P, float* film, const uint32_t* T, const KSphere* SP, uint32_t* tally,
+                  SplatQ& q, Counters& cnt, uint32_t lane, int n) {
+    wave_sync();
+    Deposit d;
+    d.has = false;
+    d.idx = 0;
+    d.v = 0.f;
+    if ((int)lane < n) {
+        const int k = (q.head + (int)lane) & (kSqCap - 1);
+        const float x[3] = {__uint_as_float(q.base[k]), __uint_as_float(q.base[kSqCap + k]),
+                            __uint_as_float(q.base[2 * kSqCap + k])};
+        d = splat_entry(P, T, SP, tally, cnt, x, q.base[3 * kSqCap + k], q.base[4 * kSqCap + k]);
+    }
+    film_add_merged(P, film, q.agg, d, lane);
+    q.head = (q.head + n) & (kSqCap - 1);
+    q.count -= n;
+    wave_sync();
+}
+
+// Once a wave's path queue is exhausted it only finishes the paths it holds,
+// and the chip empties: from then on its connections go to the wave's own
+// slice of a device buffer (same entry layout, structure of arrays of
+// `sjob_slice` entries per wave; no atomics), which a separate launch
+// evaluates with every lane busy, so the last long paths walk at the walk's
+// own speed.  A full slice falls back to the LDS queue.
+DEV void splat_defer(const KBuffers& B, SplatQ& q, bool want, const float* x, uint32_t wa, uint32_t wb,
+                     bool exhausted) {
+    const uint64_t m = __ballot(want);
+    const int n = __popcll(m);
+    if (exhausted && q.slice && q.sj_n + n <= (int)B.sjob_slice) {
+        if (want) {
+            const uint32_t S = B.sjob_slice;
+            const uint32_t k = (uint32_t)q.sj_n + mbcnt(m);
+            q.slice[k] = __float_as_uint(x[0]);
+            q.slice[S + k] = __float_as_uint(x[1]);
+            q.slice[2 * S + k] = __float_as_uint(x[2]);
+            q.slice[3 * S + k] = wa;
+            q.slice[4 * S + k] = wb;
+        }
+        q.sj_n += n;
+        return;
+    }
+    sq_push(q, want, x, wa, wb);
+}
+
+// Full batches of 64 while there are any; with `all`, the remainder as well.
+DEV void sq_drain(const KParams& P, float* film, const uint32_t* T, const KSphere* SP, uint32_t* tally,
+                  SplatQ& q, Counters& cnt, uint32_t lane, bool all) {
+    while (q.count >= 64 || (all && q.count > 0))
+        sq_flush(P, film, T, SP, tally, q, cnt, lane, q.count < 64 ? q.count : 64);
+}
 
 // -------------------------------------------------------------------------
 // Per-lane adjoint state lives in LDS: the running score S (d log p / d theta
@@ -369,6 +525,17 @@ DEV void score_length(const KParams& P, const uint32_t* T, const Lane& L, AdjVie
 // to the ordinary step.  A round serves one path with 64 lanes, two with 32 or
 // four with 16.  The result depends on the path's state and the segment width.
 DEV float rl(float x, int j) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), j)); }
+// Cross-lane moves on the VALU (DPP) instead of through the LDS crossbar.
+// row_shr:d takes the value of lane i-d within each row of 16 lanes; lanes
+// with no source get -0, the exact identity of fp32 addition.  wave_shr:1
+// takes lane i-1 across the whole wave.
+template <int D>
+DEV float row_shr(float x) {
+    return __int_as_float(__builtin_amdgcn_update_dpp((int)0x80000000, __float_as_int(x), 0x110 + D, 0xf, 0xf, false));
+}
+DEV float wave_shr1(float x) {
+    return __int_as_float(__builtin_amdgcn_update_dpp((int)0x80000000, __float_as_int(x), 0x138, 0xf, 0xf, false));
+}
 DEV int rli(int x, int j) { return __builtin_amdgcn_readlane(x, j); }
 DEV uint32_t rlu(uint32_t x, int j) { return (uint32_t)__builtin_amdgcn_readlane((int)x, j); }
 
@@ -390,7 +557,8 @@ DEV float medium_exit(const KParams& P, const float* x, const float* w, const fl
 template <int GEOM, int MODE>
 DEV void block_walk(const KParams& P, const KBuffers& B, const uint32_t* T, const KSphere* SP,
                     uint32_t* tally, Lane& L, uint64_t& elig, uint32_t lane, bool pinhole,
-                    Counters& cnt, float* Sw, float* Gxl, float* G, bool& full) {
+                    Counters& cnt, float* Sw, float* Gxl, float* G, bool& full, SplatQ& q,
+                    bool exhausted) {
     constexpr bool ADJ = (MODE == MODE_ADJ || MODE == MODE_REC_ADJ);
     constexpr bool REC = (MODE == MODE_REC || MODE == MODE_REC_ADJ);
     // segment width: one path per 64 lanes, two per 32, or four per 16
@@ -472,7 +640,7 @@ DEV void block_walk(const KParams& P, const KBuffers& B, const uint32_t* T, cons
     float win[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        const float up = __shfl_up(wn[c], 1, W);
+        const float up = wave_shr1(wn[c]);
         win[c] = pos == 0 ? Q.w[c] : up;
     }
     const float seg3[3] = {tk * win[0], tk * win[1], tk * win[2]};
@@ -480,20 +648,33 @@ DEV void block_walk(const KParams& P, const KBuffers& B, const uint32_t* T, cons
     // chunk, then the chunk totals chained in order, exactly as consecutive
     // 16-wide rounds would add them, so every segment width gives the same bits
     float s0 = seg3[0], s1 = seg3[1], s2 = seg3[2], tt = tk;
-#pragma unroll
-    for (int d = 1; d < 16; d <<= 1) {
-        const float y0 = __shfl_up(s0, d, 16), y1 = __shfl_up(s1, d, 16), y2 = __shfl_up(s2, d, 16);
-        const float yt = __shfl_up(tt, d, 16);
-        if ((pos & 15u) >= (uint32_t)d) { s0 += y0; s1 += y1; s2 += y2; tt += yt; }
-    }
+#define FPT_SCAN_STEP(D) \
+    s0 += row_shr<D>(s0); s1 += row_shr<D>(s1); s2 += row_shr<D>(s2); tt += row_shr<D>(tt);
+    FPT_SCAN_STEP(1)
+    FPT_SCAN_STEP(2)
+    FPT_SCAN_STEP(4)
+    FPT_SCAN_STEP(8)
+#undef FPT_SCAN_STEP
+    // chunk c of a segment adds the totals of the segment's chunks 0..c-1 in
+    // order; they sit in lanes 15, 31, 47 (one 64-lane segment), 15 and 47
+    // (two 32-lane segments; chunk 1 only) or nowhere (16-lane segments)
     float b0 = Q.x[0], b1 = Q.x[1], b2 = Q.x[2], bt = 0.f;
     const int chunk = (int)(pos >> 4);
-#pragma unroll
-    for (int cc = 0; cc < 3; ++cc) {
-        const int srcl = seg * W + cc * 16 + 15;
-        const float t0 = __shfl(s0, srcl), t1 = __shfl(s1, srcl), t2 = __shfl(s2, srcl);
-        const float t3 = __shfl(tt, srcl);
-        if (cc < chunk) { b0 += t0; b1 += t1; b2 += t2; bt += t3; }
+    if (W >= 32) {
+        const float a15[4] = {rl(s0, 15), rl(s1, 15), rl(s2, 15), rl(tt, 15)};
+        const float a47[4] = {rl(s0, 47), rl(s1, 47), rl(s2, 47), rl(tt, 47)};
+        const bool hi = W == 32 && seg == 1;
+        if (chunk > 0) {
+            b0 += hi ? a47[0] : a15[0];
+            b1 += hi ? a47[1] : a15[1];
+            b2 += hi ? a47[2] : a15[2];
+            bt += hi ? a47[3] : a15[3];
+        }
+        if (W == 64) {
+            const float a31[4] = {rl(s0, 31), rl(s1, 31), rl(s2, 31), rl(tt, 31)};
+            if (chunk > 1) { b0 += a31[0]; b1 += a31[1]; b2 += a31[2]; bt += a31[3]; }
+            if (chunk > 2) { b0 += a47[0]; b1 += a47[1]; b2 += a47[2]; bt += a47[3]; }
+        }
     }
     tt += bt;
     // segment k starts at p_k and, if it stays in the medium, ends at q_k
@@ -524,10 +705,16 @@ DEV void block_walk(const KParams& P, const KBuffers& B, const uint32_t* T, cons
         pss = wi(T, mb + MW_PSS);
         inv_ss = wf(T, mb + MW_INV_SS);
     }
-    if constexpr (GEOM == FPT_GEOM_BOX) {
+    if constexpr (GEOM == FPT_GEOM_BOX && MODE == MODE_FWD) {
+        if (pinhole)
+            splat_defer(B, q, mine && !(P.fluo_only && Q.comp == 0), Lk.x,
+                        sq_word_a(rr_bits(r), PEND_MEDIUM, 0, Q.comp), (uint32_t)Q.lam | (Q.batch << 16),
+                        exhausted);
+    } else if constexpr (GEOM == FPT_GEOM_BOX) {
         if (pinhole && mine && !(P.fluo_only && Q.comp == 0)) {
             const float zero3[3] = {0.f, 0.f, 0.f};
-            const SplatOut so = splat_eval(P, T, SP, Lk, PEND_MEDIUM, zero3, rr_bits(r));
+            const SplatOut so = splat_eval(P, T, SP, Lk.x, Q.lam, Q.comp, Q.batch, PEND_MEDIUM, zero3,
+                                           rr_bits(r));
             if (so.status == 0) {
                 cnt.splat_hit++;
                 dep = so.v;
@@ -580,9 +767,18 @@ DEV void block_walk(const KParams& P, const KBuffers& B, const uint32_t* T, cons
         return bits ? (__ffsll((unsigned long long)bits) - 1) : W;
     }();
     const int src = myseg < 0 ? 0 : myseg * W + (ks_of > 0 ? ks_of - 1 : 0);
-    const float nx0 = __shfl(Lk.x[0], src), nx1 = __shfl(Lk.x[1], src), nx2 = __shfl(Lk.x[2], src);
-    const float nw0 = __shfl(wn[0], src), nw1 = __shfl(wn[1], src), nw2 = __shfl(wn[2], src);
-    const float tsum = __shfl(tt, src);
+    float nx0, nx1, nx2, nw0, nw1, nw2, tsum;
+    if (W == 64) {
+        // one owner: the source lane is uniform
+        const int u = kstar > 0 ? kstar - 1 : 0;
+        nx0 = rl(Lk.x[0], u); nx1 = rl(Lk.x[1], u); nx2 = rl(Lk.x[2], u);
+        nw0 = rl(wn[0], u); nw1 = rl(wn[1], u); nw2 = rl(wn[2], u);
+        tsum = rl(tt, u);
+    } else {
+        nx0 = __shfl(Lk.x[0], src); nx1 = __shfl(Lk.x[1], src); nx2 = __shfl(Lk.x[2], src);
+        nw0 = __shfl(wn[0], src); nw1 = __shfl(wn[1], src); nw2 = __shfl(wn[2], src);
+        tsum = __shfl(tt, src);
+    }
     float dsum = 0.f;
     if constexpr (REC) {
         dsum = dep;
@@ -626,9 +822,11 @@ struct WalkState {
     Lane L;
     bool alive, fresh;
     int pend;
+    int face;  // wall face of a pending surface splat (deferred splats)
     float nrm[3];
     uint32_t rrb;
     Counters cnt;
+    SplatQ q;
 };
 
 // Vertex 0 of path `pid`: the light (eq. 12: light point and excitation
@@ -723,7 +921,8 @@ DEV void start_path(const KParams& P, const WaveCtx& C, WalkState& W, AdjView& A
 // bookkeeping of paths that ended.
 template <int GEOM, int MODE>
 DEV void advance(const KParams& P, const KBuffers& B, const WaveCtx& C, WalkState& W, AdjView& A,
-                 float* G) {
+                 float* G, bool exhausted) {
+    constexpr bool DEFER = (GEOM == FPT_GEOM_BOX && MODE == MODE_FWD);  // queued splats
     constexpr bool ADJ = (MODE == MODE_ADJ || MODE == MODE_REC_ADJ);
     constexpr bool REC = (MODE == MODE_REC || MODE == MODE_REC_ADJ);
     (void)ADJ;
@@ -758,9 +957,12 @@ DEV void advance(const KParams& P, const KBuffers& B, const WaveCtx& C, WalkStat
                                      L.st > 0.f && (P.exc_scatter || L.nem > 0u) &&
                                      (pass == 0 || full));
             if (!elig) break;
-            while (elig)  // each round takes up to four long paths off `elig`
+            while (elig) {  // each round takes up to four long paths off `elig`
                 block_walk<GEOM, MODE>(P, B, T, SP, tally, L, elig, lane, pinhole, cnt,
-                                       ADJ ? A.S - lane : nullptr, ADJ ? A.Gx : nullptr, G, full);
+                                       ADJ ? A.S - lane : nullptr, ADJ ? A.Gx : nullptr, G, full, W.q,
+                                       exhausted);
+                if constexpr (DEFER) sq_drain(P, B.film, T, SP, tally, W.q, cnt, lane, false);
+            }
         }
     }
 
@@ -885,6 +1087,7 @@ DEV void advance(const KParams& P, const KBuffers& B, const WaveCtx& C, WalkStat
                         dir_sin = fsqrt(u2);
                         dir_cos = fsqrt(1.f - u2);
                         frame = h.idx;
+                        W.face = h.idx;
                         pend = PEND_SURFACE;
                     }
                 } else {
@@ -931,10 +1134,15 @@ DEV void advance(const KParams& P, const KBuffers& B, const WaveCtx& C, WalkStat
     }
 
     // ---- convergent splat section
-    if constexpr (GEOM == FPT_GEOM_BOX) {
-        if (pend != PEND_NONE && alive && exit_code < 0) {
+    if constexpr (DEFER) {
+        if (pinhole)
+            splat_defer(B, W.q, pend != PEND_NONE && alive && exit_code < 0 && !(P.fluo_only && L.comp == 0),
+                        L.x, sq_word_a(rrb, pend, W.face, L.comp), (uint32_t)L.lam | (L.batch << 16),
+                        exhausted);
+    } else if constexpr (GEOM == FPT_GEOM_BOX) {
+        if (pinhole && pend != PEND_NONE && alive && exit_code < 0) {
             if (!(P.fluo_only && L.comp == 0)) {
-                const SplatOut so = splat_eval(P, T, SP, L, pend, nrm, rrb);
+                const SplatOut so = splat_eval(P, T, SP, L.x, L.lam, L.comp, L.batch, pend, nrm, rrb);
                 if (so.status == 0) {
                     cnt.splat_hit++;
                     L.splat_sum += so.v;
@@ -1006,6 +1214,11 @@ DEV void advance(const KParams& P, const KBuffers& B, const WaveCtx& C, WalkStat
             }
         }
     }
+    // ---- evaluate queued splats: full batches, and everything once the wave is done
+    if constexpr (DEFER) {
+        if (pinhole)
+            sq_drain(P, B.film, T, SP, tally, W.q, cnt, lane, exhausted && __ballot(alive) == 0ull);
+    }
 }
 
 // -------------------------------------------------------------------------
@@ -1059,8 +1272,23 @@ __global__ void __launch_bounds__(256) k_transport(const KParams P, const KBuffe
     W.L.pid = 0;
     W.alive = false;
     W.pend = PEND_NONE;
+    W.face = 0;
     W.nrm[0] = W.nrm[1] = W.nrm[2] = 0.f;
     W.rrb = 0;
+    constexpr bool DEFER = (GEOM == FPT_GEOM_BOX && MODE == MODE_FWD);
+    W.q.base = smem + kLdsTable + tw + P.hist_words + wave * (kSqWords + kAggWords);  // DEFER only
+    W.q.agg = W.q.base + kSqWords;
+    if constexpr (DEFER) {
+        for (int i = (int)lane; i < kAggSlots; i += 64) {
+            W.q.agg[i] = kAggEmpty;
+            W.q.agg[kAggSlots + i] = 0u;
+        }
+    }
+    W.q.head = 0;
+    W.q.count = 0;
+    const uint32_t gwave = blockIdx.x * (blockDim.x >> 6) + (uint32_t)__builtin_amdgcn_readfirstlane(wave);
+    W.q.slice = (DEFER && B.sjobs) ? B.sjobs + (size_t)gwave * 5 * B.sjob_slice : nullptr;
+    W.q.sj_n = 0;
     bool exhausted = false;
 
     for (;;) {
@@ -1072,22 +1300,33 @@ __global__ void __launch_bounds__(256) k_transport(const KParams P, const KBuffe
             if (ndead >= P.refill_lanes || ndead == 64) {
                 unsigned long long base = 0;
                 if (lane == 0) base = atomicAdd(B.counter, (unsigned long long)ndead);
-                base = __shfl(base, 0);
+                base = ((unsigned long long)(uint32_t)__builtin_amdgcn_readfirstlane((int)(base >> 32)) << 32) |
+                       (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)base);
                 if (base + (unsigned long long)ndead >= (unsigned long long)P.path_count) exhausted = true;
                 if (!W.alive) {
                     const unsigned long long idx = base + mbcnt(dead);
                     if (idx < (unsigned long long)P.path_count)
                         start_path<GEOM, MODE>(P, C, W, A, P.path_begin + (uint32_t)idx);
                 }
+                if constexpr (DEFER) {
+                    // queue the light vertices' splats; the new paths take their first step now
+                    if (C.pinhole) {
+                        const bool src = W.fresh && W.pend == PEND_SOURCE && !(P.fluo_only && W.L.comp == 0);
+                        splat_defer(B, W.q, src, W.L.x, sq_word_a(W.rrb, PEND_SOURCE, 0, W.L.comp),
+                                    (uint32_t)W.L.lam | (W.L.batch << 16), exhausted);
+                        W.pend = PEND_NONE;
+                        sq_drain(P, B.film, T, SP, tally, W.q, W.cnt, lane, false);
+                    }
+                }
             }
         }
-        if (__ballot(W.alive) == 0ull) {
-            if (exhausted) break;
-            continue;
-        }
-        advance<GEOM, MODE>(P, B, C, W, A, G);
+        if (__ballot(W.alive) == 0ull && !exhausted) continue;
+        // with every lane done and the queue exhausted this only drains the splats
+        advance<GEOM, MODE>(P, B, C, W, A, G, exhausted);
+        if (exhausted && __ballot(W.alive) == 0ull) break;
     }
 
+    if (DEFER && W.q.slice && lane == 0) B.sjob_counts[gwave] = (uint32_t)W.q.sj_n;
     // ---- flush counters: per-lane -> wave -> block LDS -> global
     {
         uint32_t a = W.cnt.vertices, b = W.cnt.scatters, c = W.cnt.splat_hit;
@@ -1143,13 +1382,6 @@ __global__ void __launch_bounds__(256) k_transport(const KParams P, const KBuffe
 // tally are flushed to that instance's global counters.
 constexpr int kParamWords = ((int)sizeof(KParams) + 15) / 16 * 4;
 
-DEV void wave_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    asm volatile("" ::: "memory");
-}
-
 DEV void batch_flush(const KBatch& Bt, int inst, uint32_t* tally, uint32_t* hist, Counters& cnt,
                      uint32_t lane) {
     uint32_t a = cnt.vertices, b = cnt.scatters, c = cnt.splat_hit;
@@ -1201,8 +1433,15 @@ __global__ void __launch_bounds__(256) k_batch(const KBatch Bt) {
     W.L.pid = 0;
     W.alive = false;
     W.pend = PEND_NONE;
+    W.face = 0;
     W.nrm[0] = W.nrm[1] = W.nrm[2] = 0.f;
     W.rrb = 0;
+    W.q.base = nullptr;
+    W.q.agg = nullptr;
+    W.q.head = 0;
+    W.q.count = 0;
+    W.q.slice = nullptr;
+    W.q.sj_n = 0;
     AdjView A;
     A.S = nullptr;
     A.Gx = nullptr;
@@ -1275,10 +1514,59 @@ __global__ void __launch_bounds__(256) k_batch(const KBatch Bt) {
             if (done && pending < 0 && lo >= hi) break;
             continue;
         }
-        if (P.geometry == FPT_GEOM_SLAB) advance<FPT_GEOM_SLAB, MODE_FWD>(P, Bd, C, W, A, G);
-        else advance<FPT_GEOM_SPHERE, MODE_FWD>(P, Bd, C, W, A, G);
+        if (P.geometry == FPT_GEOM_SLAB) advance<FPT_GEOM_SLAB, MODE_FWD>(P, Bd, C, W, A, G, false);
+        else advance<FPT_GEOM_SPHERE, MODE_FWD>(P, Bd, C, W, A, G, false);
     }
     if (cur >= 0) batch_flush(Bt, cur, tally, hist, W.cnt, lane);
+}
+
+// Connections deferred to the device buffer by the transport kernel: block b
+// evaluates the slice of transport wave b.
+__global__ void __launch_bounds__(256) k_splat_jobs(const KParams P, const KBuffers B) {
+    extern __shared__ uint32_t smem[];
+    uint32_t* tally = smem;
+    KSphere* SPw = reinterpret_cast<KSphere*>(smem + kLdsSpheres);
+    const uint32_t* T = smem + kLdsTable;
+    const uint32_t n = B.sjob_counts[blockIdx.x];
+    if (n == 0) return;  // uniform across the block
+    for (int i = threadIdx.x; i < FPT_N_TALLIES; i += blockDim.x) tally[i] = 0u;
+    for (int i = threadIdx.x; i < P.table_words; i += blockDim.x) smem[kLdsTable + i] = B.tables[i];
+    for (int i = threadIdx.x; i < P.n_spheres; i += blockDim.x) SPw[i] = P.spheres[i];
+    __syncthreads();
+    const uint32_t S = B.sjob_slice;
+    const uint32_t* sl = B.sjobs + (size_t)blockIdx.x * 5 * S;
+    const uint32_t lane = lane_id();
+    const uint32_t wv = threadIdx.x >> 6;
+    uint32_t* agg = smem + kLdsTable + ((P.table_words + 63) & ~63) + wv * kAggWords;
+    for (int i = (int)lane; i < kAggSlots; i += 64) {
+        agg[i] = kAggEmpty;
+        agg[kAggSlots + i] = 0u;
+    }
+    Counters cnt = {0u, 0u, 0u};
+    for (uint32_t b0 = wv * 64; b0 < n; b0 += blockDim.x) {  // uniform per wave
+        const uint32_t i = b0 + lane;
+        Deposit d;
+        d.has = false;
+        d.idx = 0;
+        d.v = 0.f;
+        if (i < n) {
+            const float x[3] = {__uint_as_float(sl[i]), __uint_as_float(sl[S + i]), __uint_as_float(sl[2 * S + i])};
+            d = splat_entry(P, T, SPw, tally, cnt, x, sl[3 * S + i], sl[4 * S + i]);
+        }
+        film_add_merged(P, B.film, agg, d, lane);
+    }
+    uint32_t h = cnt.splat_hit;
+    for (int off = 32; off > 0; off >>= 1) h += __shfl_xor(h, off);
+    if (lane_id() == 0 && h) atomicAdd(&tally[FPT_T_SPLAT_HIT], h);
+    __syncthreads();
+    if (threadIdx.x < FPT_N_TALLIES && B.tallies && tally[threadIdx.x])
+        atomicAdd(&B.tallies[threadIdx.x], (unsigned long long)tally[threadIdx.x]);
+}
+
+hipError_t launch_splat_jobs(const KParams& P, const KBuffers& B, int grid, hipStream_t s) {
+    const size_t lds = (size_t)(kLdsTable + ((P.table_words + 63) & ~63) + 4 * kAggWords) * 4;
+    hipLaunchKernelGGL(k_splat_jobs, dim3(grid), dim3(256), lds, s, P, B);
+    return hipGetLastError();
 }
 
 // films[i] += counts[i] * wscale[instance of i]
@@ -1355,6 +1643,8 @@ __global__ void k_reduce_partials(const float* partials, int nblocks, int np, fl
 // Host-side launchers (called by the C-ABI implementation).
 size_t transport_lds_bytes(const KParams& P, int block_threads, int mode) {
     size_t words = kLdsTable + ((P.table_words + 63) & ~63) + P.hist_words;
+    if (mode == MODE_FWD && P.geometry == FPT_GEOM_BOX)  // deferred splat rings and merging tables
+        words += (size_t)(block_threads / 64) * (kSqWords + kAggWords);
     if (mode == MODE_ADJ || mode == MODE_REC_ADJ)
         words += (size_t)(block_threads / 64) * 2 * kMaxNP * 64 + (size_t)(block_threads / 64) * kMaxNP;
     return words * 4;
