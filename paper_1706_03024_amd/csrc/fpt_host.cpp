@@ -527,13 +527,16 @@ void fill_run(const fpt_scene* sc, const fpt_run* run, uint32_t B, KParams* P) {
     P->splat_rr = (float)run->splat_rr;
     P->inv_splat_rr = run->splat_rr > 0.0 ? (float)(1.0 / run->splat_rr) : 0.f;
     P->max_vertices = 0;
-    P->refill_lanes = sc->tune.refill_lanes > 0 ? std::min(64, sc->tune.refill_lanes) : 16;
+    // defaults measured on MI355X: refill once most lanes are free, walk paths
+    // in media in wave blocks from their second vertex (pinhole scenes) or
+    // eighth (escape sensors), up to four paths per block round
+    const bool pin = sc->desc.sensor == FPT_SENSOR_PINHOLE;
+    P->refill_lanes = sc->tune.refill_lanes > 0 ? std::min(64, sc->tune.refill_lanes) : (pin ? 48 : 60);
     // escape films up to 8192 counters use a per-block LDS histogram
     const int64_t hw = sc->desc.sensor == FPT_SENSOR_ESCAPE ? film_elems(sc->desc, B) : 0;
     P->hist_words = hw <= 8192 ? (int)hw : 0;
-    P->block_min_v = sc->tune.block_min_vertices > 0 ? (uint32_t)sc->tune.block_min_vertices : 16u;
-    P->max_segments = sc->tune.block_segments > 0 ? sc->tune.block_segments
-                                                  : (sc->desc.sensor == FPT_SENSOR_PINHOLE ? 4 : 1);
+    P->block_min_v = sc->tune.block_min_vertices > 0 ? (uint32_t)sc->tune.block_min_vertices : (pin ? 2u : 8u);
+    P->max_segments = sc->tune.block_segments > 0 ? sc->tune.block_segments : 4;
 }
 
 int32_t ensure_scratch(fpt_scene* sc, size_t counts, size_t partials) {
@@ -635,9 +638,9 @@ int32_t batch_build_items(fpt_batch* bt) {
     if (!items.empty())
         HIP_TRY(hipMemcpy(bt->d_items, items.data(), items.size() * sizeof(KWorkItem), hipMemcpyHostToDevice),
                 "upload items");
-    const int refill = bt->tune.refill_lanes > 0 ? std::min(64, bt->tune.refill_lanes) : 16;
+    const int refill = bt->tune.refill_lanes > 0 ? std::min(64, bt->tune.refill_lanes) : 8;
     const uint32_t bmin = bt->tune.block_min_vertices > 0 ? (uint32_t)bt->tune.block_min_vertices : 64u;
-    const int segs = bt->tune.block_segments > 0 ? bt->tune.block_segments : 1;
+    const int segs = bt->tune.block_segments > 0 ? bt->tune.block_segments : 2;
     for (KParams& p : bt->params) {
         p.refill_lanes = refill;
         p.block_min_v = bmin;
@@ -947,7 +950,7 @@ int32_t fpt_batch_create(const fpt_scene_desc* descs, const fpt_run* runs, int32
         toff[i] = (uint32_t)tables.size();
         tables.insert(tables.end(), tmp.image.begin(), tmp.image.end());
         while (tables.size() % 4) tables.push_back(0u);
-        max_tw = std::max(max_tw, params[i].table_words);
+        max_tw = std::max(max_tw, params[i].off_kap);  // forward only: no d sigma_a rows
         wscale[i] = params[i].wscale;
         // expected work: paths x (1 + scattering optical size), for longest-first ordering
         const fpt_medium& md = d.media[d.body_medium];
@@ -1058,24 +1061,18 @@ int32_t fpt_autotune(fpt_scene* sc, const fpt_run* run, fpt_batch* bt, fpt_tune*
     const fpt_tune saved = sc ? sc->tune : bt->tune;
     std::vector<fpt_tune> cand;
     const int blocks[2] = {128, 256};
-    const int refills[3] = {8, 16, 32};
-    const int bmins[4] = {8, 16, 32, 64};
-    const int chunks[3] = {1024, 4096, 16384};
-    for (int b : blocks)
-        for (int r : refills)
-            for (int m : bmins) {
-                if (sc) {
-                    for (int g : {1, 4}) {
-                        fpt_tune t = {b, 0, r, 0, m, g};
-                        cand.push_back(t);
-                    }
-                } else {
-                    for (int c : chunks) {
-                        fpt_tune t = {b, 0, r, c, m, 1};
-                        cand.push_back(t);
-                    }
-                }
-            }
+    if (sc) {
+        for (int b : blocks)
+            for (int r : {16, 32, 48, 60})
+                for (int m : {1, 2, 8})
+                    for (int g : {1, 2, 4}) cand.push_back(fpt_tune{b, 0, r, 0, m, g});
+    } else {
+        for (int b : blocks)
+            for (int r : {8, 32})
+                for (int m : {16, 64})
+                    for (int g : {1, 2})
+                        for (int c : {1024, 4096}) cand.push_back(fpt_tune{b, 0, r, c, m, g});
+    }
     float best = 1e30f;
     fpt_tune best_t = saved;
     int32_t rc = FPT_OK;

@@ -558,19 +558,24 @@ template <int GEOM, int MODE>
 DEV void block_walk(const KParams& P, const KBuffers& B, const uint32_t* T, const KSphere* SP,
                     uint32_t* tally, Lane& L, uint64_t& elig, uint32_t lane, bool pinhole,
                     Counters& cnt, float* Sw, float* Gxl, float* G, bool& full, SplatQ& q,
-                    bool exhausted) {
+                    bool exhausted, uint64_t deepmask) {
     constexpr bool ADJ = (MODE == MODE_ADJ || MODE == MODE_REC_ADJ);
     constexpr bool REC = (MODE == MODE_REC || MODE == MODE_REC_ADJ);
-    // segment width: one path per 64 lanes, two per 32, or four per 16
-    const int ne = __popcll(elig);
+    // segment width: one path per 64 lanes, two per 32, or four per 16.  A
+    // path whose last round ran its full width is deep in its medium and
+    // likely to fill 64 lanes again: such paths go first, one per round.
+    const uint64_t ed = elig & deepmask;
+    uint64_t pick = ed ? ed : elig;
+    const int ne = ed ? 1 : __popcll(elig);
     const int W = (ne >= 3 && P.max_segments >= 4) ? 16 : ((ne >= 2 && P.max_segments >= 2) ? 32 : 64);
     const int nseg = 64 / W;
     int own[4] = {-1, -1, -1, -1};
 #pragma unroll
     for (int g = 0; g < 4; ++g) {
-        if (g < nseg && elig) {
-            own[g] = __ffsll((unsigned long long)elig) - 1;
-            elig &= elig - 1ull;
+        if (g < nseg && pick) {
+            own[g] = __ffsll((unsigned long long)pick) - 1;
+            elig &= ~(1ull << own[g]);
+            pick &= pick - 1ull;
         }
     }
     const int seg = (int)lane / W;
@@ -821,6 +826,7 @@ struct WaveCtx {
 struct WalkState {
     Lane L;
     bool alive, fresh;
+    bool deep;  // the path's last wave-block round ran its full width
     int pend;
     int face;  // wall face of a pending surface splat (deferred splats)
     float nrm[3];
@@ -861,6 +867,7 @@ DEV void start_path(const KParams& P, const WaveCtx& C, WalkState& W, AdjView& A
     // ---- vertex 0: the light (eq. 12: light point, excitation wavelength)
     alive = true;
     fresh = true;
+    W.deep = false;
     L.v = 0;
     L.nsc = 0;
     L.nem = 0;
@@ -949,6 +956,7 @@ DEV void advance(const KParams& P, const KBuffers& B, const WaveCtx& C, WalkStat
     (void)lane;
     // ---- long paths: wave-cooperative blocks of up to 64 vertices each
     bool full = false;
+    const uint64_t dm = __ballot(W.deep);
     if constexpr (MODE != MODE_REC_ADJ) {
         // paths whose last block ran its full width without stopping go again,
         // up to kBlockPasses passes per iteration
@@ -960,12 +968,13 @@ DEV void advance(const KParams& P, const KBuffers& B, const WaveCtx& C, WalkStat
             while (elig) {  // each round takes up to four long paths off `elig`
                 block_walk<GEOM, MODE>(P, B, T, SP, tally, L, elig, lane, pinhole, cnt,
                                        ADJ ? A.S - lane : nullptr, ADJ ? A.Gx : nullptr, G, full, W.q,
-                                       exhausted);
+                                       exhausted, dm);
                 if constexpr (DEFER) sq_drain(P, B.film, T, SP, tally, W.q, cnt, lane, false);
             }
         }
     }
 
+    W.deep = full;
     // ---- one segment of the walk for every live lane with no pending splat
     int ev = EV_NONE;
     int exit_code = -1;
@@ -1232,12 +1241,14 @@ __global__ void __launch_bounds__(256) k_transport(const KParams P, const KBuffe
     KSphere* SPw = reinterpret_cast<KSphere*>(smem + kLdsSpheres);  // sphere table
     const KSphere* SP = SPw;
     const uint32_t* T = smem + kLdsTable;                            // table image
-    const int tw = (P.table_words + 63) & ~63;
+    // the image up to the d sigma_a / d conc rows, which only the adjoint reads
+    const int staged = ADJ ? P.table_words : P.off_kap;
+    const int tw = (staged + 63) & ~63;
     // escape histogram in LDS (FWD, escape sensor, small films), flushed once per block
     uint32_t* hist = smem + kLdsTable + tw;
     const bool lds_hist = MODE == MODE_FWD && P.hist_words > 0;
     for (int i = threadIdx.x; i < FPT_N_TALLIES; i += blockDim.x) tally[i] = 0u;
-    for (int i = threadIdx.x; i < P.table_words; i += blockDim.x) smem[kLdsTable + i] = B.tables[i];
+    for (int i = threadIdx.x; i < staged; i += blockDim.x) smem[kLdsTable + i] = B.tables[i];
     for (int i = threadIdx.x; i < P.n_spheres; i += blockDim.x) SPw[i] = P.spheres[i];
     if (lds_hist)
         for (int i = threadIdx.x; i < P.hist_words; i += blockDim.x) hist[i] = 0u;
@@ -1271,6 +1282,7 @@ __global__ void __launch_bounds__(256) k_transport(const KParams P, const KBuffe
     W.cnt = {0u, 0u, 0u};
     W.L.pid = 0;
     W.alive = false;
+    W.deep = false;
     W.pend = PEND_NONE;
     W.face = 0;
     W.nrm[0] = W.nrm[1] = W.nrm[2] = 0.f;
@@ -1432,6 +1444,7 @@ __global__ void __launch_bounds__(256) k_batch(const KBatch Bt) {
     W.cnt = {0u, 0u, 0u};
     W.L.pid = 0;
     W.alive = false;
+    W.deep = false;
     W.pend = PEND_NONE;
     W.face = 0;
     W.nrm[0] = W.nrm[1] = W.nrm[2] = 0.f;
@@ -1482,7 +1495,7 @@ __global__ void __launch_bounds__(256) k_batch(const KBatch Bt) {
                     for (int i = lane; i < 32; i += 64) tally[i] = 0u;
                     for (int i = lane; i < Bt.hist_words; i += 64) hist[i] = 0u;
                     const uint32_t* tsrc = Bt.tables + Bt.table_off[item.instance];
-                    const int tw = Bt.params[item.instance].table_words;
+                    const int tw = Bt.params[item.instance].off_kap;  // forward: no d sigma_a rows
                     for (int i = lane; i < tw; i += 64) table[i] = tsrc[i];
                     wave_sync();
                     cur = (int)item.instance;
@@ -1530,14 +1543,14 @@ __global__ void __launch_bounds__(256) k_splat_jobs(const KParams P, const KBuff
     const uint32_t n = B.sjob_counts[blockIdx.x];
     if (n == 0) return;  // uniform across the block
     for (int i = threadIdx.x; i < FPT_N_TALLIES; i += blockDim.x) tally[i] = 0u;
-    for (int i = threadIdx.x; i < P.table_words; i += blockDim.x) smem[kLdsTable + i] = B.tables[i];
+    for (int i = threadIdx.x; i < P.off_kap; i += blockDim.x) smem[kLdsTable + i] = B.tables[i];
     for (int i = threadIdx.x; i < P.n_spheres; i += blockDim.x) SPw[i] = P.spheres[i];
     __syncthreads();
     const uint32_t S = B.sjob_slice;
     const uint32_t* sl = B.sjobs + (size_t)blockIdx.x * 5 * S;
     const uint32_t lane = lane_id();
     const uint32_t wv = threadIdx.x >> 6;
-    uint32_t* agg = smem + kLdsTable + ((P.table_words + 63) & ~63) + wv * kAggWords;
+    uint32_t* agg = smem + kLdsTable + ((P.off_kap + 63) & ~63) + wv * kAggWords;
     for (int i = (int)lane; i < kAggSlots; i += 64) {
         agg[i] = kAggEmpty;
         agg[kAggSlots + i] = 0u;
@@ -1564,7 +1577,7 @@ __global__ void __launch_bounds__(256) k_splat_jobs(const KParams P, const KBuff
 }
 
 hipError_t launch_splat_jobs(const KParams& P, const KBuffers& B, int grid, hipStream_t s) {
-    const size_t lds = (size_t)(kLdsTable + ((P.table_words + 63) & ~63) + 4 * kAggWords) * 4;
+    const size_t lds = (size_t)(kLdsTable + ((P.off_kap + 63) & ~63) + 4 * kAggWords) * 4;
     hipLaunchKernelGGL(k_splat_jobs, dim3(grid), dim3(256), lds, s, P, B);
     return hipGetLastError();
 }
@@ -1642,7 +1655,8 @@ __global__ void k_reduce_partials(const float* partials, int nblocks, int np, fl
 // -------------------------------------------------------------------------
 // Host-side launchers (called by the C-ABI implementation).
 size_t transport_lds_bytes(const KParams& P, int block_threads, int mode) {
-    size_t words = kLdsTable + ((P.table_words + 63) & ~63) + P.hist_words;
+    const int staged = (mode == MODE_ADJ || mode == MODE_REC_ADJ) ? P.table_words : P.off_kap;
+    size_t words = kLdsTable + ((staged + 63) & ~63) + P.hist_words;
     if (mode == MODE_FWD && P.geometry == FPT_GEOM_BOX)  // deferred splat rings and merging tables
         words += (size_t)(block_threads / 64) * (kSqWords + kAggWords);
     if (mode == MODE_ADJ || mode == MODE_REC_ADJ)
