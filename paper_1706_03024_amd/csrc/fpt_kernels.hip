@@ -835,92 +835,14 @@ struct WalkState {
     SplatQ q;
 };
 
-// Vertex 0 of path `pid`: the light (eq. 12: light point and excitation
-// wavelength are sampled), then the source splat is left pending.
-template <int GEOM, int MODE>
-DEV void start_path(const KParams& P, const WaveCtx& C, WalkState& W, AdjView& A, uint32_t pid) {
-    constexpr bool ADJ = (MODE == MODE_ADJ || MODE == MODE_REC_ADJ);
-    constexpr bool REC = (MODE == MODE_REC || MODE == MODE_REC_ADJ);
-    (void)ADJ;
-    (void)REC;
-    Lane& L = W.L;
-    bool& alive = W.alive;
-    bool& fresh = W.fresh;
-    int& pend = W.pend;
-    float* nrm = W.nrm;
-    uint32_t& rrb = W.rrb;
-    Counters& cnt = W.cnt;
-    const uint32_t* T = C.T;
-    const KSphere* SP = C.SP;
-    uint32_t* tally = C.tally;
-    uint32_t* hist = C.hist;
-    const bool lds_hist = C.lds_hist;
-    const bool pinhole = C.pinhole;
-    const uint32_t lane = C.lane;
-    (void)SP;
-    (void)hist;
-    (void)lds_hist;
-    (void)pinhole;
-    (void)tally;
-    (void)lane;
-    L.pid = pid;
-    // ---- vertex 0: the light (eq. 12: light point, excitation wavelength)
-    alive = true;
-    fresh = true;
+// A dead lane takes path `pid`; its light vertex is drawn in the lane's next
+// step, together with the vertices of the paths in flight.
+DEV void assign_path(WalkState& W, uint32_t pid) {
+    W.L.pid = pid;
+    W.L.v = 0;
+    W.alive = true;
+    W.fresh = true;
     W.deep = false;
-    L.v = 0;
-    L.nsc = 0;
-    L.nem = 0;
-    L.comp = 0;
-    L.batch = L.pid % P.batches;
-    L.splat_sum = 0.f;
-    const uint4 r = philox(L.pid, 0u, 0u, 0u, P.key0, P.key1);
-    const float u = u24(r.x);
-    int line = 0;
-    for (; line < P.n_lines - 1; ++line)
-        if (u < P.line_cum[line]) break;
-    L.lam = P.line_bin[line];
-    if (P.light == FPT_LIGHT_BEAM) {
-        L.x[0] = P.lpos[0]; L.x[1] = P.lpos[1]; L.x[2] = P.lpos[2];
-        L.w[0] = P.ldir[0]; L.w[1] = P.ldir[1]; L.w[2] = P.ldir[2];
-        L.region = 0;
-    } else {
-        const uint4 r1 = philox(L.pid, 0u, 1u, 0u, P.key0, P.key1);
-        const float ua = u24(r1.x), ub = u24(r1.y);
-        float sp, cp;
-        sincos_rev(ub, &sp, &cp);
-        if (P.light == FPT_LIGHT_POINT) {
-            L.x[0] = P.lpos[0]; L.x[1] = P.lpos[1]; L.x[2] = P.lpos[2];
-            const float ct = 1.f - 2.f * ua;
-            const float st = 2.f * fsqrt(ua * (1.f - ua));
-            L.w[0] = st * cp; L.w[1] = st * sp; L.w[2] = ct;
-            L.region = 0;
-        } else {
-            const float a = u24(r.y), b = u24(r.z);
-            const float sr = fsqrt(ua), cz = fsqrt(1.f - ua);
-            const float lx = sr * cp, ly = sr * sp;
-#pragma unroll
-            for (int i = 0; i < 3; ++i) {
-                L.x[i] = P.lpos[i] + a * P.lu[i] + b * P.lv[i];
-                L.w[i] = lx * P.lt1[i] + ly * P.lt2[i] + cz * P.ln[i];
-            }
-            L.region = -1;
-        }
-    }
-    L.medium = (GEOM == FPT_GEOM_BOX) ? -1 : P.body_medium;
-    L.sc[0] = L.sc[1] = L.sc[2] = 0.f;
-    L.sr2 = 0.f;
-    load_medium(P, T, L);
-    cnt.vertices++;
-    if constexpr (ADJ) {
-#pragma unroll
-        for (int i = 0; i < kMaxNP; ++i) A.S[i * 64] = 0.f;
-    }
-    if (pinhole && P.light == FPT_LIGHT_QUAD) {
-        pend = PEND_SOURCE;
-        nrm[0] = P.ln[0]; nrm[1] = P.ln[1]; nrm[2] = P.ln[2];
-        rrb = rr_bits(r);
-    }
 }
 
 // One iteration of the walk for every live lane: wave-cooperative blocks for
@@ -975,169 +897,244 @@ DEV void advance(const KParams& P, const KBuffers& B, const WaveCtx& C, WalkStat
     }
 
     W.deep = full;
-    // ---- one segment of the walk for every live lane with no pending splat
+    // ---- one step for every live lane: the light vertex of a path assigned in
+    // this iteration, or the next vertex of a path in flight.  Both draw their
+    // uniforms from the same Philox calls (counter (pid, vertex, call, 0)), so a
+    // new path costs no evaluation of the generator of its own.
     int ev = EV_NONE;
     int exit_code = -1;
-    if (alive && !(fresh && pend != PEND_NONE) && !full) {
-        L.v++;
-        if (REC && P.max_vertices && L.v >= P.max_vertices) {
-            exit_code = FPT_EXIT_TRUNC;
-        } else if (L.v >= kMaxPathVertices) {
-            exit_code = FPT_EXIT_SCAP;  // hard bound: every wave's loop terminates
-        } else {
-            cnt.vertices++;
-            const uint4 r = philox(L.pid, L.v, 0u, 0u, P.key0, P.key1);
-            const float u0 = u24(r.x), u1 = u24(r.y), u2 = u24(r.z), u3 = u24(r.w);
-            // eq. 6: free flight with density sigma_t exp(-sigma_t t)
-            const float tf = (L.inv == kInf) ? kInf : -__logf(1.f - u0) * L.inv;
-            const Hit h = next_surface<GEOM>(P, SP, L, GEOM == FPT_GEOM_BOX && L.v == 1u);
-            const bool collide = tf < h.d;
-            const float len = collide ? tf : h.d;
-            if (len < kInf) {
-                L.x[0] += len * L.w[0];
-                L.x[1] += len * L.w[1];
-                L.x[2] += len * L.w[2];
-                score_length<MODE>(P, T, L, A, len);
+    if (alive && !full) {
+        const bool start = fresh;
+        bool step = false;
+        if (!start) {
+            L.v++;
+            if (REC && P.max_vertices && L.v >= P.max_vertices) {
+                exit_code = FPT_EXIT_TRUNC;
+            } else if (L.v >= kMaxPathVertices) {
+                exit_code = FPT_EXIT_SCAP;  // hard bound: every wave's loop terminates
+            } else {
+                step = true;
             }
-            if (!collide) snap_to_plane<GEOM>(P, L, h);
+        }
+        if (start || step) {
+            cnt.vertices++;
+            const uint32_t vc = start ? 0u : L.v;
+            const uint4 r = philox(L.pid, vc, 0u, 0u, P.key0, P.key1);
+            const float u0 = u24(r.x), u1 = u24(r.y), u2 = u24(r.z), u3 = u24(r.w);
             float dir_sin = 0.f, dir_cos = 0.f;  // polar sine/cosine of a new direction
             int frame = -1;                      // -1 world axes, else wall face
-            if (collide) {
-                const float s = u1 * L.st;
-                if (s < L.ss) {
-                    // elastic scattering, isotropic phase function (eq. 2)
-                    ev = EV_SCATTER;
-                    if constexpr (ADJ)
-                        adj_add(A.S, wi(T, P.off_med + L.medium * kMedWords + MW_PSS),
-                                wf(T, P.off_med + L.medium * kMedWords + MW_INV_SS));
-                    L.nsc++;
-                    cnt.scatters++;
-                    if (!P.exc_scatter && L.nem == 0u) exit_code = FPT_EXIT_EXCSCAT;
-                    else if (L.nsc > P.max_scatter) exit_code = FPT_EXIT_SCAP;
-                    else {
-                        dir_cos = 1.f - 2.f * u2;
-                        dir_sin = 2.f * fsqrt(u2 * (1.f - u2));
-                        pend = PEND_MEDIUM;
-                    }
-                } else if (s < L.thr_bg || L.ndy == 0) {
-                    ev = EV_BG;
-                    exit_code = FPT_EXIT_BG;
-                } else {
-                    // a fluorescent particle: which dye slot (sec. 4.1)
-                    ev = EV_DYE;
-                    int j = 0;
-                    const int cb = P.off_cum + L.medium * P.cum_stride * P.N + L.lam;
-                    for (; j < L.ndy - 1; ++j)
-                        if (s < wf(T, cb + j * P.N)) break;
-                    const int mb = P.off_med + L.medium * kMedWords;
-                    if constexpr (ADJ) adj_add(A.S, wi(T, mb + MW_PC + j), wf(T, mb + MW_INV_C + j));
-                    lds_count(tally, FPT_T_DYE_ABS);
-                    if (L.nem >= P.max_emissions) {
-                        exit_code = FPT_EXIT_KCAP;
-                    } else {
-                        const int dye = wi(T, mb + MW_DYE + j);
-                        const int db = P.off_dye + dye * kDyeWords;
-                        const uint4 r1 = philox(L.pid, L.v, 1u, 0u, P.key0, P.key1);
-                        const float uq = u24(r1.x);
-                        if (!(uq < wf(T, db + DW_QY))) {
-                            if constexpr (ADJ) adj_add(A.S, wi(T, db + DW_PQ), -wf(T, db + DW_INV_1MQY));
-                            exit_code = FPT_EXIT_NONRAD;
-                        } else {
-                            if constexpr (ADJ) adj_add(A.S, wi(T, db + DW_PQ), wf(T, db + DW_INV_QY));
-                            // eq. 10: emitted wavelength from the emission CDF,
-                            // independent of the excitation wavelength (sec. 2.1)
-                            const float ul = u24(r1.y);
-                            const uint32_t* cdf = T + P.off_cdf + dye * P.N;
-                            int lo = 0, hi = P.N - 1;
-                            while (lo < hi) {
-                                const int mid = (lo + hi) >> 1;
-                                if (ul < __uint_as_float(cdf[mid])) hi = mid;
-                                else lo = mid + 1;
-                            }
-                            L.lam = lo;
-                            load_sigma(P, T, L);
-                            L.nem++;
-                            L.comp = 1;
-                            lds_count(tally, FPT_T_EMISSIONS);
+            bool need1 = false;                  // the vertex draws call 1 of its counter too
+            int dye = 0;                         // the absorbing dye (step lanes)
+            if (start) {
+                // vertex 0: the light (eq. 12: light point, excitation wavelength)
+                L.nsc = 0;
+                L.nem = 0;
+                L.comp = 0;
+                L.batch = L.pid % P.batches;
+                L.splat_sum = 0.f;
+                int line = 0;
+                for (; line < P.n_lines - 1; ++line)
+                    if (u0 < P.line_cum[line]) break;
+                L.lam = P.line_bin[line];
+                need1 = P.light != FPT_LIGHT_BEAM;
+                if constexpr (ADJ) {
+#pragma unroll
+                    for (int i = 0; i < kMaxNP; ++i) A.S[i * 64] = 0.f;
+                }
+            } else {
+                // eq. 6: free flight with density sigma_t exp(-sigma_t t)
+                const float tf = (L.inv == kInf) ? kInf : -__logf(1.f - u0) * L.inv;
+                const Hit h = next_surface<GEOM>(P, SP, L, GEOM == FPT_GEOM_BOX && L.v == 1u);
+                const bool collide = tf < h.d;
+                const float len = collide ? tf : h.d;
+                if (len < kInf) {
+                    L.x[0] += len * L.w[0];
+                    L.x[1] += len * L.w[1];
+                    L.x[2] += len * L.w[2];
+                    score_length<MODE>(P, T, L, A, len);
+                }
+                if (!collide) snap_to_plane<GEOM>(P, L, h);
+                if (collide) {
+                    const float s = u1 * L.st;
+                    if (s < L.ss) {
+                        // elastic scattering, isotropic phase function (eq. 2)
+                        ev = EV_SCATTER;
+                        if constexpr (ADJ)
+                            adj_add(A.S, wi(T, P.off_med + L.medium * kMedWords + MW_PSS),
+                                    wf(T, P.off_med + L.medium * kMedWords + MW_INV_SS));
+                        L.nsc++;
+                        cnt.scatters++;
+                        if (!P.exc_scatter && L.nem == 0u) exit_code = FPT_EXIT_EXCSCAT;
+                        else if (L.nsc > P.max_scatter) exit_code = FPT_EXIT_SCAP;
+                        else {
                             dir_cos = 1.f - 2.f * u2;
                             dir_sin = 2.f * fsqrt(u2 * (1.f - u2));
                             pend = PEND_MEDIUM;
                         }
-                    }
-                }
-            } else {
-                ev = h.ev;
-                if (ev == EV_ESC || ev == EV_INF) {
-                    const int side = L.w[2] < 0.f ? 0 : 1;
-                    exit_code = side == 0 ? FPT_EXIT_ESC_R : FPT_EXIT_ESC_T;
-                    if (!pinhole && !(P.fluo_only && L.comp == 0)) {
-                        const int idx = ((L.batch * 2 + L.comp) * 2 + side) * P.N + L.lam;
-                        if constexpr (MODE == MODE_FWD) {
-                            if (lds_hist) atomicAdd(&hist[idx], 1u);
-                            else atomicAdd(&B.counts[idx], 1u);
-                        }
-                        L.splat_sum += P.wscale;
-                        if constexpr (ADJ) {
-                            const float g = B.gfilm[idx] * P.wscale;
-#pragma unroll
-                            for (int i = 0; i < kMaxNP; ++i)
-                                if (i < P.np) G[i] += g * A.S[i * 64];
-                        }
-                    }
-                } else if (ev == EV_LIGHT) {
-                    exit_code = FPT_EXIT_LIGHT;
-                } else if (ev == EV_WALL) {
-                    const float rho = h.idx >= 0 ? wf(T, P.off_rho + h.idx * P.N + L.lam) : 0.f;
-                    if (!(u1 < rho)) {
-                        exit_code = FPT_EXIT_WALL;
+                    } else if (s < L.thr_bg || L.ndy == 0) {
+                        ev = EV_BG;
+                        exit_code = FPT_EXIT_BG;
                     } else {
-                        // Lambertian reflection about the wall's inward normal
-                        lds_count(tally, FPT_T_WALL_REFLECT);
-                        dir_sin = fsqrt(u2);
-                        dir_cos = fsqrt(1.f - u2);
-                        frame = h.idx;
-                        W.face = h.idx;
-                        pend = PEND_SURFACE;
+                        // a fluorescent particle: which dye slot (sec. 4.1)
+                        ev = EV_DYE;
+                        int j = 0;
+                        const int cb = P.off_cum + L.medium * P.cum_stride * P.N + L.lam;
+                        for (; j < L.ndy - 1; ++j)
+                            if (s < wf(T, cb + j * P.N)) break;
+                        const int mb = P.off_med + L.medium * kMedWords;
+                        if constexpr (ADJ) adj_add(A.S, wi(T, mb + MW_PC + j), wf(T, mb + MW_INV_C + j));
+                        lds_count(tally, FPT_T_DYE_ABS);
+                        if (L.nem >= P.max_emissions) {
+                            exit_code = FPT_EXIT_KCAP;
+                        } else {
+                            dye = wi(T, mb + MW_DYE + j);
+                            need1 = true;  // quantum-yield test and emitted wavelength
+                        }
                     }
                 } else {
-                    // index-matched interface: change medium, keep direction
-                    lds_count(tally, FPT_T_CROSSINGS);
-                    if constexpr (GEOM == FPT_GEOM_BOX) {
-                        L.region = (ev == EV_ENTER) ? h.idx : -1;
-                        L.medium = -1;
-                        if (L.region >= 0) {
-                            const KSphere& sp = SP[L.region];
-                            L.sc[0] = sp.c[0];
-                            L.sc[1] = sp.c[1];
-                            L.sc[2] = sp.c[2];
-                            L.sr2 = sp.r2;
-                            L.medium = sp.medium;
+                    ev = h.ev;
+                    if (ev == EV_ESC || ev == EV_INF) {
+                        const int side = L.w[2] < 0.f ? 0 : 1;
+                        exit_code = side == 0 ? FPT_EXIT_ESC_R : FPT_EXIT_ESC_T;
+                        if (!pinhole && !(P.fluo_only && L.comp == 0)) {
+                            const int idx = ((L.batch * 2 + L.comp) * 2 + side) * P.N + L.lam;
+                            if constexpr (MODE == MODE_FWD) {
+                                if (lds_hist) atomicAdd(&hist[idx], 1u);
+                                else atomicAdd(&B.counts[idx], 1u);
+                            }
+                            L.splat_sum += P.wscale;
+                            if constexpr (ADJ) {
+                                const float g = B.gfilm[idx] * P.wscale;
+#pragma unroll
+                                for (int i = 0; i < kMaxNP; ++i)
+                                    if (i < P.np) G[i] += g * A.S[i * 64];
+                            }
                         }
-                        load_medium(P, T, L);
+                    } else if (ev == EV_LIGHT) {
+                        exit_code = FPT_EXIT_LIGHT;
+                    } else if (ev == EV_WALL) {
+                        const float rho = h.idx >= 0 ? wf(T, P.off_rho + h.idx * P.N + L.lam) : 0.f;
+                        if (!(u1 < rho)) {
+                            exit_code = FPT_EXIT_WALL;
+                        } else {
+                            // Lambertian reflection about the wall's inward normal
+                            lds_count(tally, FPT_T_WALL_REFLECT);
+                            dir_sin = fsqrt(u2);
+                            dir_cos = fsqrt(1.f - u2);
+                            frame = h.idx;
+                            W.face = h.idx;
+                            pend = PEND_SURFACE;
+                        }
+                    } else {
+                        // index-matched interface: change medium, keep direction
+                        lds_count(tally, FPT_T_CROSSINGS);
+                        if constexpr (GEOM == FPT_GEOM_BOX) {
+                            L.region = (ev == EV_ENTER) ? h.idx : -1;
+                            L.medium = -1;
+                            if (L.region >= 0) {
+                                const KSphere& sp = SP[L.region];
+                                L.sc[0] = sp.c[0];
+                                L.sc[1] = sp.c[1];
+                                L.sc[2] = sp.c[2];
+                                L.sr2 = sp.r2;
+                                L.medium = sp.medium;
+                            }
+                            load_medium(P, T, L);
+                        }
                     }
                 }
             }
-            if (pend != PEND_NONE && exit_code < 0) {
-                float sp, cp;
-                sincos_rev(u3, &sp, &cp);
-                const float a = dir_sin * cp, b = dir_sin * sp;
-                if (frame < 0) {
-                    L.w[0] = a; L.w[1] = b; L.w[2] = dir_cos;
+            // call 1 of the counter: the light's direction (and position on a
+            // quad), or the quantum-yield test and emitted wavelength of a dye
+            uint4 r1 = make_uint4(0u, 0u, 0u, 0u);
+            if (need1) r1 = philox(L.pid, vc, 1u, 0u, P.key0, P.key1);
+            if (start) {
+                if (P.light == FPT_LIGHT_BEAM) {
+                    L.x[0] = P.lpos[0]; L.x[1] = P.lpos[1]; L.x[2] = P.lpos[2];
+                    L.w[0] = P.ldir[0]; L.w[1] = P.ldir[1]; L.w[2] = P.ldir[2];
+                    L.region = 0;
                 } else {
-                    // wall frame: normal n = sg e_ax, tangents e_(ax+1), sg e_(ax+2)
-                    const int ax = frame >> 1;
-                    const float sg = (frame & 1) ? -1.f : 1.f;
-                    const float c = sg * dir_cos, bb = sg * b;
-                    L.w[0] = ax == 0 ? c : (ax == 1 ? bb : a);
-                    L.w[1] = ax == 0 ? a : (ax == 1 ? c : bb);
-                    L.w[2] = ax == 0 ? bb : (ax == 1 ? a : c);
-                    nrm[0] = ax == 0 ? sg : 0.f;
-                    nrm[1] = ax == 1 ? sg : 0.f;
-                    nrm[2] = ax == 2 ? sg : 0.f;
+                    const float ua = u24(r1.x), ub = u24(r1.y);
+                    float sp, cp;
+                    sincos_rev(ub, &sp, &cp);
+                    if (P.light == FPT_LIGHT_POINT) {
+                        L.x[0] = P.lpos[0]; L.x[1] = P.lpos[1]; L.x[2] = P.lpos[2];
+                        const float ct = 1.f - 2.f * ua;
+                        const float st = 2.f * fsqrt(ua * (1.f - ua));
+                        L.w[0] = st * cp; L.w[1] = st * sp; L.w[2] = ct;
+                        L.region = 0;
+                    } else {
+                        const float a = u1, b = u2;
+                        const float sr = fsqrt(ua), cz = fsqrt(1.f - ua);
+                        const float lx = sr * cp, ly = sr * sp;
+#pragma unroll
+                        for (int i = 0; i < 3; ++i) {
+                            L.x[i] = P.lpos[i] + a * P.lu[i] + b * P.lv[i];
+                            L.w[i] = lx * P.lt1[i] + ly * P.lt2[i] + cz * P.ln[i];
+                        }
+                        L.region = -1;
+                    }
                 }
-                rrb = rr_bits(r);
+                L.medium = (GEOM == FPT_GEOM_BOX) ? -1 : P.body_medium;
+                L.sc[0] = L.sc[1] = L.sc[2] = 0.f;
+                L.sr2 = 0.f;
+                load_medium(P, T, L);
+                if (pinhole && P.light == FPT_LIGHT_QUAD) {
+                    pend = PEND_SOURCE;
+                    nrm[0] = P.ln[0]; nrm[1] = P.ln[1]; nrm[2] = P.ln[2];
+                    rrb = rr_bits(r);
+                }
             } else {
-                pend = PEND_NONE;
+                if (need1) {
+                    const int db = P.off_dye + dye * kDyeWords;
+                    const float uq = u24(r1.x);
+                    if (!(uq < wf(T, db + DW_QY))) {
+                        if constexpr (ADJ) adj_add(A.S, wi(T, db + DW_PQ), -wf(T, db + DW_INV_1MQY));
+                        exit_code = FPT_EXIT_NONRAD;
+                    } else {
+                        if constexpr (ADJ) adj_add(A.S, wi(T, db + DW_PQ), wf(T, db + DW_INV_QY));
+                        // eq. 10: emitted wavelength from the emission CDF,
+                        // independent of the excitation wavelength (sec. 2.1)
+                        const float ul = u24(r1.y);
+                        const uint32_t* cdf = T + P.off_cdf + dye * P.N;
+                        int lo = 0, hi = P.N - 1;
+                        while (lo < hi) {
+                            const int mid = (lo + hi) >> 1;
+                            if (ul < __uint_as_float(cdf[mid])) hi = mid;
+                            else lo = mid + 1;
+                        }
+                        L.lam = lo;
+                        load_sigma(P, T, L);
+                        L.nem++;
+                        L.comp = 1;
+                        lds_count(tally, FPT_T_EMISSIONS);
+                        dir_cos = 1.f - 2.f * u2;
+                        dir_sin = 2.f * fsqrt(u2 * (1.f - u2));
+                        pend = PEND_MEDIUM;
+                    }
+                }
+                if (pend != PEND_NONE && exit_code < 0) {
+                    float sp, cp;
+                    sincos_rev(u3, &sp, &cp);
+                    const float a = dir_sin * cp, b = dir_sin * sp;
+                    if (frame < 0) {
+                        L.w[0] = a; L.w[1] = b; L.w[2] = dir_cos;
+                    } else {
+                        // wall frame: normal n = sg e_ax, tangents e_(ax+1), sg e_(ax+2)
+                        const int ax = frame >> 1;
+                        const float sg = (frame & 1) ? -1.f : 1.f;
+                        const float c = sg * dir_cos, bb = sg * b;
+                        L.w[0] = ax == 0 ? c : (ax == 1 ? bb : a);
+                        L.w[1] = ax == 0 ? a : (ax == 1 ? c : bb);
+                        L.w[2] = ax == 0 ? bb : (ax == 1 ? a : c);
+                        nrm[0] = ax == 0 ? sg : 0.f;
+                        nrm[1] = ax == 1 ? sg : 0.f;
+                        nrm[2] = ax == 2 ? sg : 0.f;
+                    }
+                    rrb = rr_bits(r);
+                } else {
+                    pend = PEND_NONE;
+                }
             }
         }
     }
@@ -1317,18 +1314,7 @@ __global__ void __launch_bounds__(256) k_transport(const KParams P, const KBuffe
                 if (base + (unsigned long long)ndead >= (unsigned long long)P.path_count) exhausted = true;
                 if (!W.alive) {
                     const unsigned long long idx = base + mbcnt(dead);
-                    if (idx < (unsigned long long)P.path_count)
-                        start_path<GEOM, MODE>(P, C, W, A, P.path_begin + (uint32_t)idx);
-                }
-                if constexpr (DEFER) {
-                    // queue the light vertices' splats; the new paths take their first step now
-                    if (C.pinhole) {
-                        const bool src = W.fresh && W.pend == PEND_SOURCE && !(P.fluo_only && W.L.comp == 0);
-                        splat_defer(B, W.q, src, W.L.x, sq_word_a(W.rrb, PEND_SOURCE, 0, W.L.comp),
-                                    (uint32_t)W.L.lam | (W.L.batch << 16), exhausted);
-                        W.pend = PEND_NONE;
-                        sq_drain(P, B.film, T, SP, tally, W.q, W.cnt, lane, false);
-                    }
+                    if (idx < (unsigned long long)P.path_count) assign_path(W, P.path_begin + (uint32_t)idx);
                 }
             }
         }
@@ -1514,12 +1500,7 @@ __global__ void __launch_bounds__(256) k_batch(const KBatch Bt) {
                 lo = min(hi, lo + (uint32_t)ndead);
                 if (!W.alive) {
                     const uint32_t idx = base + mbcnt(dead);
-                    if (idx < hi) {
-                        if (P.geometry == FPT_GEOM_SLAB)
-                            start_path<FPT_GEOM_SLAB, MODE_FWD>(P, C, W, A, P.path_begin + idx);
-                        else
-                            start_path<FPT_GEOM_SPHERE, MODE_FWD>(P, C, W, A, P.path_begin + idx);
-                    }
+                    if (idx < hi) assign_path(W, P.path_begin + idx);
                 }
             }
         }
