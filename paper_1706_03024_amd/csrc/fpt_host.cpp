@@ -24,6 +24,7 @@ hipError_t launch_zero_u32(uint32_t* p, size_t n, hipStream_t s);
 hipError_t launch_zero_u64(unsigned long long* p, size_t n, hipStream_t s);
 hipError_t launch_finalize_counts(const uint32_t* counts, float* film, size_t n, float scale,
                                   hipStream_t s);
+size_t queue_words();
 hipError_t launch_splat_jobs(const KParams& P, const KBuffers& B, int grid, hipStream_t s);
 hipError_t launch_reduce_partials(const float* partials, int nblocks, int np, float* grad,
                                   hipStream_t s);
@@ -540,7 +541,7 @@ void fill_run(const fpt_scene* sc, const fpt_run* run, uint32_t B, KParams* P) {
 }
 
 int32_t ensure_scratch(fpt_scene* sc, size_t counts, size_t partials) {
-    if (!sc->d_counter) HIP_TRY(hipMalloc(&sc->d_counter, 64), "hipMalloc(counter)");
+    if (!sc->d_counter) HIP_TRY(hipMalloc(&sc->d_counter, queue_words() * 8), "hipMalloc(path queue)");
     if (!sc->d_tally) HIP_TRY(hipMalloc(&sc->d_tally, FPT_N_TALLIES * 8), "hipMalloc(tally)");
     if (counts > sc->counts_cap) {
         if (sc->d_counts) (void)hipFree(sc->d_counts);
@@ -840,7 +841,7 @@ int32_t fpt_render(fpt_scene* sc, const fpt_run* run, float* film, uint64_t* tal
         Bf.sjob_counts = sc->d_sjob_counts;
         Bf.sjob_slice = kSjobSlice;
     }
-    HIP_TRY(launch_zero_u64(sc->d_counter, 1, s), "zero queue");
+    HIP_TRY(launch_zero_u64(sc->d_counter, queue_words(), s), "zero queue");
     if (escape) HIP_TRY(launch_zero_u32(sc->d_counts, n_counts, s), "zero counts");
     HIP_TRY(launch_transport(P, Bf, MODE_FWD, grid, block, s), "transport launch");
     if (defer) HIP_TRY(launch_splat_jobs(P, Bf, (int)waves, s), "deferred splats");
@@ -870,7 +871,7 @@ int32_t fpt_render_adjoint(fpt_scene* sc, const fpt_run* run, const float* gfilm
     Bf.counter = sc->d_counter;
     Bf.gfilm = gfilm;
     Bf.partials = sc->d_partials;
-    HIP_TRY(launch_zero_u64(sc->d_counter, 1, s), "zero queue");
+    HIP_TRY(launch_zero_u64(sc->d_counter, queue_words(), s), "zero queue");
     HIP_TRY(launch_transport(P, Bf, MODE_ADJ, grid, block, s), "adjoint launch");
     HIP_TRY(launch_reduce_partials(sc->d_partials, grid, sc->np, grad, s), "gradient reduction");
     return FPT_OK;
@@ -901,7 +902,7 @@ int32_t fpt_render_records(fpt_scene* sc, const fpt_run* run, fpt_path_record* r
     Bf.gfilm = gfilm;
     Bf.rec = rec;
     Bf.rec_grad = rec_grad;
-    HIP_TRY(launch_zero_u64(sc->d_counter, 1, s), "zero queue");
+    HIP_TRY(launch_zero_u64(sc->d_counter, queue_words(), s), "zero queue");
     HIP_TRY(launch_transport(P, Bf, mode, grid, block, s), "records launch");
     return FPT_OK;
 }

@@ -23,7 +23,9 @@ constexpr float kInf = __builtin_inff();
 constexpr uint32_t kMaxPathVertices = 1u << 28;
 constexpr int kBlockPasses = 4;   // block passes per iteration for paths that never stop
 constexpr float kTauZero = 110.f;  // exp(-110) = 1.7e-48 rounds to 0 in fp32
-constexpr int kLdsSpheres = 32;                                // word offset of the sphere table
+constexpr int kLdsSpheres = 32;
+constexpr int kQueueShards = 64;   // path-queue heads (see k_transport)
+constexpr int kShardStride = 16;   // u64 words between heads: separate 128-byte lines                                // word offset of the sphere table
 constexpr int kLdsTable = kLdsSpheres + 8 * FPT_MAX_SPHERES;   // word offset of the table image
 constexpr float kInv4Pi = 0.0795774715459476679f;
 constexpr float kInvPi = 0.318309886183790672f;
@@ -1299,6 +1301,12 @@ __global__ void __launch_bounds__(256) k_transport(const KParams P, const KBuffe
     W.q.slice = (DEFER && B.sjobs) ? B.sjobs + (size_t)gwave * 5 * B.sjob_slice : nullptr;
     W.q.sj_n = 0;
     bool exhausted = false;
+    // the path queue is split into kQueueShards contiguous ranges with a head
+    // each (a single head serialises every wave's claim at the memory-side
+    // atomic unit); a wave starts on shard gwave mod kQueueShards and moves on
+    // to the next shard only once its own is used up
+    int shard = (int)(gwave % (uint32_t)kQueueShards);
+    int moves = 0;
 
     for (;;) {
         // ---- refill dead lanes from the path queue (one atomic per wave)
@@ -1307,14 +1315,36 @@ __global__ void __launch_bounds__(256) k_transport(const KParams P, const KBuffe
             const uint64_t dead = __ballot(!W.alive);
             const int ndead = __popcll(dead);
             if (ndead >= P.refill_lanes || ndead == 64) {
-                unsigned long long base = 0;
-                if (lane == 0) base = atomicAdd(B.counter, (unsigned long long)ndead);
-                base = ((unsigned long long)(uint32_t)__builtin_amdgcn_readfirstlane((int)(base >> 32)) << 32) |
-                       (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)base);
-                if (base + (unsigned long long)ndead >= (unsigned long long)P.path_count) exhausted = true;
-                if (!W.alive) {
-                    const unsigned long long idx = base + mbcnt(dead);
-                    if (idx < (unsigned long long)P.path_count) assign_path(W, P.path_begin + (uint32_t)idx);
+                for (;;) {  // at most kQueueShards iterations over the wave's life
+                    const unsigned long long lo = (unsigned long long)shard * P.path_count / kQueueShards;
+                    const unsigned long long hi = (unsigned long long)(shard + 1) * P.path_count / kQueueShards;
+                    unsigned long long off = 0;
+                    if (lane == 0) off = atomicAdd(&B.counter[shard * kShardStride], (unsigned long long)ndead);
+                    off = ((unsigned long long)(uint32_t)__builtin_amdgcn_readfirstlane((int)(off >> 32)) << 32) |
+                          (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)off);
+                    const unsigned long long base = lo + off;
+                    if (base < hi) {
+                        if (!W.alive) {
+                            const unsigned long long idx = base + mbcnt(dead);
+                            if (idx < hi) assign_path(W, P.path_begin + (uint32_t)idx);
+                        }
+                        if (base + (unsigned long long)ndead < hi) break;
+                        // this claim used the shard up: count it
+                        if (lane == 0) atomicAdd(&B.counter[kQueueShards * kShardStride], 1ull);
+                    }
+                    // this shard is used up: the end of the queue once every
+                    // shard is, else the next shard
+                    unsigned long long used = 0;
+                    if (lane == 0)
+                        used = __hip_atomic_load(&B.counter[kQueueShards * kShardStride], __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT);
+                    used = (unsigned long long)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)used);
+                    if (++moves == kQueueShards || used >= (unsigned long long)kQueueShards) {
+                        exhausted = true;
+                        break;
+                    }
+                    shard = shard + 1 == kQueueShards ? 0 : shard + 1;
+                    if (base < hi) break;  // the lanes got paths; claim from the next shard later
                 }
             }
         }
@@ -1635,6 +1665,8 @@ __global__ void k_reduce_partials(const float* partials, int nblocks, int np, fl
 
 // -------------------------------------------------------------------------
 // Host-side launchers (called by the C-ABI implementation).
+size_t queue_words() { return (size_t)(kQueueShards + 1) * kShardStride; }  // heads, used-up count
+
 size_t transport_lds_bytes(const KParams& P, int block_threads, int mode) {
     const int staged = (mode == MODE_ADJ || mode == MODE_REC_ADJ) ? P.table_words : P.off_kap;
     size_t words = kLdsTable + ((staged + 63) & ~63) + P.hist_words;
