@@ -240,6 +240,17 @@ int32_t fpt_grad_param_count(const fpt_scene* scene);
 /* Optional launch-shape override for this scene (NULL restores defaults). */
 int32_t fpt_scene_set_tune(fpt_scene* scene, const fpt_tune* tune);
 
+/* Launch timing, for measurement.  While enabled (enable != 0), every
+ * fpt_render of this scene records HIP events on the caller's stream around
+ * its transport launch and its deferred-connection launch (pinhole scenes);
+ * up to FPT_MAX_TIMED_RENDERS renders are kept, later ones are not timed.
+ * Enabling or disabling clears the record.  fpt_scene_timing waits for the
+ * recorded renders, writes their count and the mean duration in ms of each
+ * launch (0 where there was none), and clears the record. */
+#define FPT_MAX_TIMED_RENDERS 4096
+int32_t fpt_scene_set_timing(fpt_scene* scene, int32_t enable);
+int32_t fpt_scene_timing(fpt_scene* scene, int32_t* renders, float* transport_ms, float* deferred_ms);
+
 /* Forward render.  Accumulates (+=) into film_dev (device, fp32, film shape)
  * and tallies_dev (device, FPT_N_TALLIES uint64; optional, may be NULL).
  * Escape films are integer counts scaled by parity_batches/total_paths at the

@@ -132,6 +132,8 @@ def lib():
         "fpt_film_shape": (C.c_int32, [vp, C.c_uint32, C.POINTER(C.c_int64), C.POINTER(C.c_int32)]),
         "fpt_grad_param_count": (C.c_int32, [vp]),
         "fpt_scene_set_tune": (C.c_int32, [vp, C.POINTER(Tune)]),
+        "fpt_scene_set_timing": (C.c_int32, [vp, C.c_int32]),
+        "fpt_scene_timing": (C.c_int32, [vp, C.POINTER(C.c_int32), C.POINTER(C.c_float), C.POINTER(C.c_float)]),
         "fpt_render": (C.c_int32, [vp, C.POINTER(Run), vp, vp, vp]),
         "fpt_render_adjoint": (C.c_int32, [vp, C.POINTER(Run), vp, vp, vp, vp]),
         "fpt_render_records": (C.c_int32, [vp, C.POINTER(Run), vp, C.c_uint32, vp, vp, vp]),

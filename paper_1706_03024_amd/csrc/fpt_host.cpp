@@ -129,6 +129,9 @@ struct fpt_scene {
     uint32_t* d_sjobs = nullptr;  // deferred pinhole connections, kSjobSlice entries per wave
     size_t sjob_waves = 0;        // waves d_sjobs has slices for
     uint32_t* d_sjob_counts = nullptr;
+    bool timing = false;             // record events around launches (fpt_scene_set_timing)
+    std::vector<hipEvent_t> events;  // 3 per timed render: transport start, end, deferred end
+    int timed = 0;
     fpt_tune tune;
     std::vector<float> h_st, h_cdf, h_rho;
     std::vector<int> h_line_bin;
@@ -732,6 +735,7 @@ void fpt_scene_destroy(fpt_scene* sc) {
     if (sc->d_partials) (void)hipFree(sc->d_partials);
     if (sc->d_sjobs) (void)hipFree(sc->d_sjobs);
     if (sc->d_sjob_counts) (void)hipFree(sc->d_sjob_counts);
+    for (hipEvent_t e : sc->events) (void)hipEventDestroy(e);
     delete sc;
 }
 
@@ -774,6 +778,32 @@ int32_t fpt_film_shape(const fpt_scene* sc, uint32_t batches, int64_t dims[5], i
 }
 
 int32_t fpt_grad_param_count(const fpt_scene* sc) { return sc ? sc->np : set_err(FPT_E_INVALID, "NULL scene"); }
+
+int32_t fpt_scene_set_timing(fpt_scene* sc, int32_t enable) {
+    if (!sc) return set_err(FPT_E_INVALID, "NULL scene");
+    sc->timing = enable != 0;
+    sc->timed = 0;
+    return FPT_OK;
+}
+
+int32_t fpt_scene_timing(fpt_scene* sc, int32_t* renders, float* transport_ms, float* deferred_ms) {
+    if (!sc || !renders || !transport_ms || !deferred_ms) return set_err(FPT_E_INVALID, "NULL argument");
+    double t = 0.0, d = 0.0;
+    for (int k = 0; k < sc->timed; ++k) {
+        hipEvent_t* ev = &sc->events[(size_t)k * 3];
+        HIP_TRY(hipEventSynchronize(ev[2]), "hipEventSynchronize");
+        float a = 0.f, b = 0.f;
+        HIP_TRY(hipEventElapsedTime(&a, ev[0], ev[1]), "hipEventElapsedTime");
+        HIP_TRY(hipEventElapsedTime(&b, ev[1], ev[2]), "hipEventElapsedTime");
+        t += a;
+        d += b;
+    }
+    *renders = sc->timed;
+    *transport_ms = sc->timed ? (float)(t / sc->timed) : 0.f;
+    *deferred_ms = sc->timed ? (float)(d / sc->timed) : 0.f;
+    sc->timed = 0;
+    return FPT_OK;
+}
 
 int32_t fpt_scene_set_tune(fpt_scene* sc, const fpt_tune* tune) {
     if (!sc) return set_err(FPT_E_INVALID, "NULL scene");
@@ -843,8 +873,21 @@ int32_t fpt_render(fpt_scene* sc, const fpt_run* run, float* film, uint64_t* tal
     }
     HIP_TRY(launch_zero_u64(sc->d_counter, queue_words(), s), "zero queue");
     if (escape) HIP_TRY(launch_zero_u32(sc->d_counts, n_counts, s), "zero counts");
+    hipEvent_t* ev = nullptr;
+    if (sc->timing && sc->timed < FPT_MAX_TIMED_RENDERS) {
+        while (sc->events.size() < (size_t)(sc->timed + 1) * 3) {
+            hipEvent_t e;
+            HIP_TRY(hipEventCreate(&e), "hipEventCreate");
+            sc->events.push_back(e);
+        }
+        ev = &sc->events[(size_t)sc->timed * 3];
+        ++sc->timed;
+    }
+    if (ev) HIP_TRY(hipEventRecord(ev[0], s), "hipEventRecord");
     HIP_TRY(launch_transport(P, Bf, MODE_FWD, grid, block, s), "transport launch");
+    if (ev) HIP_TRY(hipEventRecord(ev[1], s), "hipEventRecord");
     if (defer) HIP_TRY(launch_splat_jobs(P, Bf, (int)waves, s), "deferred splats");
+    if (ev) HIP_TRY(hipEventRecord(ev[2], s), "hipEventRecord");
     if (escape) HIP_TRY(launch_finalize_counts(sc->d_counts, film, n_counts, P.wscale, s), "finalize");
     return FPT_OK;
 }

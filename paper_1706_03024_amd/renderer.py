@@ -83,6 +83,16 @@ class Scene:
                       block_min_vertices, block_segments)
         check(lib().fpt_scene_set_tune(self._h, C.byref(t)))
 
+    def set_timing(self, enable=True):
+        """fpt_scene_set_timing: record launch events in later renders."""
+        check(lib().fpt_scene_set_timing(self._h, 1 if enable else 0))
+
+    def timing(self):
+        """fpt_scene_timing: (renders, mean transport ms, mean deferred-connection ms)."""
+        n, t, d = C.c_int32(), C.c_float(), C.c_float()
+        check(lib().fpt_scene_timing(self._h, C.byref(n), C.byref(t), C.byref(d)))
+        return n.value, t.value, d.value
+
     def tables(self):
         d = self.desc
         N = d["grid"]["n_bins"]
