@@ -184,7 +184,7 @@ typedef struct {
 
 /* Launch shape knobs; all-zero = library defaults.  Results never depend on them. */
 typedef struct {
-    int32_t block_threads;  /* 64..1024, multiple of 64 */
+    int32_t block_threads;  /* 64..256, multiple of 64 */
     int32_t blocks_per_cu;  /* persistent blocks per compute unit */
     int32_t refill_lanes;   /* a wave refills dead lanes once this many are dead (1..64;
                                default 48 with a camera, 60 with escape sensors, 8 batched) */
@@ -194,6 +194,8 @@ typedef struct {
                                    64 batched) */
     int32_t block_segments; /* paths per block round: 1, 2 or 4 (default 4, batched 2); paths
                                whose last round ran full width always get a whole wave */
+    int32_t wide_rounds;    /* forward renders: such paths walk 128 vertices per round
+                               (0 default = on, 1 on, -1 off) */
 } fpt_tune;
 
 /* Per-path replay record (fp32 path state at exit). */

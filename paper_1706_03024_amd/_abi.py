@@ -98,7 +98,8 @@ class Run(C.Structure):
 class Tune(C.Structure):
     _fields_ = [("block_threads", C.c_int32), ("blocks_per_cu", C.c_int32),
                 ("refill_lanes", C.c_int32), ("chunk_paths", C.c_int32),
-                ("block_min_vertices", C.c_int32), ("block_segments", C.c_int32)]
+                ("block_min_vertices", C.c_int32), ("block_segments", C.c_int32),
+                ("wide_rounds", C.c_int32)]
 
 
 class PathRecord(C.Structure):

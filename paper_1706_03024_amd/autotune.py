@@ -18,7 +18,7 @@ from ._abi import check, lib
 
 DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_cache.json")
 FIELDS = ("block_threads", "blocks_per_cu", "refill_lanes", "chunk_paths", "block_min_vertices",
-          "block_segments")
+          "block_segments", "wide_rounds")
 
 
 def device_tag():
@@ -68,5 +68,5 @@ def autotune(name, scene=None, run=None, batch=None, cache_path=DEFAULT_CACHE, f
         except OSError:
             pass
     if scene is not None:
-        scene.set_tune(**{f: best[f] for f in FIELDS})
+        scene.set_tune(**{f: best.get(f, 0) for f in FIELDS})
     return best

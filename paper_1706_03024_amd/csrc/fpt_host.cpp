@@ -541,6 +541,7 @@ void fill_run(const fpt_scene* sc, const fpt_run* run, uint32_t B, KParams* P) {
     P->hist_words = hw <= 8192 ? (int)hw : 0;
     P->block_min_v = sc->tune.block_min_vertices > 0 ? (uint32_t)sc->tune.block_min_vertices : (pin ? 2u : 8u);
     P->max_segments = sc->tune.block_segments > 0 ? sc->tune.block_segments : 4;
+    P->wide_rounds = sc->tune.wide_rounds >= 0 ? 1 : 0;
 }
 
 int32_t ensure_scratch(fpt_scene* sc, size_t counts, size_t partials) {
@@ -818,6 +819,7 @@ int32_t fpt_scene_set_tune(fpt_scene* sc, const fpt_tune* tune) {
     if (tune->block_segments != 0 && tune->block_segments != 1 && tune->block_segments != 2 &&
         tune->block_segments != 4)
         return set_err(FPT_E_RANGE, "block_segments must be 0, 1, 2 or 4");
+    if (tune->wide_rounds < -1 || tune->wide_rounds > 1) return set_err(FPT_E_RANGE, "wide_rounds must be -1, 0 or 1");
     sc->tune = *tune;
     return FPT_OK;
 }

@@ -75,6 +75,7 @@ struct KParams {
     int refill_lanes;
     uint32_t block_min_v;  // paths with at least this many vertices walk in wave blocks
     int max_segments;      // long paths served per block round: 1, 2 or 4
+    int wide_rounds;       // forward: deep paths walk 128 vertices per round
 };
 
 struct KBuffers {

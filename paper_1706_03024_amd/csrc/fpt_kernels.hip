@@ -812,6 +812,126 @@ DEV void block_walk(const KParams& P, const KBuffers& B, const uint32_t* T, cons
     }
 }
 
+// A deep path in a forward render (its last round ran the whole wave) walks
+// 128 vertices per round: lane k draws vertices v+1+k and v+65+k.  The second
+// half's generator and direction work is independent of the first half, so
+// the two interleave; its positions chain from the first half's last vertex
+// exactly as a following 64-lane round would, so the result is the same as
+// two consecutive rounds (and the second half counts only if the first one
+// committed all 64 vertices).
+template <int GEOM>
+DEV void deep_half(const KParams& P, const Lane& Q, uint32_t v0, uint32_t lane, const float* wprev,
+                   const float* xbase, float* wn, float* xk, float* pk, float* win, bool& stop_out) {
+    const uint32_t vk = v0 + 1u + lane;
+    const uint4 r = philox(Q.pid, vk, 0u, 0u, P.key0, P.key1);
+    const float u0 = u24(r.x), u1 = u24(r.y), u2 = u24(r.z), u3 = u24(r.w);
+    const float tk = -__logf(1.f - u0) * Q.inv;
+    const bool scat = u1 * Q.st < Q.ss;
+    float sp, cp;
+    sincos_rev(u3, &sp, &cp);
+    const float ct = 1.f - 2.f * u2, stt = 2.f * fsqrt(u2 * (1.f - u2));
+    wn[0] = stt * cp;
+    wn[1] = stt * sp;
+    wn[2] = ct;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const float up = wave_shr1(wn[c]);
+        win[c] = lane == 0 ? wprev[c] : up;
+    }
+    const float seg3[3] = {tk * win[0], tk * win[1], tk * win[2]};
+    float s0 = seg3[0], s1 = seg3[1], s2 = seg3[2];
+#define FPT_SCAN3(D) s0 += row_shr<D>(s0); s1 += row_shr<D>(s1); s2 += row_shr<D>(s2);
+    FPT_SCAN3(1)
+    FPT_SCAN3(2)
+    FPT_SCAN3(4)
+    FPT_SCAN3(8)
+#undef FPT_SCAN3
+    float b0 = xbase[0], b1 = xbase[1], b2 = xbase[2];
+    const int chunk = (int)(lane >> 4);
+    const float a15[3] = {rl(s0, 15), rl(s1, 15), rl(s2, 15)};
+    const float a31[3] = {rl(s0, 31), rl(s1, 31), rl(s2, 31)};
+    const float a47[3] = {rl(s0, 47), rl(s1, 47), rl(s2, 47)};
+    if (chunk > 0) { b0 += a15[0]; b1 += a15[1]; b2 += a15[2]; }
+    if (chunk > 1) { b0 += a31[0]; b1 += a31[1]; b2 += a31[2]; }
+    if (chunk > 2) { b0 += a47[0]; b1 += a47[1]; b2 += a47[2]; }
+    pk[0] = b0 + (s0 - seg3[0]);
+    pk[1] = b1 + (s1 - seg3[1]);
+    pk[2] = b2 + (s2 - seg3[2]);
+    xk[0] = b0 + s0;
+    xk[1] = b1 + s1;
+    xk[2] = b2 + s2;
+    const float dif = medium_exit<GEOM>(P, pk, win, Q.sc, Q.sr2);
+    stop_out = !(tk < dif) || !scat || (Q.nsc + (vk - Q.v) > P.max_scatter) || (vk >= kMaxPathVertices);
+    // the rr bits of the vertex's own uniforms, for its camera connection
+    xk[3] = __uint_as_float(rr_bits(r));
+}
+
+template <int GEOM>
+DEV void deep_round(const KParams& P, const KBuffers& B, const uint32_t* T, const KSphere* SP,
+                    uint32_t* tally, Lane& L, int j, uint32_t lane, bool pinhole, Counters& cnt, bool& full,
+                    SplatQ& q, bool exhausted) {
+    Lane Q;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        Q.x[c] = rl(L.x[c], j);
+        Q.w[c] = rl(L.w[c], j);
+        Q.sc[c] = rl(L.sc[c], j);
+    }
+    Q.sr2 = rl(L.sr2, j);
+    Q.st = rl(L.st, j);
+    Q.inv = rl(L.inv, j);
+    Q.ss = rl(L.ss, j);
+    Q.lam = rli(L.lam, j);
+    Q.comp = rli(L.comp, j);
+    Q.pid = rlu(L.pid, j);
+    Q.v = rlu(L.v, j);
+    Q.nsc = rlu(L.nsc, j);
+    Q.batch = rlu(L.batch, j);
+    float wn1[3], x1[4], p1[3], win1[3], wn2[3], x2[4], p2[3], win2[3];
+    bool st1, st2;
+    deep_half<GEOM>(P, Q, Q.v, lane, Q.w, Q.x, wn1, x1, p1, win1, st1);
+    // the second half starts from the state after the first half's vertex 64
+    const float w64[3] = {rl(wn1[0], 63), rl(wn1[1], 63), rl(wn1[2], 63)};
+    const float x64[3] = {rl(x1[0], 63), rl(x1[1], 63), rl(x1[2], 63)};
+    deep_half<GEOM>(P, Q, Q.v + 64u, lane, w64, x64, wn2, x2, p2, win2, st2);
+    const uint64_t sm1 = __ballot(st1), sm2 = __ballot(st2);
+    const int k1 = sm1 ? (__ffsll((unsigned long long)sm1) - 1) : 64;
+    const int k2 = k1 < 64 ? 0 : (sm2 ? (__ffsll((unsigned long long)sm2) - 1) : 64);
+    const bool m1 = (int)lane < k1, m2 = (int)lane < k2;
+    cnt.vertices += (uint32_t)m1 + (uint32_t)m2;
+    cnt.scatters += (uint32_t)m1 + (uint32_t)m2;
+    if constexpr (GEOM == FPT_GEOM_BOX) {
+        if (pinhole) {
+            const bool dep = !(P.fluo_only && Q.comp == 0);
+            const uint32_t wb = (uint32_t)Q.lam | (Q.batch << 16);
+            splat_defer(B, q, m1 && dep, x1, sq_word_a(__float_as_uint(x1[3]), PEND_MEDIUM, 0, Q.comp), wb,
+                        exhausted);
+            sq_drain(P, B.film, T, SP, tally, q, cnt, lane, false);
+            if (k2 > 0) {
+                splat_defer(B, q, m2 && dep, x2, sq_word_a(__float_as_uint(x2[3]), PEND_MEDIUM, 0, Q.comp), wb,
+                            exhausted);
+            }
+        }
+    }
+    const int k = k1 + k2;
+    full = k == 128;
+    if (k > 0) {
+        const int u = (k2 > 0 ? k2 : k1) - 1;
+        const float nx0 = k2 > 0 ? rl(x2[0], u) : rl(x1[0], u);
+        const float nx1 = k2 > 0 ? rl(x2[1], u) : rl(x1[1], u);
+        const float nx2 = k2 > 0 ? rl(x2[2], u) : rl(x1[2], u);
+        const float nw0 = k2 > 0 ? rl(wn2[0], u) : rl(wn1[0], u);
+        const float nw1 = k2 > 0 ? rl(wn2[1], u) : rl(wn1[1], u);
+        const float nw2 = k2 > 0 ? rl(wn2[2], u) : rl(wn1[2], u);
+        if ((int)lane == j) {
+            L.x[0] = nx0; L.x[1] = nx1; L.x[2] = nx2;
+            L.w[0] = nw0; L.w[1] = nw1; L.w[2] = nw2;
+            L.v += (uint32_t)k;
+            L.nsc += (uint32_t)k;
+        }
+    }
+}
+
 // -------------------------------------------------------------------------
 // Per-wave context and per-lane walk state, shared by the single-scene and the
 // batched persistent kernels.
@@ -889,10 +1009,24 @@ DEV void advance(const KParams& P, const KBuffers& B, const WaveCtx& C, WalkStat
                                      L.st > 0.f && (P.exc_scatter || L.nem > 0u) &&
                                      (pass == 0 || full));
             if (!elig) break;
+            // after the first pass every eligible path has just run a full round
+            const uint64_t deepm = pass == 0 ? dm : elig;
             while (elig) {  // each round takes up to four long paths off `elig`
+                if constexpr (MODE == MODE_FWD) {
+                    const uint64_t ed = P.wide_rounds ? (elig & deepm) : 0ull;
+                    if (ed) {
+                        const int j = __ffsll((unsigned long long)ed) - 1;
+                        elig &= ~(1ull << j);
+                        bool fj = false;
+                        deep_round<GEOM>(P, B, T, SP, tally, L, j, lane, pinhole, cnt, fj, W.q, exhausted);
+                        if ((int)lane == j) full = fj;
+                        if constexpr (DEFER) sq_drain(P, B.film, T, SP, tally, W.q, cnt, lane, false);
+                        continue;
+                    }
+                }
                 block_walk<GEOM, MODE>(P, B, T, SP, tally, L, elig, lane, pinhole, cnt,
                                        ADJ ? A.S - lane : nullptr, ADJ ? A.Gx : nullptr, G, full, W.q,
-                                       exhausted, dm);
+                                       exhausted, deepm);
                 if constexpr (DEFER) sq_drain(P, B.film, T, SP, tally, W.q, cnt, lane, false);
             }
         }

@@ -78,9 +78,9 @@ class Scene:
             None if s is None else s.ctypes.data))
 
     def set_tune(self, block_threads=0, blocks_per_cu=0, refill_lanes=0, chunk_paths=0,
-                 block_min_vertices=0, block_segments=0):
+                 block_min_vertices=0, block_segments=0, wide_rounds=0):
         t = _abi.Tune(block_threads, blocks_per_cu, refill_lanes, chunk_paths,
-                      block_min_vertices, block_segments)
+                      block_min_vertices, block_segments, wide_rounds)
         check(lib().fpt_scene_set_tune(self._h, C.byref(t)))
 
     def set_timing(self, enable=True):
@@ -198,7 +198,8 @@ class Batch:
         if tune is not None:
             t = _abi.Tune(tune.get("block_threads", 0), tune.get("blocks_per_cu", 0),
                           tune.get("refill_lanes", 0), tune.get("chunk_paths", 0),
-                          tune.get("block_min_vertices", 0), tune.get("block_segments", 0))
+                          tune.get("block_min_vertices", 0), tune.get("block_segments", 0),
+                          tune.get("wide_rounds", 0))
         h = C.c_void_p()
         check(lib().fpt_batch_create(self._descs, self._runs, n, None if t is None else C.byref(t),
                                      C.byref(h)))

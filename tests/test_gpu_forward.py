@@ -286,8 +286,9 @@ def test_splat_roulette_and_fluorescence_only():
 @pytest.mark.parametrize("scene_name", ["slab", "box"])
 def test_block_rounds_are_width_independent(scene_name):
     """Long paths walk in wave blocks of 64, 32 or 16 lanes depending on how
-    many share a wave; the arithmetic is defined in 16-vertex chunks, so every
-    launch shape and segment count gives bit-identical integer tallies."""
+    many share a wave, or 128 vertices per round when deep in a medium; the
+    arithmetic is defined in 16-vertex chunks, so every launch shape, segment
+    count and round width gives bit-identical integer tallies."""
     import torch
     fpt = _fpt()
     if scene_name == "slab":
@@ -301,7 +302,8 @@ def test_block_rounds_are_width_independent(scene_name):
     outs = []
     for tune in ({"block_segments": 1}, {"block_segments": 4},
                  {"block_segments": 2, "block_threads": 64, "refill_lanes": 1},
-                 {"block_segments": 4, "block_threads": 128, "refill_lanes": 40}):
+                 {"block_segments": 4, "block_threads": 128, "refill_lanes": 40},
+                 {"block_segments": 4, "wide_rounds": -1}, {"block_segments": 1, "wide_rounds": -1}):
         sc.set_tune(**tune)
         t = fpt.new_tallies()
         f = sc.render(run, tallies=t)
