@@ -194,8 +194,10 @@ typedef struct {
                                    64 batched) */
     int32_t block_segments; /* paths per block round: 1, 2 or 4 (default 4, batched 2); paths
                                whose last round ran full width always get a whole wave */
-    int32_t wide_rounds;    /* forward renders: such paths walk 128 vertices per round
-                               (0 default = on, 1 on, -1 off) */
+    int32_t wide_rounds;    /* forward renders: such paths walk 128 vertices per round;
+                               -1 off, 1 a path counts as deep after any full round,
+                               2 only after a full round of the whole wave (0 default:
+                               1 with a camera and batched, 2 with escape sensors) */
 } fpt_tune;
 
 /* Per-path replay record (fp32 path state at exit). */

@@ -541,7 +541,7 @@ void fill_run(const fpt_scene* sc, const fpt_run* run, uint32_t B, KParams* P) {
     P->hist_words = hw <= 8192 ? (int)hw : 0;
     P->block_min_v = sc->tune.block_min_vertices > 0 ? (uint32_t)sc->tune.block_min_vertices : (pin ? 2u : 8u);
     P->max_segments = sc->tune.block_segments > 0 ? sc->tune.block_segments : 4;
-    P->wide_rounds = sc->tune.wide_rounds >= 0 ? 1 : 0;
+    P->wide_rounds = sc->tune.wide_rounds < 0 ? 0 : (sc->tune.wide_rounds > 0 ? sc->tune.wide_rounds : (pin ? 1 : 2));
 }
 
 int32_t ensure_scratch(fpt_scene* sc, size_t counts, size_t partials) {
@@ -650,6 +650,7 @@ int32_t batch_build_items(fpt_batch* bt) {
         p.refill_lanes = refill;
         p.block_min_v = bmin;
         p.max_segments = segs;
+        p.wide_rounds = bt->tune.wide_rounds < 0 ? 0 : (bt->tune.wide_rounds > 0 ? bt->tune.wide_rounds : 1);
     }
     HIP_TRY(hipMemcpy(bt->d_params, bt->params.data(), sizeof(KParams) * bt->n, hipMemcpyHostToDevice),
             "upload params");
@@ -819,7 +820,7 @@ int32_t fpt_scene_set_tune(fpt_scene* sc, const fpt_tune* tune) {
     if (tune->block_segments != 0 && tune->block_segments != 1 && tune->block_segments != 2 &&
         tune->block_segments != 4)
         return set_err(FPT_E_RANGE, "block_segments must be 0, 1, 2 or 4");
-    if (tune->wide_rounds < -1 || tune->wide_rounds > 1) return set_err(FPT_E_RANGE, "wide_rounds must be -1, 0 or 1");
+    if (tune->wide_rounds < -1 || tune->wide_rounds > 2) return set_err(FPT_E_RANGE, "wide_rounds must be -1..2");
     sc->tune = *tune;
     return FPT_OK;
 }
@@ -1111,43 +1112,58 @@ int32_t fpt_autotune(fpt_scene* sc, const fpt_run* run, fpt_batch* bt, fpt_tune*
         for (int b : blocks)
             for (int r : {16, 32, 48, 60})
                 for (int m : {1, 2, 8})
-                    for (int g : {1, 2, 4}) cand.push_back(fpt_tune{b, 0, r, 0, m, g});
+                    for (int g : {2, 4})
+                        for (int wr : {1, 2}) cand.push_back(fpt_tune{b, 0, r, 0, m, g, wr});
     } else {
         for (int b : blocks)
             for (int r : {8, 32})
                 for (int m : {16, 64})
                     for (int g : {1, 2})
-                        for (int c : {1024, 4096}) cand.push_back(fpt_tune{b, 0, r, c, m, g});
+                        for (int c : {1024, 4096}) cand.push_back(fpt_tune{b, 0, r, c, m, g, 0});
     }
     float best = 1e30f;
     fpt_tune best_t = saved;
     int32_t rc = FPT_OK;
-    for (const fpt_tune& t : cand) {
+    // one candidate: `reps` renders back to back after one untimed render, mean ms
+    auto time_cand = [&](const fpt_tune& t, int reps, float* ms_out) -> int32_t {
+        int32_t r = FPT_OK;
         if (sc) {
             sc->tune = t;
         } else {
             bt->tune = t;
-            if ((rc = batch_build_items(bt)) != FPT_OK) break;
+            if ((r = batch_build_items(bt)) != FPT_OK) return r;
         }
-        float ms_sum = 0.f;
-        for (int rep = 0; rep < 3 && rc == FPT_OK; ++rep) {
-            if (sc) rc = fpt_render(sc, run, film, nullptr, nullptr);
-            else rc = fpt_batch_render(bt, film, nullptr, nullptr);
-            if (rc != FPT_OK) break;
-            if (hipEventRecord(e0, nullptr) != hipSuccess) { rc = set_err(FPT_E_DEVICE, "event record"); break; }
-            if (sc) rc = fpt_render(sc, run, film, nullptr, nullptr);
-            else rc = fpt_batch_render(bt, film, nullptr, nullptr);
-            if (rc != FPT_OK) break;
-            (void)hipEventRecord(e1, nullptr);
-            (void)hipEventSynchronize(e1);
+        r = sc ? fpt_render(sc, run, film, nullptr, nullptr) : fpt_batch_render(bt, film, nullptr, nullptr);
+        if (r != FPT_OK) return r;
+        if (hipEventRecord(e0, nullptr) != hipSuccess) return set_err(FPT_E_DEVICE, "event record");
+        for (int rep = 0; rep < reps && r == FPT_OK; ++rep)
+            r = sc ? fpt_render(sc, run, film, nullptr, nullptr) : fpt_batch_render(bt, film, nullptr, nullptr);
+        if (r != FPT_OK) return r;
+        (void)hipEventRecord(e1, nullptr);
+        (void)hipEventSynchronize(e1);
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        *ms_out = ms / reps;
+        return FPT_OK;
+    };
+    // a short screen of every candidate, then the best few again with more
+    // renders, so the choice is not decided by one lucky measurement
+    std::vector<std::pair<float, size_t>> screen;
+    for (size_t i = 0; i < cand.size() && rc == FPT_OK; ++i) {
+        float ms = 0.f;
+        rc = time_cand(cand[i], 3, &ms);
+        screen.push_back({ms, i});
+    }
+    if (rc == FPT_OK) {
+        std::sort(screen.begin(), screen.end());
+        const size_t keep = std::min<size_t>(screen.size(), 6);
+        for (size_t k = 0; k < keep && rc == FPT_OK; ++k) {
             float ms = 0.f;
-            (void)hipEventElapsedTime(&ms, e0, e1);
-            ms_sum += ms;
-        }
-        if (rc != FPT_OK) break;
-        if (ms_sum / 3 < best) {
-            best = ms_sum / 3;
-            best_t = t;
+            rc = time_cand(cand[screen[k].second], 12, &ms);
+            if (rc == FPT_OK && ms < best) {
+                best = ms;
+                best_t = cand[screen[k].second];
+            }
         }
     }
     if (sc) sc->tune = saved;

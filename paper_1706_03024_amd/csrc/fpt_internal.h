@@ -75,7 +75,8 @@ struct KParams {
     int refill_lanes;
     uint32_t block_min_v;  // paths with at least this many vertices walk in wave blocks
     int max_segments;      // long paths served per block round: 1, 2 or 4
-    int wide_rounds;       // forward: deep paths walk 128 vertices per round
+    int wide_rounds;       // forward: deep paths walk 128 vertices per round (0 off); a path is
+                           // deep after any full round (1) or a full whole-wave round (2)
 };
 
 struct KBuffers {

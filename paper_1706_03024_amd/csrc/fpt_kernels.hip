@@ -559,7 +559,7 @@ DEV float medium_exit(const KParams& P, const float* x, const float* w, const fl
 template <int GEOM, int MODE>
 DEV void block_walk(const KParams& P, const KBuffers& B, const uint32_t* T, const KSphere* SP,
                     uint32_t* tally, Lane& L, uint64_t& elig, uint32_t lane, bool pinhole,
-                    Counters& cnt, float* Sw, float* Gxl, float* G, bool& full, SplatQ& q,
+                    Counters& cnt, float* Sw, float* Gxl, float* G, bool& full, bool& deep, SplatQ& q,
                     bool exhausted, uint64_t deepmask) {
     constexpr bool ADJ = (MODE == MODE_ADJ || MODE == MODE_REC_ADJ);
     constexpr bool REC = (MODE == MODE_REC || MODE == MODE_REC_ADJ);
@@ -794,7 +794,11 @@ DEV void block_walk(const KParams& P, const KBuffers& B, const uint32_t* T, cons
     }
     // a path that committed the whole width without stopping continues with
     // another round instead of an ordinary step, whatever the width was
-    if (myseg >= 0) full = ks_of == W;
+    if (myseg >= 0) {
+        full = ks_of == W;
+        // counted as deep after any full round, or only after a full round of the whole wave
+        deep = full && (P.wide_rounds == 1 || W == 64);
+    }
     if (myseg >= 0 && ks_of > 0) {
         L.x[0] = nx0; L.x[1] = nx1; L.x[2] = nx2;
         L.w[0] = nw0; L.w[1] = nw1; L.w[2] = nw2;
@@ -1000,6 +1004,7 @@ DEV void advance(const KParams& P, const KBuffers& B, const WaveCtx& C, WalkStat
     (void)lane;
     // ---- long paths: wave-cooperative blocks of up to 64 vertices each
     bool full = false;
+    bool deep = false;  // this iteration's last round of the path filled the whole wave
     const uint64_t dm = __ballot(W.deep);
     if constexpr (MODE != MODE_REC_ADJ) {
         // paths whose last block ran its full width without stopping go again,
@@ -1009,8 +1014,8 @@ DEV void advance(const KParams& P, const KBuffers& B, const WaveCtx& C, WalkStat
                                      L.st > 0.f && (P.exc_scatter || L.nem > 0u) &&
                                      (pass == 0 || full));
             if (!elig) break;
-            // after the first pass every eligible path has just run a full round
-            const uint64_t deepm = pass == 0 ? dm : elig;
+            // paths whose round in this iteration filled the whole wave
+            const uint64_t deepm = pass == 0 ? dm : __ballot(deep);
             while (elig) {  // each round takes up to four long paths off `elig`
                 if constexpr (MODE == MODE_FWD) {
                     const uint64_t ed = P.wide_rounds ? (elig & deepm) : 0ull;
@@ -1019,20 +1024,23 @@ DEV void advance(const KParams& P, const KBuffers& B, const WaveCtx& C, WalkStat
                         elig &= ~(1ull << j);
                         bool fj = false;
                         deep_round<GEOM>(P, B, T, SP, tally, L, j, lane, pinhole, cnt, fj, W.q, exhausted);
-                        if ((int)lane == j) full = fj;
+                        if ((int)lane == j) {
+                            full = fj;
+                            deep = fj;
+                        }
                         if constexpr (DEFER) sq_drain(P, B.film, T, SP, tally, W.q, cnt, lane, false);
                         continue;
                     }
                 }
                 block_walk<GEOM, MODE>(P, B, T, SP, tally, L, elig, lane, pinhole, cnt,
-                                       ADJ ? A.S - lane : nullptr, ADJ ? A.Gx : nullptr, G, full, W.q,
+                                       ADJ ? A.S - lane : nullptr, ADJ ? A.Gx : nullptr, G, full, deep, W.q,
                                        exhausted, deepm);
                 if constexpr (DEFER) sq_drain(P, B.film, T, SP, tally, W.q, cnt, lane, false);
             }
         }
     }
 
-    W.deep = full;
+    W.deep = deep;
     // ---- one step for every live lane: the light vertex of a path assigned in
     // this iteration, or the next vertex of a path in flight.  Both draw their
     // uniforms from the same Philox calls (counter (pid, vertex, call, 0)), so a

@@ -303,7 +303,8 @@ def test_block_rounds_are_width_independent(scene_name):
     for tune in ({"block_segments": 1}, {"block_segments": 4},
                  {"block_segments": 2, "block_threads": 64, "refill_lanes": 1},
                  {"block_segments": 4, "block_threads": 128, "refill_lanes": 40},
-                 {"block_segments": 4, "wide_rounds": -1}, {"block_segments": 1, "wide_rounds": -1}):
+                 {"block_segments": 4, "wide_rounds": -1}, {"block_segments": 1, "wide_rounds": -1},
+                 {"block_segments": 2, "wide_rounds": 2}):
         sc.set_tune(**tune)
         t = fpt.new_tallies()
         f = sc.render(run, tallies=t)
