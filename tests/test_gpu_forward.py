@@ -244,8 +244,10 @@ def test_cornell_full_size_sampled():
     total equals the sum of every path's deposited values."""
     import torch
     fpt = _fpt()
+    from paper_1706_03024_amd import autotune
     scene, run = workloads.cornell_config()
     sc = fpt.Scene(scene)
+    autotune.autotune("cornell-128-64spp", scene=sc, run=run, measure=False)  # the cached shape, if any
     film = sc.render(run)
     rec, _ = sc.records(run)
     torch.cuda.synchronize()
