@@ -158,6 +158,29 @@ def batched_form(steps, warmup):
             "instances": len(scenes), "tune": tune}
 
 
+def sweep_form(steps, warmup):
+    """The excitation scan of the paper's experiments: 81 dye-slab instances
+    (300-700 nm, 2^18 paths each) in one batched launch."""
+    import torch
+    import paper_1706_03024_amd as fpt
+    import workloads
+    scenes, runs = workloads.excitation_scan()
+    b = fpt.Batch(scenes, runs)
+    films = b.new_films()
+    tal = b.count_vertices()
+    for _ in range(warmup):
+        b.render(films)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        b.render(films)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / steps * 1e3
+    b.close()
+    return {"vertices": tal, "ms_per_step": ms, "vertices_per_s": tal / (ms / 1e3),
+            "instances": len(scenes)}
+
+
 def cpu_baseline(scene, run, target_s=12.0):
     """The oracle as it stands (single thread, fp64) on a bounded sample of the
     workload: the first paths of the same job, sized to roughly target_s; a
@@ -329,6 +352,7 @@ def main():
         b = batched_form(max(3, args.steps // 10), 1)
         if b is not None:
             extra["batched"] = b
+        extra["excitation_scan"] = sweep_form(max(3, args.steps // 5), 1)
     line["forms"] = extra
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(scene, run)

@@ -1006,6 +1006,9 @@ DEV void advance(const KParams& P, const KBuffers& B, const WaveCtx& C, WalkStat
     bool full = false;
     bool deep = false;  // this iteration's last round of the path filled the whole wave
     const uint64_t dm = __ballot(W.deep);
+    // a wave holding a deep path issues first on its SIMD while it walks blocks:
+    // such paths set the end of the launch
+    if (dm) __builtin_amdgcn_s_setprio(2);
     if constexpr (MODE != MODE_REC_ADJ) {
         // paths whose last block ran its full width without stopping go again,
         // up to kBlockPasses passes per iteration
@@ -1040,6 +1043,7 @@ DEV void advance(const KParams& P, const KBuffers& B, const WaveCtx& C, WalkStat
         }
     }
 
+    __builtin_amdgcn_s_setprio(0);
     W.deep = deep;
     // ---- one step for every live lane: the light vertex of a path assigned in
     // this iteration, or the next vertex of a path in flight.  Both draw their

@@ -1,0 +1,52 @@
+"""The paper's experiments (sec. 5) as batched sweeps, and the reduction its
+figures report: the fluorescent spectral power distribution (SPD),
+peak-normalised.
+
+A sweep is a list of escape-sensor instances rendered by one persistent
+launch (fpt_batch_*).  For camera films the SPD is averaged over the pixels
+that receive fluorescence before normalisation.  All work is on the device.
+"""
+from __future__ import annotations
+
+import torch
+
+from .renderer import Batch, new_tallies
+
+
+def run_sweep(scenes, runs, tune=None, tallies=False):
+    """Renders every instance of a sweep in one batched launch; returns the
+    escape films [n][2 comp][2 side][n_bins] (fractions of source photons)
+    and, if asked, the per-instance tallies."""
+    b = Batch(scenes, runs, tune=tune)
+    try:
+        films = b.new_films()
+        t = new_tallies(len(scenes)) if tallies else None
+        b.render(films, t)
+        torch.cuda.current_stream().synchronize()
+    finally:
+        b.close()
+    return (films, t) if tallies else films
+
+
+def fluorescent_spd(films):
+    """Escape films [n][2][2][N] -> fluorescent SPD [n][N]: component 1
+    (emitted at least once), reflected plus transmitted."""
+    return films[:, 1, 0, :] + films[:, 1, 1, :]
+
+
+def pinhole_spd(film):
+    """Camera film [B][2][H][W][N] -> fluorescent SPD [N]: component 1 summed
+    over parity batches, averaged over the pixels that receive any."""
+    f = film[:, 1].sum(0)                      # [H][W][N]
+    lit = f.sum(-1) > 0
+    n = int(lit.sum().item())
+    if n == 0:
+        return torch.zeros(f.shape[-1], dtype=f.dtype, device=f.device)
+    return f[lit].sum(0) / n
+
+
+def normalized(spd):
+    """Each spectrum divided by its peak (all-zero spectra stay zero)."""
+    peak = spd.amax(-1, keepdim=True)
+    return torch.where(peak > 0, spd / torch.where(peak > 0, peak, torch.ones_like(peak)),
+                       torch.zeros_like(spd))

@@ -1,0 +1,65 @@
+"""The paper's experiments as batched sweeps on the GPU: an excitation scan
+300-700 nm and a concentration sweep of a non-scattering dye slab against
+their closed forms (every instance), a scattering excitation scan against
+the oracle, and the peak-normalised SPD reduction."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from stats import check_z, escape_z
+from test_oracle_sweeps import slab_closed_form, sweep_z
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    torch.cuda.set_device(0)
+    yield
+    torch.cuda.synchronize()
+
+
+def test_excitation_scan_matches_closed_form():
+    from paper_1706_03024_amd import experiments as ex
+    n = 1 << 18
+    scenes, runs = workloads.excitation_scan(paths=n)
+    films, t = ex.run_sweep(scenes, runs, tallies=True)
+    f = films.cpu().numpy().astype(np.float64)
+    assert (t[:, 0].cpu().numpy() == n).all()
+    lams = [s["light"]["lines"][0][0] for s in scenes]
+    check_z(sweep_z(f, n, [(lx, 10.0) for lx in lams]), "GPU excitation scan vs closed form")
+    # the figure's reduction: yield follows the absorption band, peak-normalised SPDs
+    spd = ex.fluorescent_spd(films)
+    tot = spd.sum(-1).cpu().numpy()
+    expect = np.array([sum(map(np.sum, slab_closed_form(lx, 10.0))) for lx in lams])
+    assert int(np.argmax(tot)) == int(np.argmax(expect))
+    nz = ex.normalized(spd).cpu().numpy()
+    lit = tot > 1e-3
+    assert lit.sum() >= 10 and np.allclose(nz[lit].max(1), 1.0)
+
+
+def test_concentration_sweep_matches_closed_form():
+    from paper_1706_03024_amd import experiments as ex
+    n = 1 << 18
+    scenes, runs = workloads.concentration_sweep(paths=n)
+    f = ex.run_sweep(scenes, runs).cpu().numpy().astype(np.float64)
+    concs = [s["media"][0]["dyes"][0][1] for s in scenes]
+    check_z(sweep_z(f, n, [(490.0, c) for c in concs]), "GPU concentration sweep vs closed form")
+
+
+def test_scattering_excitation_scan_vs_oracle():
+    from paper_1706_03024_amd import experiments as ex
+    n_g, n_o = 1 << 19, 1 << 15
+    lams = [420.0, 470.0, 490.0, 510.0, 560.0]
+    scenes, runs = workloads.excitation_scan(lams, sigma_s=20.0, paths=n_g)
+    g = ex.run_sweep(scenes, runs).cpu().numpy().astype(np.float64)
+    z = []
+    for k, s in enumerate(scenes):
+        o = oracle.render(s, workloads.make_run(n_o, seed=99, instance=k))["film"][0]
+        z.append(escape_z(g[k], n_g, o, n_o))
+    check_z(np.concatenate(z), "scattering excitation scan: GPU vs oracle")

@@ -279,6 +279,41 @@ def batch_config(instances=None):
 
 
 # --------------------------------------------------------------------------
+# The paper's experiments as batched sweeps (sec. 5: one dye, its excitation
+# varied across the spectrum, and its concentration varied at fixed
+# illumination).  Each instance is a 1 mm slab of the dye's solution lit by a
+# normal beam and read by escape tallies; the instance key is its index.
+# --------------------------------------------------------------------------
+SWEEP_DYE = {"abs": (490.0, 20.0), "em": (520.0, 25.0), "epsilon": 7e4, "qy": 0.9}
+
+
+def sweep_slab(lambda_x, conc_uM, sigma_s=0.0, sigma_a_bg=0.01, d=1.0, n_bins=101):
+    return _one_medium({"kind": "slab", "z0": 0.0, "z1": d, "medium": 0}, sigma_s, sigma_a_bg,
+                       dyes=[conc_uM], light=_beam(lambda_x), n_bins=n_bins,
+                       absorption=gauss((*SWEEP_DYE["abs"], 1.0)),
+                       emission=gauss((*SWEEP_DYE["em"], 1.0)),
+                       epsilon=SWEEP_DYE["epsilon"], qy=SWEEP_DYE["qy"])
+
+
+def excitation_scan(lambdas=None, conc_uM=10.0, sigma_s=0.0, paths=1 << 18, seed=0):
+    """Excitation wavelengths 300-700 nm in 5 nm steps (81 instances)."""
+    if lambdas is None:
+        lambdas = [300.0 + 5.0 * i for i in range(81)]
+    scenes = [sweep_slab(lx, conc_uM, sigma_s) for lx in lambdas]
+    runs = [make_run(paths, seed=seed, instance=i) for i in range(len(scenes))]
+    return scenes, runs
+
+
+def concentration_sweep(concs=None, lambda_x=490.0, sigma_s=0.0, paths=1 << 18, seed=0):
+    """Concentrations 0.1-1000 uM, four per decade (17 instances)."""
+    if concs is None:
+        concs = [10.0 ** (-1.0 + 0.25 * i) for i in range(17)]
+    scenes = [sweep_slab(lambda_x, c, sigma_s) for c in concs]
+    runs = [make_run(paths, seed=seed, instance=i) for i in range(len(scenes))]
+    return scenes, runs
+
+
+# --------------------------------------------------------------------------
 # Closed-form test scenes.
 # --------------------------------------------------------------------------
 def _one_medium(geometry, sigma_s, sigma_a_bg, dyes=(), light=None, n_bins=101,
