@@ -45,6 +45,30 @@ def pinhole_spd(film):
     return f[lit].sum(0) / n
 
 
+def rebin(film, factor):
+    """Sums a fine spectral axis (last) onto a grid `factor` times coarser with
+    the same end points: coarse point k collects the fine points within half a
+    coarse spacing of it, a point on a boundary shared by two coarse points
+    going half to each (so the total is kept).  For a 1-nm grid of 300-800 nm
+    (501 points) and factor 5 this gives the 101-point grid."""
+    n = film.shape[-1]
+    if (n - 1) % factor:
+        raise ValueError("the fine grid does not refine the coarse one")
+    m = (n - 1) // factor + 1
+    w = torch.zeros((n, m), dtype=film.dtype, device=film.device)
+    h = factor / 2.0
+    for j in range(n):
+        # fine point j lies at coarse coordinate j / factor
+        for k in (j // factor, j // factor + 1):
+            if k < m:
+                dist = abs(j - k * factor)
+                if dist < h:
+                    w[j, k] = 1.0
+                elif dist == h:
+                    w[j, k] = 0.5
+    return film @ w
+
+
 def normalized(spd):
     """Each spectrum divided by its peak (all-zero spectra stay zero)."""
     peak = spd.amax(-1, keepdim=True)

@@ -1,7 +1,8 @@
 """The paper's experiments as batched sweeps on the GPU: an excitation scan
 300-700 nm and a concentration sweep of a non-scattering dye slab against
 their closed forms (every instance), a scattering excitation scan against
-the oracle, and the peak-normalised SPD reduction."""
+the oracle, the peak-normalised SPD reduction, and the paper's 1-nm
+spectral grid."""
 from __future__ import annotations
 
 import numpy as np
@@ -63,3 +64,22 @@ def test_scattering_excitation_scan_vs_oracle():
         o = oracle.render(s, workloads.make_run(n_o, seed=99, instance=k))["film"][0]
         z.append(escape_z(g[k], n_g, o, n_o))
     check_z(np.concatenate(z), "scattering excitation scan: GPU vs oracle")
+
+
+def test_fine_spectral_grid():
+    """A 1-nm grid (501 points, the paper's internal sampling): the GPU film
+    against the oracle on the same grid, and rebinned onto the 5-nm grid
+    against the GPU's own 101-point render (independent seeds)."""
+    import torch
+    import paper_1706_03024_amd as fpt
+    from paper_1706_03024_amd import experiments as ex
+    n_g, n_o = 1 << 20, 1 << 15
+    fine_scene = workloads.slab_scene(n_bins=501)
+    g, _ = fpt.render(fine_scene, workloads.make_run(n_g, seed=61))
+    c, _ = fpt.render(workloads.slab_scene(n_bins=101), workloads.make_run(n_g, seed=62))
+    torch.cuda.synchronize()
+    g64 = g.double()
+    o = oracle.render(fine_scene, workloads.make_run(n_o, seed=63))["film"][0]
+    check_z(escape_z(g64[0].cpu().numpy(), n_g, o, n_o), "1-nm grid: GPU vs oracle")
+    r = ex.rebin(g64, 5)[0].cpu().numpy()
+    check_z(escape_z(r, n_g, c.double()[0].cpu().numpy(), n_g), "1-nm grid rebinned vs 5-nm grid (GPU)")
