@@ -109,6 +109,9 @@ def lib():
         L.orc_render.restype = C.c_int32
         L.orc_render.argtypes = [C.POINTER(Scene), C.POINTER(Run), C.c_void_p, C.c_void_p,
                                  C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_uint32]
+        L.orc_render_camera.restype = C.c_int32
+        L.orc_render_camera.argtypes = [C.POINTER(Scene), C.POINTER(Run), C.c_void_p,
+                                        C.c_void_p, C.c_void_p, C.c_uint32]
         L.orc_film_size.restype = C.c_int64
         L.orc_film_size.argtypes = [C.POINTER(Scene), C.c_uint32]
         L.orc_n_params.restype = C.c_int32
@@ -293,6 +296,34 @@ def render(scene, run, film=True, grad_film=None, records=False, record_grad=Fal
         out["records"] = rec
     if rg is not None:
         out["record_grad"] = rg
+    return out
+
+
+def camera_paths(scene, spp):
+    """Path count of a camera-side render with spp samples per (pixel, bin)."""
+    se = scene["sensor"]
+    return spp * se["height"] * se["width"] * scene["grid"]["n_bins"]
+
+
+def render_camera(scene, run, film=True, records=False, max_vertices=0):
+    """Run the camera-side estimator (paths from the eye, light connected at
+    each collision in a dye medium).  run["total_paths"] must be
+    camera_paths(scene, spp).  Returns 'film' (fp64, film_shape; component 1
+    only), 'tallies' and optionally 'records'."""
+    L = lib()
+    sc = make_scene(scene)
+    ru = make_run(run)
+    B = max(1, run["parity_batches"])
+    f = np.zeros(film_shape(scene, B), np.float64) if film else None
+    t = np.zeros(N_TALLIES, np.uint64)
+    rec = np.zeros(run["path_count"], RECORD_DTYPE) if records else None
+    rc = L.orc_render_camera(C.byref(sc), C.byref(ru), _ptr(f), _ptr(t), _ptr(rec),
+                             max_vertices)
+    if rc != 0:
+        raise OracleError(L.orc_last_error().decode())
+    out = {"film": f, "tallies": t}
+    if rec is not None:
+        out["records"] = rec
     return out
 
 

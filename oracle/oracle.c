@@ -792,10 +792,13 @@ static void run_path(ctx_t* c, uint32_t pid, orc_record* rec, uint32_t max_verti
             double rho = t->rho[h.index * N + p.lam];
             upd_margin(&p.margin, fabs(u1 - rho));
             if (!(u1 < rho)) { exit_code = ORC_EXIT_WALL; break; }
+            T[ORC_T_WALL_REFLECT]++;
+            /* direct excitation only: a wall reflection before the emission is an
+             * elastic event at the excitation wavelength like a scatter */
+            if (!run->excitation_scatter && p.n_emit == 0) { exit_code = ORC_EXIT_EXCSCAT; break; }
             double n[3], t1[3];
             face_frame(h.index, n, t1);
             cos_dir(n, t1, u2, u3, p.w);
-            T[ORC_T_WALL_REFLECT]++;
             splat(c, &p, n, 0, rr_bits_of(r));
             continue;
         }
@@ -884,6 +887,271 @@ int32_t orc_render(const orc_scene* sc, const orc_run* run, double* film, uint64
     if (tallies)
         for (int i = 0; i < ORC_N_TALLIES; ++i) tallies[i] += local_tally[i];
     free(scratch_film);
+    free_tables(&t);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Camera-side estimator (sec. 4.1: paths start at the camera at the emission
+ * wavelength and the light is sampled only where a fluorescence emission is
+ * realised; sec. 4.3, eq. 12).
+ *
+ * One path per (sample s, pixel, emission bin k): a ray from the eye through
+ * a uniform point of the pixel enters the box through its open face and walks
+ * analogously at wavelength k (free flight eq. 6, isotropic scatter with
+ * probability sigma_s/sigma_t, Lambertian walls with probability rho(k)); any
+ * absorption ends it, a dye absorption included (one emission per path, K = 1),
+ * as do the light quad and the open face.  Every collision in a dye medium is
+ * a candidate emission vertex x_{n-1} of the paper's path: a uniform point x_n
+ * on the light is drawn, the light is connected directly (V = 1 inside the
+ * convex box, eq. 4 geometry term, eq. 5 transmittance at each line
+ * wavelength, Lambertian emitter of radiance 1/(pi A) per unit power) and the
+ * fluorescence source
+ *     Q = 1/(4 pi) sum_d QY_d pmf_d(k) sum_l w_l sigma_a,d(lambda_l) T_l cos_n / (pi r^2)
+ * (eq. 9 with F_f of eq. 10; w_l the light's line power fractions, summed
+ * exactly) is scored divided by sigma_t(k): the collision estimate of the
+ * radiance reaching the eye along the ray.  The pixel weight is
+ * parity_batches / spp: a uniform point of the pixel has direction density
+ * equal to the pinhole importance N_pix / (A_img cos^3), so no further factor
+ * enters.  The forward walk with excitation_scatter = 0 and max_emissions = 1
+ * estimates the same film component (comp 1). */
+
+static void camera_frame(const orc_scene* sc, ctx_t* c) {
+    cross3(sc->lu, sc->lv, c->qn);
+    normalize3(c->qn);
+    for (int i = 0; i < 3; ++i) c->cf[i] = sc->look[i] - sc->eye[i];
+    normalize3(c->cf);
+    cross3(c->cf, sc->up, c->cr);
+    normalize3(c->cr);
+    cross3(c->cr, c->cf, c->cu);
+    c->tany = tan(0.5 * sc->fov_y_deg * M_PI / 180.0);
+    c->tanx = c->tany * (double)sc->width / (double)sc->height;
+}
+
+/* Fluorescence source Q at the path's position for emission bin k, from one
+ * light point drawn with (ua, ub). */
+static double cam_source(ctx_t* c, path_t* p, int k, double ua, double ub) {
+    const orc_scene* sc = c->sc;
+    const tables_t* t = c->t;
+    int N = t->N, m = p->medium;
+    const orc_medium* md = &sc->media[m];
+    double xn[3], d[3];
+    for (int i = 0; i < 3; ++i) {
+        xn[i] = sc->lpos[i] + ua * sc->lu[i] + ub * sc->lv[i];
+        d[i] = xn[i] - p->x[i];
+    }
+    double r2 = dot3(d, d), r = sqrt(r2);
+    double cos_n = -dot3(c->qn, d) / r; /* the light emits along +qn */
+    upd_margin(&p->margin, fabs(cos_n));
+    if (!(cos_n > 0.0)) { c->tally[ORC_T_SPLAT_MISS]++; return 0.0; }
+    double wc[3] = {d[0] / r, d[1] / r, d[2] / r};
+    double len[ORC_MAX_SPHERES];
+    for (int s = 0; s < sc->n_spheres; ++s) len[s] = chord(p->x, wc, r, &sc->spheres[s], &p->margin);
+    double total = 0.0;
+    for (int l = 0; l < sc->n_lines; ++l) total += sc->line_power[l];
+    double sum = 0.0;
+    for (int l = 0; l < sc->n_lines; ++l) {
+        int bl = t->line_bin[l];
+        double tau = 0.0;
+        for (int s = 0; s < sc->n_spheres; ++s)
+            tau += t->sigma_t[sc->spheres[s].medium * N + bl] * len[s];
+        double conv = 0.0;
+        for (int j = 0; j < md->n_dyes; ++j) {
+            int dye = md->dye[j];
+            conv += t->sigma_a[(m * ORC_MAX_MEDIUM_DYES + j) * N + bl] * sc->dyes[dye].qy *
+                    t->pmf[dye * N + k];
+        }
+        sum += sc->line_power[l] / total * exp(-tau) * conv;
+    }
+    c->tally[ORC_T_SPLAT_HIT]++;
+    return sum * cos_n / (M_PI * r2) / (4.0 * M_PI);
+}
+
+static void run_camera_path(ctx_t* c, uint32_t pid, uint32_t spp, orc_record* rec,
+                            uint32_t max_vertices) {
+    const orc_scene* sc = c->sc;
+    const tables_t* t = c->t;
+    const orc_run* run = c->run;
+    uint64_t* T = c->tally;
+    int N = t->N, W = sc->width, H = sc->height;
+    rng_t rng;
+    rng.key[0] = (uint32_t)run->seed;
+    rng.key[1] = (uint32_t)(run->seed >> 32) ^ run->instance;
+    rng.pid = pid;
+    path_t p;
+    memset(&p, 0, sizeof p);
+    p.margin = INFINITY;
+    int k = (int)(pid % (uint32_t)N);
+    uint32_t pix = (pid / (uint32_t)N) % (uint32_t)(W * H);
+    uint32_t s = pid / ((uint32_t)N * (uint32_t)(W * H));
+    int px = (int)(pix % (uint32_t)W), py = (int)(pix / (uint32_t)W);
+    (void)spp;
+    p.batch = s % (run->parity_batches ? run->parity_batches : 1);
+    p.lam = k;
+    p.comp = 1;
+    p.region = -1;
+    p.medium = -1;
+    double L = scene_scale(sc);
+    int exit_code = -1;
+    uint32_t r[4], r1[4];
+    int64_t idx = ((((int64_t)p.batch * 2 + 1) * H + py) * W + px) * N + k;
+    double acc = 0.0;
+
+    /* vertex 0: the eye ray through a uniform point of the pixel */
+    draw(&rng, 0, 0, r);
+    double xi = 2.0 * (px + unif(r[0])) / W - 1.0;
+    double yi = 1.0 - 2.0 * (py + unif(r[1])) / H;
+    for (int i = 0; i < 3; ++i) p.w[i] = c->cf[i] + xi * c->tanx * c->cr[i] + yi * c->tany * c->cu[i];
+    normalize3(p.w);
+    T[ORC_T_PATHS]++;
+    T[ORC_T_VERTICES]++;
+    {
+        /* entry into the box from outside: the last of the three slab entries */
+        double t_in = -INFINITY, t_out = INFINITY;
+        int face = -1, inside = 1;
+        for (int a = 0; a < 3; ++a) {
+            if (p.w[a] == 0.0) {
+                if (sc->eye[a] < sc->box_lo[a] || sc->eye[a] > sc->box_hi[a]) inside = 0;
+                continue;
+            }
+            double t0 = (sc->box_lo[a] - sc->eye[a]) / p.w[a];
+            double t1 = (sc->box_hi[a] - sc->eye[a]) / p.w[a];
+            double tn = p.w[a] > 0.0 ? t0 : t1, tf = p.w[a] > 0.0 ? t1 : t0;
+            if (tn > t_in) { t_in = tn; face = p.w[a] > 0.0 ? 2 * a : 2 * a + 1; }
+            if (tf < t_out) t_out = tf;
+        }
+        int enters = inside && face == sc->open_face && t_in > 0.0 && t_in < t_out;
+        /* margin: the crossing of the open face's plane against that face's edges */
+        int oa = sc->open_face / 2;
+        double plane = (sc->open_face % 2) ? sc->box_hi[oa] : sc->box_lo[oa];
+        double tp = p.w[oa] != 0.0 ? (plane - sc->eye[oa]) / p.w[oa] : INFINITY;
+        if (isfinite(tp) && tp > 0.0)
+            for (int b = 0; b < 3; ++b) {
+                if (b == oa) continue;
+                double q = sc->eye[b] + tp * p.w[b];
+                double ext = sc->box_hi[b] - sc->box_lo[b];
+                upd_margin(&p.margin, fmin(fabs(q - sc->box_lo[b]), fabs(sc->box_hi[b] - q)) / ext);
+            }
+        if (!enters) {
+            exit_code = ORC_EXIT_ESC_T;
+        } else {
+            for (int i = 0; i < 3; ++i) p.x[i] = sc->eye[i] + t_in * p.w[i];
+            p.x[oa] = plane;
+        }
+    }
+
+    while (exit_code < 0) {
+        p.v++;
+        if (max_vertices && p.v >= max_vertices) { exit_code = ORC_EXIT_TRUNC; break; }
+        if (p.v >= (1u << 28)) { exit_code = ORC_EXIT_SCAP; break; }
+        T[ORC_T_VERTICES]++;
+        draw(&rng, p.v, 0, r);
+        double u0 = unif(r[0]), u1 = unif(r[1]), u2 = unif(r[2]), u3 = unif(r[3]);
+        double st = p.medium >= 0 ? t->sigma_t[p.medium * N + k] : 0.0;
+        double tf = st > 0.0 ? -log(1.0 - u0) / st : INFINITY;
+        hit_t h = next_surface(sc, p.x, p.w, p.region, 0);
+        upd_margin(&p.margin, h.margin);
+        if (isfinite(tf) && isfinite(h.d))
+            upd_margin(&p.margin, fabs(tf - h.d) / fmax(fmax(tf, h.d), L));
+        if (tf < h.d) {
+            for (int i = 0; i < 3; ++i) p.x[i] += tf * p.w[i];
+            const orc_medium* md = &sc->media[p.medium];
+            if (md->n_dyes > 0) {
+                /* a candidate emission vertex: connect to the light */
+                draw(&rng, p.v, 1, r1);
+                double q = cam_source(c, &p, k, unif(r1[0]), unif(r1[1]));
+                acc += c->wscale * q / st;
+            }
+            double sv = u1 * st;
+            double thr = md->sigma_s;
+            upd_margin(&p.margin, fabs(sv - thr) / st);
+            if (sv < thr) {
+                T[ORC_T_SCATTERS]++;
+                p.n_scatter++;
+                if (p.n_scatter > run->max_scatter) { exit_code = ORC_EXIT_SCAP; break; }
+                iso_dir(u2, u3, p.w);
+                continue;
+            }
+            thr += md->sigma_a_bg;
+            upd_margin(&p.margin, fabs(sv - thr) / st);
+            if (sv < thr || md->n_dyes == 0) { exit_code = ORC_EXIT_BG; break; }
+            /* a dye absorbs at the emission wavelength: a second emission ends the path */
+            T[ORC_T_DYE_ABS]++;
+            exit_code = ORC_EXIT_KCAP;
+            break;
+        }
+        double dd = h.d;
+        if (isfinite(dd)) {
+            for (int i = 0; i < 3; ++i) p.x[i] += dd * p.w[i];
+            if ((h.kind == SURF_WALL || h.kind == SURF_ESCAPE) && h.index >= 0)
+                p.x[h.index / 2] = (h.index % 2) ? sc->box_hi[h.index / 2] : sc->box_lo[h.index / 2];
+        }
+        if (h.kind == SURF_ESCAPE) { exit_code = ORC_EXIT_ESC_R; break; }
+        if (h.kind == SURF_LIGHT) { exit_code = ORC_EXIT_LIGHT; break; }
+        if (h.kind == SURF_WALL) {
+            double rho = t->rho[h.index * N + k];
+            upd_margin(&p.margin, fabs(u1 - rho));
+            if (!(u1 < rho)) { exit_code = ORC_EXIT_WALL; break; }
+            double n[3], t1[3];
+            face_frame(h.index, n, t1);
+            cos_dir(n, t1, u2, u3, p.w);
+            T[ORC_T_WALL_REFLECT]++;
+            continue;
+        }
+        T[ORC_T_CROSSINGS]++;
+        p.region = (h.kind == SURF_ENTER) ? h.index : -1;
+        p.medium = region_medium(sc, p.region);
+    }
+    if (acc != 0.0 && c->film) deposit(c, &p, idx, acc, NULL);
+    p.splat_sum = acc;
+    T[ORC_T_EXIT0 + exit_code]++;
+    if (rec) {
+        rec->n_vertices = p.v + (exit_code == ORC_EXIT_TRUNC ? 0u : 1u);
+        rec->n_scatter = p.n_scatter;
+        rec->n_emit = 0;
+        rec->exit_code = (uint32_t)exit_code;
+        rec->lambda = k;
+        rec->comp = 1;
+        rec->region = p.region;
+        memcpy(rec->pos, p.x, sizeof p.x);
+        memcpy(rec->dir, p.w, sizeof p.w);
+        rec->splat_sum = acc;
+        rec->margin = p.margin;
+    }
+}
+
+int32_t orc_render_camera(const orc_scene* sc, const orc_run* run, double* film,
+                          uint64_t* tallies, orc_record* rec, uint32_t max_vertices) {
+    g_err[0] = 0;
+    if (!sc || !run) return fail("null argument");
+    if (sc->geom != ORC_GEOM_BOX || sc->sensor != ORC_SENSOR_PINHOLE || sc->light != ORC_LIGHT_QUAD)
+        return fail("the camera-side estimator needs a box scene with a pinhole and a quad light");
+    uint64_t per_sample = (uint64_t)sc->width * (uint64_t)sc->height * (uint64_t)sc->n_bins;
+    if (per_sample == 0 || run->total_paths == 0 || run->total_paths % per_sample != 0)
+        return fail("total_paths must be spp * width * height * n_bins");
+    if (run->path_begin + run->path_count > run->total_paths)
+        return fail("path range outside total_paths");
+    if (run->total_paths > 0xFFFFFFFFull) return fail("total_paths exceeds 2^32");
+    uint32_t spp = (uint32_t)(run->total_paths / per_sample);
+    tables_t t;
+    if (build_tables(sc, &t)) return -1;
+    ctx_t c;
+    memset(&c, 0, sizeof c);
+    c.sc = sc;
+    c.run = run;
+    c.t = &t;
+    c.film = film;
+    uint64_t local_tally[ORC_N_TALLIES];
+    memset(local_tally, 0, sizeof local_tally);
+    c.tally = local_tally;
+    uint32_t B = run->parity_batches ? run->parity_batches : 1;
+    c.wscale = (double)B / (double)spp;
+    camera_frame(sc, &c);
+    for (uint64_t i = 0; i < run->path_count; ++i)
+        run_camera_path(&c, (uint32_t)(run->path_begin + i), spp, rec ? rec + i : NULL,
+                        max_vertices);
+    if (tallies)
+        for (int i = 0; i < ORC_N_TALLIES; ++i) tallies[i] += local_tally[i];
     free_tables(&t);
     return 0;
 }

@@ -116,7 +116,8 @@ typedef struct {
     uint64_t path_begin, path_count, total_paths;
     uint32_t max_emissions; /* K; 0xFFFFFFFF = unlimited */
     int32_t fluorescence_only;
-    int32_t excitation_scatter; /* 0: kill a path at its first scatter before emitting */
+    int32_t excitation_scatter; /* 0: end a path at its first scatter or wall reflection
+                                   before emitting (direct excitation only) */
     uint32_t parity_batches;    /* B >= 1: film slice = path_id % B */
     double splat_rr;            /* transmittance roulette threshold, 0 = off */
 } orc_run;
@@ -156,5 +157,21 @@ int32_t orc_tables(const orc_scene* sc, double* lambda, double* a_hat, double* e
 int32_t orc_render(const orc_scene* sc, const orc_run* run, double* film, uint64_t* tallies,
                    const double* gfilm, double* grad, orc_record* rec, double* rec_grad,
                    uint32_t max_vertices);
+
+/* Camera-side estimator (sec. 4.1, eq. 12): paths start at the eye at the
+ * emission wavelength and connect to the light at every collision in a dye
+ * medium (direct excitation, lines summed with their power fractions).  Box
+ * scenes with a pinhole and a quad light.  Path p of total_paths =
+ * spp * height * width * n_bins is (sample s, pixel (py, px), bin k) with
+ *   p = ((s * height + py) * width + px) * n_bins + k,
+ * and adds to film component 1 of slice s % parity_batches with weight
+ * parity_batches / spp.  Uses seed, instance, the path range, max_scatter and
+ * parity_batches of run.  Record fields as for orc_render (n_emit 0, comp 1,
+ * splat_sum = the path's deposit).  Exits: ESC_T the eye ray misses the open
+ * face, ESC_R the walk leaves through it, KCAP a dye absorbs at the emission
+ * wavelength, BG, WALL, LIGHT, SCAP, TRUNC as for orc_render.  Tallies
+ * SPLAT_HIT / SPLAT_MISS count light connections made / facing away. */
+int32_t orc_render_camera(const orc_scene* sc, const orc_run* run, double* film,
+                          uint64_t* tallies, orc_record* rec, uint32_t max_vertices);
 
 #endif
