@@ -79,7 +79,8 @@ enum { FPT_BASE_DECADIC = 0, FPT_BASE_NATURAL = 1 };
 
 /* Run flags. */
 #define FPT_FLAG_FLUORESCENCE_ONLY 1u  /* film records only paths that emitted (V_f, eq. 9) */
-#define FPT_FLAG_NO_EXCITATION_SCATTER 2u /* end a path at its first scatter before emitting */
+#define FPT_FLAG_NO_EXCITATION_SCATTER 2u /* direct excitation only: end a path at its first
+                                             scatter or wall reflection before emitting */
 
 /* Exit codes (one per path) and tally slots (uint64, accumulated). */
 enum { FPT_EXIT_ESC_R = 0, FPT_EXIT_ESC_T = 1, FPT_EXIT_BG = 2, FPT_EXIT_NONRAD = 3,
@@ -280,6 +281,36 @@ int32_t fpt_render_adjoint(fpt_scene* scene, const fpt_run* run, const float* gr
 int32_t fpt_render_records(fpt_scene* scene, const fpt_run* run, fpt_path_record* rec_dev,
                            uint32_t max_vertices, const float* grad_film_dev,
                            float* rec_grad_dev, void* hip_stream);
+
+/* Camera-side estimator (sec. 4.1: paths start at the camera at the emission
+ * wavelength and the light is sampled only where an emission is realised;
+ * sec. 4.3, eq. 12).  Box scenes with a pinhole.  total_paths must be
+ * spp * height * width * n_bins; path p is sample s, pixel (py, px), emission
+ * bin k with p = ((s * height + py) * width + px) * n_bins + k.  Each path
+ * walks analogously at bin k from the eye through a uniform point of its pixel
+ * (entering through the open face; free flight eq. 6, isotropic scatter,
+ * Lambertian walls); at every collision in a dye medium it draws one uniform
+ * point on the light and adds the directly excited fluorescence source
+ *   sum_d QY_d pmf_d(k) sum_l w_l sigma_a,d(lambda_l) T_l cos_n / (4 pi^2 r^2)
+ * over sigma_t(k) (w_l the lines' power fractions, T_l the transmittance at
+ * line l through every sphere).  Any absorption ends the walk (K = 1).  The
+ * path's sum, times parity_batches / spp, is added once to film component 1
+ * (film_dev, device, pinhole film shape, optional) of slice s % parity_batches;
+ * component 0 is never touched.  It estimates what fpt_render estimates in
+ * component 1 with FPT_FLAG_NO_EXCITATION_SCATTER and max_emissions = 1.
+ * Uses seed, instance, the path range, max_scatter and parity_batches of run.
+ * rec_dev (device, path_count records, optional) receives per-path records
+ * (n_emit 0, comp 1, splat_sum = the path's deposit); max_vertices > 0 ends
+ * paths after that many vertices (exit TRUNC).  Exits: ESC_T the eye ray
+ * misses the open face, ESC_R the walk leaves through it, KCAP a dye absorbs,
+ * BG, WALL, LIGHT, SCAP, TRUNC.  Tallies SPLAT_HIT / SPLAT_MISS count light
+ * connections made / facing away.  At least one of film_dev and rec_dev.
+ * FPT_E_UNSUPPORTED for other scenes, or if the table image exceeds LDS
+ * (160 KiB).  Timed like fpt_render when timing is on (deferred time 0).
+ * Asynchronous. */
+int32_t fpt_render_camera(fpt_scene* scene, const fpt_run* run, float* film_dev,
+                          uint64_t* tallies_dev, fpt_path_record* rec_dev,
+                          uint32_t max_vertices, void* hip_stream);
 
 /* Test hook: copies the fp32 tables the kernels use to host arrays (each
  * optional): sigma_t[n_media][n_bins], emis_cdf[n_dyes][n_bins],

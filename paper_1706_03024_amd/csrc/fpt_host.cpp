@@ -34,6 +34,10 @@ hipError_t batch_occupancy(const KBatch& Bt, int block, int* n);
 hipError_t launch_batch(const KBatch& Bt, int grid, int block, hipStream_t s);
 hipError_t launch_finalize_batch(const uint32_t* counts, float* films, const float* wscale,
                                  int hist_words, size_t n, hipStream_t s);
+size_t camera_lds_bytes(const KParams& P);
+hipError_t camera_occupancy(const KParams& P, bool rec, int block, int* blocks_per_cu);
+hipError_t launch_camera(const KParams& P, const KBuffers& B, bool rec, int grid, int block,
+                         hipStream_t s);
 }  // namespace fpt
 
 using namespace fpt;
@@ -279,6 +283,7 @@ int32_t build_tables(fpt_scene* sc) {
 
     // absorption peak-normalised on the grid; emission an area-normalised PMF
     std::vector<double> ahat((size_t)std::max(1, d.n_dyes) * N), cdf((size_t)std::max(1, d.n_dyes) * N);
+    std::vector<double> pmf((size_t)std::max(1, d.n_dyes) * N);
     for (int i = 0; i < d.n_dyes; ++i) {
         double peak = 0.0, area = 0.0;
         for (int k = 0; k < N; ++k) {
@@ -294,6 +299,7 @@ int32_t build_tables(fpt_scene* sc) {
         double run = 0.0;
         for (int k = 0; k < N; ++k) {
             ahat[(size_t)i * N + k] /= peak;
+            pmf[(size_t)i * N + k] = cdf[(size_t)i * N + k] / area;
             run += cdf[(size_t)i * N + k] / area;
             cdf[(size_t)i * N + k] = run;
         }
@@ -331,6 +337,9 @@ int32_t build_tables(fpt_scene* sc) {
     P.off_cdf = off; off += d.n_dyes * N;
     P.off_rho = off; off += 6 * N;
     P.off_kap = off; off += d.n_media * kap_stride * N;
+    const bool cam = d.geometry == FPT_GEOM_BOX && d.sensor == FPT_SENSOR_PINHOLE;
+    P.off_src = off; off += cam ? d.n_media * N * d.n_lines : 0;
+    P.off_csig = off; off += cam ? d.n_spheres * d.n_lines : 0;
     P.table_words = off;
     std::vector<uint32_t>& img = sc->image;
     img.assign((size_t)off, 0u);
@@ -404,6 +413,31 @@ int32_t build_tables(fpt_scene* sc) {
     }
     P.line_cum[d.n_lines - 1] = 1.0f;
     P.n_lines = d.n_lines;
+    if (cam) {
+        // camera-side source per (medium, emission bin, line): the line's power
+        // fraction times the light absorbed by each dye at the line and
+        // re-emitted into bin k (QY, emission PMF), over 4 pi (isotropic) and pi
+        // (Lambertian emitter of unit power per unit area)
+        for (int m = 0; m < d.n_media; ++m) {
+            const fpt_medium& md = d.media[m];
+            for (int k = 0; k < N; ++k)
+                for (int l = 0; l < d.n_lines; ++l) {
+                    double v = 0.0;
+                    for (int j = 0; j < md.n_dyes; ++j) {
+                        const int y = md.dye[j];
+                        const double sa = base * d.dyes[y].epsilon_M_cm * 1e-7 *
+                                          ahat[(size_t)y * N + P.line_bin[l]] * md.conc_uM[j];
+                        v += d.dyes[y].qy * pmf[(size_t)y * N + k] * sa;
+                    }
+                    v *= d.line_power[l] / tot / (4.0 * M_PI * M_PI);
+                    img[P.off_src + (m * N + k) * d.n_lines + l] = fbits((float)v);
+                }
+        }
+        for (int s = 0; s < d.n_spheres; ++s)
+            for (int l = 0; l < d.n_lines; ++l)
+                img[P.off_csig + s * d.n_lines + l] =
+                    fbits(sc->h_st[(size_t)d.spheres[s].medium * N + P.line_bin[l]]);
+    }
     // geometry
     P.geometry = d.geometry;
     P.body_medium = d.body_medium;
@@ -477,6 +511,8 @@ int32_t build_tables(fpt_scene* sc) {
         }
         P.inv_tanx = (float)(1.0 / tx);
         P.inv_tany = (float)(1.0 / ty);
+        P.tanx = (float)tx;
+        P.tany = (float)ty;
         P.W = d.width;
         P.H = d.height;
         P.splat_norm = (float)((double)d.width * d.height / (4.0 * tx * ty));
@@ -577,6 +613,20 @@ int32_t grid_for(fpt_scene* sc, const KParams& P, int mode, int block, uint64_t 
     const uint64_t full = (uint64_t)sc->n_cu * per_cu;
     const uint64_t need = (paths + block - 1) / block;
     *grid = (int)std::max<uint64_t>(1, std::min(full, need));
+    return FPT_OK;
+}
+
+// The three events of the next timed render (fpt_scene_set_timing), or null.
+int32_t timing_slot(fpt_scene* sc, hipEvent_t** ev) {
+    *ev = nullptr;
+    if (!sc->timing || sc->timed >= FPT_MAX_TIMED_RENDERS) return FPT_OK;
+    while (sc->events.size() < (size_t)(sc->timed + 1) * 3) {
+        hipEvent_t e;
+        HIP_TRY(hipEventCreate(&e), "hipEventCreate");
+        sc->events.push_back(e);
+    }
+    *ev = &sc->events[(size_t)sc->timed * 3];
+    ++sc->timed;
     return FPT_OK;
 }
 
@@ -877,15 +927,7 @@ int32_t fpt_render(fpt_scene* sc, const fpt_run* run, float* film, uint64_t* tal
     HIP_TRY(launch_zero_u64(sc->d_counter, queue_words(), s), "zero queue");
     if (escape) HIP_TRY(launch_zero_u32(sc->d_counts, n_counts, s), "zero counts");
     hipEvent_t* ev = nullptr;
-    if (sc->timing && sc->timed < FPT_MAX_TIMED_RENDERS) {
-        while (sc->events.size() < (size_t)(sc->timed + 1) * 3) {
-            hipEvent_t e;
-            HIP_TRY(hipEventCreate(&e), "hipEventCreate");
-            sc->events.push_back(e);
-        }
-        ev = &sc->events[(size_t)sc->timed * 3];
-        ++sc->timed;
-    }
+    if ((rc = timing_slot(sc, &ev)) != FPT_OK) return rc;
     if (ev) HIP_TRY(hipEventRecord(ev[0], s), "hipEventRecord");
     HIP_TRY(launch_transport(P, Bf, MODE_FWD, grid, block, s), "transport launch");
     if (ev) HIP_TRY(hipEventRecord(ev[1], s), "hipEventRecord");
@@ -950,6 +992,52 @@ int32_t fpt_render_records(fpt_scene* sc, const fpt_run* run, fpt_path_record* r
     Bf.rec_grad = rec_grad;
     HIP_TRY(launch_zero_u64(sc->d_counter, queue_words(), s), "zero queue");
     HIP_TRY(launch_transport(P, Bf, mode, grid, block, s), "records launch");
+    return FPT_OK;
+}
+
+int32_t fpt_render_camera(fpt_scene* sc, const fpt_run* run, float* film, uint64_t* tallies,
+                          fpt_path_record* rec, uint32_t max_vertices, void* stream) {
+    if (!sc || (!film && !rec)) return set_err(FPT_E_INVALID, "NULL argument");
+    const fpt_scene_desc& d = sc->desc;
+    if (d.geometry != FPT_GEOM_BOX || d.sensor != FPT_SENSOR_PINHOLE)
+        return set_err(FPT_E_UNSUPPORTED, "the camera-side estimator needs a box scene with a pinhole");
+    uint32_t B;
+    int32_t rc = check_run(sc, run, &B);
+    if (rc != FPT_OK) return rc;
+    const uint64_t per_sample = (uint64_t)d.width * (uint64_t)d.height * (uint64_t)d.n_bins;
+    if (run->total_paths % per_sample != 0)
+        return set_err(FPT_E_RANGE, "total_paths must be spp * width * height * n_bins");
+    if (run->path_count == 0) return FPT_OK;
+    hipStream_t s = (hipStream_t)stream;
+    KParams P;
+    fill_run(sc, run, B, &P);
+    P.wscale = (float)((double)B / (double)(run->total_paths / per_sample));
+    P.max_vertices = max_vertices;
+    P.refill_lanes = sc->tune.refill_lanes > 0 ? std::min(64, sc->tune.refill_lanes) : 32;
+    if (camera_lds_bytes(P) > 160u * 1024u)
+        return set_err(FPT_E_UNSUPPORTED, "table image of %d words exceeds LDS", P.table_words);
+    const bool records = rec != nullptr;
+    const int block = block_for(sc);
+    int per_cu = 0;
+    HIP_TRY(camera_occupancy(P, records, block, &per_cu), "occupancy query");
+    if (sc->tune.blocks_per_cu > 0) per_cu = std::min(per_cu, sc->tune.blocks_per_cu);
+    per_cu = std::max(per_cu, 1);
+    const uint64_t need = (run->path_count + block - 1) / block;
+    const int grid = (int)std::max<uint64_t>(1, std::min<uint64_t>((uint64_t)sc->n_cu * per_cu, need));
+    KBuffers Bf;
+    std::memset(&Bf, 0, sizeof Bf);
+    Bf.tables = sc->d_tables;
+    Bf.film = film;
+    Bf.tallies = tallies ? reinterpret_cast<unsigned long long*>(tallies) : nullptr;
+    Bf.counter = sc->d_counter;
+    Bf.rec = rec;
+    HIP_TRY(launch_zero_u64(sc->d_counter, 1, s), "zero path counter");
+    hipEvent_t* ev = nullptr;
+    if ((rc = timing_slot(sc, &ev)) != FPT_OK) return rc;
+    if (ev) HIP_TRY(hipEventRecord(ev[0], s), "hipEventRecord");
+    HIP_TRY(launch_camera(P, Bf, records, grid, block, s), "camera launch");
+    if (ev) HIP_TRY(hipEventRecord(ev[1], s), "hipEventRecord");
+    if (ev) HIP_TRY(hipEventRecord(ev[2], s), "hipEventRecord");
     return FPT_OK;
 }
 

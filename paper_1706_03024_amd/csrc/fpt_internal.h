@@ -41,6 +41,9 @@ struct KParams {
     int off_rho;    // float [6][N]
     int off_kap;    // float [n_media][kap_stride][N]: d sigma_a / d conc per slot
     int kap_stride;
+    // camera-side estimator (box + pinhole + quad light), at the end of the image:
+    int off_src;    // float [n_media][N][n_lines]: w_l sum_d QY_d pmf_d(k) sigma_a,d(lambda_l) / (4 pi^2)
+    int off_csig;   // float [n_spheres][n_lines]: sigma_t of sphere s's medium at line l
     int n_media, n_dyes, n_spheres, n_lines;
     KSphere spheres[FPT_MAX_SPHERES];
     float line_cum[FPT_MAX_LINES];
@@ -58,6 +61,7 @@ struct KParams {
     float lu_inv2, lv_inv2;
     float eye[3], cf[3], cr[3], cu[3];
     float inv_tanx, inv_tany;
+    float tanx, tany;
     int W, H;
     float splat_norm;  // N_pix / A_img
     int film_u32;      // film element indices fit 32 bits (deposits merge per wave)

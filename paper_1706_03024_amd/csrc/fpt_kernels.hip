@@ -225,12 +225,16 @@ DEV void snap_to_plane(const KParams& P, Lane& L, const Hit& h) {
     }
 }
 
-// Length of the segment x + t wc, t in [0, dist], inside a sphere.
+// Length of the segment x + t wc, t in [0, dist], inside a sphere.  The
+// half-chord squared is r^2 minus the squared distance of the line from the
+// centre, taken from the perpendicular offset o - b wc: the textbook b^2 - |o|^2
+// + r^2 cancels to fp32 noise when the line passes a distant sphere nearly
+// tangentially, where the chord, going as its square root, is most sensitive.
 DEV float chord_len(const KSphere& sp, const float* x, const float* wc, float dist) {
     const float o0 = x[0] - sp.c[0], o1 = x[1] - sp.c[1], o2 = x[2] - sp.c[2];
     const float b = o0 * wc[0] + o1 * wc[1] + o2 * wc[2];
-    const float cc = o0 * o0 + o1 * o1 + o2 * o2 - sp.r2;
-    const float disc = b * b - cc;
+    const float p0 = o0 - b * wc[0], p1 = o1 - b * wc[1], p2 = o2 - b * wc[2];
+    const float disc = sp.r2 - (p0 * p0 + p1 * p1 + p2 * p2);
     const float sq = fsqrt(fmaxf(disc, 0.f));
     const float lo = fmaxf(-b - sq, 0.f), hi = fminf(-b + sq, dist);
     return disc > 0.f ? fmaxf(hi - lo, 0.f) : 0.f;
@@ -1165,13 +1169,18 @@ DEV void advance(const KParams& P, const KBuffers& B, const WaveCtx& C, WalkStat
                         if (!(u1 < rho)) {
                             exit_code = FPT_EXIT_WALL;
                         } else {
-                            // Lambertian reflection about the wall's inward normal
                             lds_count(tally, FPT_T_WALL_REFLECT);
-                            dir_sin = fsqrt(u2);
-                            dir_cos = fsqrt(1.f - u2);
-                            frame = h.idx;
-                            W.face = h.idx;
-                            pend = PEND_SURFACE;
+                            if (!P.exc_scatter && L.nem == 0u) {
+                                // direct excitation only: an elastic event before the emission
+                                exit_code = FPT_EXIT_EXCSCAT;
+                            } else {
+                                // Lambertian reflection about the wall's inward normal
+                                dir_sin = fsqrt(u2);
+                                dir_cos = fsqrt(1.f - u2);
+                                frame = h.idx;
+                                W.face = h.idx;
+                                pend = PEND_SURFACE;
+                            }
                         }
                     } else {
                         // index-matched interface: change medium, keep direction
@@ -1387,7 +1396,7 @@ __global__ void __launch_bounds__(256) k_transport(const KParams P, const KBuffe
     const KSphere* SP = SPw;
     const uint32_t* T = smem + kLdsTable;                            // table image
     // the image up to the d sigma_a / d conc rows, which only the adjoint reads
-    const int staged = ADJ ? P.table_words : P.off_kap;
+    const int staged = ADJ ? P.off_src : P.off_kap;
     const int tw = (staged + 63) & ~63;
     // escape histogram in LDS (FWD, escape sensor, small films), flushed once per block
     uint32_t* hist = smem + kLdsTable + tw;
@@ -1810,11 +1819,306 @@ __global__ void k_reduce_partials(const float* partials, int nblocks, int np, fl
 }
 
 // -------------------------------------------------------------------------
+// Camera-side estimator (sec. 4.1: paths leave the camera at the emission
+// wavelength and sample the light only where an emission is realised; sec.
+// 4.3, eq. 12).  Path p = ((s H + py) W + px) N + k walks analogously at bin
+// k from the eye through a uniform point of pixel (px, py).  At every
+// collision in a dye medium the light is connected directly: a uniform point
+// on the quad, the transmittance at each of its lines through every sphere,
+// the emitter cosine and 1/r^2; the fluorescence source over sigma_t(k) is
+// added to the path's sum, which goes to film component 1 once, when the path
+// ends.  Any absorption ends the walk (a dye absorbing at the emission
+// wavelength would be a second emission: K = 1), as do the light quad and the
+// open face.  One lane per path; a wave takes new paths from a global counter
+// for its finished lanes once refill_lanes of them are free.  The whole table
+// image, camera rows included, sits in LDS.
+
+// New direction from its polar cosine/sine about +z (frame < 0) or about the
+// inward normal of wall `frame`, azimuth 2 pi u3.
+DEV void turn(float* w, float c, float sn, int frame, float u3) {
+    float sp, cp;
+    sincos_rev(u3, &sp, &cp);
+    const float a = sn * cp, b = sn * sp;
+    if (frame < 0) {
+        w[0] = a; w[1] = b; w[2] = c;
+        return;
+    }
+    // wall frame: normal n = sg e_ax, tangents e_(ax+1), sg e_(ax+2)
+    const int ax = frame >> 1;
+    const float sg = (frame & 1) ? -1.f : 1.f;
+    const float cc = sg * c, bb = sg * b;
+    w[0] = ax == 0 ? cc : (ax == 1 ? bb : a);
+    w[1] = ax == 0 ? a : (ax == 1 ? cc : bb);
+    w[2] = ax == 0 ? bb : (ax == 1 ? a : cc);
+}
+
+// Fluorescence source at the lane's collision from the light point (ua, ub):
+// sum_l src[m][k][l] T_l cos_n / r^2, or 0 with hit = false when the point's
+// emitting side faces away.
+DEV float cam_source(const KParams& P, const uint32_t* S, const KSphere* SP, const Lane& L,
+                     float ua, float ub, bool& hit) {
+    const float d0 = P.lpos[0] + ua * P.lu[0] + ub * P.lv[0] - L.x[0];
+    const float d1 = P.lpos[1] + ua * P.lu[1] + ub * P.lv[1] - L.x[1];
+    const float d2 = P.lpos[2] + ua * P.lu[2] + ub * P.lv[2] - L.x[2];
+    const float r2 = d0 * d0 + d1 * d1 + d2 * d2;
+    const float rinv = __builtin_amdgcn_rsqf(r2);
+    const float cos_n = -(P.ln[0] * d0 + P.ln[1] * d1 + P.ln[2] * d2) * rinv;
+    hit = cos_n > 0.f;
+    if (!hit) return 0.f;
+    const float wc[3] = {d0 * rinv, d1 * rinv, d2 * rinv};
+    const float r = r2 * rinv;
+    float len[FPT_MAX_SPHERES];
+#pragma unroll
+    for (int s = 0; s < FPT_MAX_SPHERES; ++s)
+        len[s] = s < P.n_spheres ? chord_len(SP[s], L.x, wc, r) : 0.f;
+    const int row = P.off_src + (L.medium * P.N + L.lam) * P.n_lines;
+    float sum = 0.f;
+#pragma unroll
+    for (int l = 0; l < FPT_MAX_LINES; ++l) {
+        if (l >= P.n_lines) break;
+        float tau = 0.f;
+#pragma unroll
+        for (int s = 0; s < FPT_MAX_SPHERES; ++s)
+            if (s < P.n_spheres) tau += wf(S, P.off_csig + s * P.n_lines + l) * len[s];
+        sum += wf(S, row + l) * (tau < kTauZero ? __expf(-tau) : 0.f);
+    }
+    return sum * cos_n * (rinv * rinv);
+}
+
+struct CamLane {
+    Lane L;
+    float acc;       // the path's deposit so far
+    long long fidx;  // its film element
+};
+
+// Vertex 0: the eye ray through a uniform point of the pixel enters the box
+// through the open face (the last of the three slab entries), else the path
+// ends at once (exit ESC_T).  Returns the exit code or -1.
+DEV int cam_start(const KParams& P, const uint32_t* S, CamLane& C, uint32_t pid) {
+    Lane& L = C.L;
+    const uint32_t npix = (uint32_t)P.W * (uint32_t)P.H;
+    const uint32_t k = pid % (uint32_t)P.N, rest = pid / (uint32_t)P.N;
+    const uint32_t pix = rest % npix, smp = rest / npix;
+    const uint32_t px = pix % (uint32_t)P.W, py = pix / (uint32_t)P.W;
+    L.pid = pid;
+    L.v = 0u;
+    L.nsc = 0u;
+    L.nem = 0u;
+    L.lam = (int)k;
+    L.comp = 1;
+    L.batch = smp % P.batches;
+    L.region = -1;
+    L.medium = -1;
+    L.splat_sum = 0.f;
+    load_medium(P, S, L);
+    C.acc = 0.f;
+    C.fidx = (((long long)L.batch * 2 + 1) * npix + pix) * P.N + k;
+    const uint4 r = philox(pid, 0u, 0u, 0u, P.key0, P.key1);
+    const float xi = fdiv(2.f * ((float)px + u24(r.x)), (float)P.W) - 1.f;
+    const float yi = 1.f - fdiv(2.f * ((float)py + u24(r.y)), (float)P.H);
+    float w[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) w[a] = P.cf[a] + xi * P.tanx * P.cr[a] + yi * P.tany * P.cu[a];
+    const float wn = __builtin_amdgcn_rsqf(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
+    float t_in = -kInf, t_out = kInf;
+    int face = -1;
+    bool inside = true;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        w[a] *= wn;
+        L.w[a] = w[a];
+        if (w[a] == 0.f) {
+            if (P.eye[a] < P.lo[a] || P.eye[a] > P.hi[a]) inside = false;
+            continue;
+        }
+        const float t0 = fdiv(P.lo[a] - P.eye[a], w[a]), t1 = fdiv(P.hi[a] - P.eye[a], w[a]);
+        const float tn = w[a] > 0.f ? t0 : t1, tf = w[a] > 0.f ? t1 : t0;
+        if (tn > t_in) {
+            t_in = tn;
+            face = w[a] > 0.f ? 2 * a : 2 * a + 1;
+        }
+        t_out = fminf(t_out, tf);
+    }
+    if (!(inside && face == P.open_face && t_in > 0.f && t_in < t_out)) return FPT_EXIT_ESC_T;
+    const int oa = P.open_face >> 1;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) L.x[a] = a == oa ? P.vis_plane : P.eye[a] + t_in * w[a];
+    return -1;
+}
+
+// One vertex of a live camera path.  Returns the exit code or -1.
+DEV int cam_step(const KParams& P, const uint32_t* S, const KSphere* SP, uint32_t* tally,
+                 Counters& cnt, CamLane& C) {
+    Lane& L = C.L;
+    L.v += 1u;
+    if (P.max_vertices && L.v >= P.max_vertices) return FPT_EXIT_TRUNC;
+    if (L.v >= kMaxPathVertices) return FPT_EXIT_SCAP;
+    cnt.vertices++;
+    const uint4 r = philox(L.pid, L.v, 0u, 0u, P.key0, P.key1);
+    const float u0 = u24(r.x), u1 = u24(r.y), u2 = u24(r.z), u3 = u24(r.w);
+    // eq. 6: free flight at the emission wavelength
+    const float tf = (L.inv == kInf) ? kInf : -__logf(1.f - u0) * L.inv;
+    const Hit h = next_surface<FPT_GEOM_BOX>(P, SP, L, false);
+    const bool collide = tf < h.d;
+    const float len = collide ? tf : h.d;
+    if (len < kInf) {
+        L.x[0] += len * L.w[0];
+        L.x[1] += len * L.w[1];
+        L.x[2] += len * L.w[2];
+    }
+    if (collide) {
+        if (L.ndy > 0) {
+            // a candidate emission vertex: connect to the light
+            const uint4 r1 = philox(L.pid, L.v, 1u, 0u, P.key0, P.key1);
+            bool hit;
+            const float q = cam_source(P, S, SP, L, u24(r1.x), u24(r1.y), hit);
+            if (hit) {
+                cnt.splat_hit++;
+                C.acc += P.wscale * q * L.inv;
+            } else {
+                lds_count(tally, FPT_T_SPLAT_MISS);
+            }
+        }
+        const float sv = u1 * L.st;
+        if (sv < L.ss) {
+            // elastic scattering, isotropic phase function (eq. 2)
+            L.nsc++;
+            cnt.scatters++;
+            if (L.nsc > P.max_scatter) return FPT_EXIT_SCAP;
+            turn(L.w, 1.f - 2.f * u2, 2.f * fsqrt(u2 * (1.f - u2)), -1, u3);
+            return -1;
+        }
+        if (sv < L.thr_bg || L.ndy == 0) return FPT_EXIT_BG;
+        lds_count(tally, FPT_T_DYE_ABS);
+        return FPT_EXIT_KCAP;
+    }
+    snap_to_plane<FPT_GEOM_BOX>(P, L, h);
+    if (h.ev == EV_ESC || h.ev == EV_INF) return FPT_EXIT_ESC_R;
+    if (h.ev == EV_LIGHT) return FPT_EXIT_LIGHT;
+    if (h.ev == EV_WALL) {
+        const float rho = h.idx >= 0 ? wf(S, P.off_rho + h.idx * P.N + L.lam) : 0.f;
+        if (!(u1 < rho)) return FPT_EXIT_WALL;
+        lds_count(tally, FPT_T_WALL_REFLECT);
+        turn(L.w, fsqrt(1.f - u2), fsqrt(u2), h.idx, u3);
+        return -1;
+    }
+    // index-matched interface: change medium, keep direction
+    lds_count(tally, FPT_T_CROSSINGS);
+    L.region = (h.ev == EV_ENTER) ? h.idx : -1;
+    L.medium = -1;
+    if (L.region >= 0) {
+        const KSphere& sp = SP[L.region];
+        L.sc[0] = sp.c[0];
+        L.sc[1] = sp.c[1];
+        L.sc[2] = sp.c[2];
+        L.sr2 = sp.r2;
+        L.medium = sp.medium;
+    }
+    load_medium(P, S, L);
+    return -1;
+}
+
+template <bool REC>
+DEV void cam_finish(const KParams& P, const KBuffers& B, uint32_t* tally, const CamLane& C,
+                    int exit_code) {
+    lds_count(tally, FPT_T_EXIT0 + exit_code);
+    if (C.acc != 0.f && B.film) atomicAdd(&B.film[C.fidx], C.acc);
+    if constexpr (REC) {
+        const Lane& L = C.L;
+        fpt_path_record rc;
+        rc.n_vertices = L.v + (exit_code == FPT_EXIT_TRUNC ? 0u : 1u);
+        rc.n_scatter = L.nsc;
+        rc.n_emit = 0u;
+        rc.exit_code = (uint32_t)exit_code;
+        rc.lambda = L.lam;
+        rc.comp = 1;
+        rc.region = L.region;
+        rc.pad = 0;
+        rc.pos[0] = L.x[0]; rc.pos[1] = L.x[1]; rc.pos[2] = L.x[2];
+        rc.dir[0] = L.w[0]; rc.dir[1] = L.w[1]; rc.dir[2] = L.w[2];
+        rc.splat_sum = C.acc;
+        rc.pad2 = 0.f;
+        B.rec[L.pid - P.path_begin] = rc;
+    }
+}
+
+template <bool REC>
+__global__ void __launch_bounds__(256) k_camera(const KParams P, const KBuffers B) {
+    extern __shared__ uint32_t smem[];
+    uint32_t* tally = smem;
+    KSphere* SPw = reinterpret_cast<KSphere*>(smem + kLdsSpheres);
+    const KSphere* SP = SPw;
+    const uint32_t* T = smem + kLdsTable;
+    for (int i = threadIdx.x; i < FPT_N_TALLIES; i += blockDim.x) tally[i] = 0u;
+    for (int i = threadIdx.x; i < P.table_words; i += blockDim.x) smem[kLdsTable + i] = B.tables[i];
+    for (int i = threadIdx.x; i < P.n_spheres; i += blockDim.x) SPw[i] = P.spheres[i];
+    __syncthreads();
+    const uint32_t lane = lane_id();
+    CamLane C;
+    C.acc = 0.f;
+    C.fidx = 0;
+    C.L.pid = 0u;
+    C.L.v = 0u;
+    Counters cnt = {0u, 0u, 0u};
+    bool alive = false, exhausted = false;
+    for (;;) {
+        const uint64_t idle = __ballot(!alive);
+        if (exhausted && idle == ~0ull) break;
+        if (!exhausted && __popcll(idle) >= (uint32_t)P.refill_lanes) {
+            const uint32_t n = (uint32_t)__popcll(idle);
+            unsigned long long base = 0ull;
+            if (lane == 0u) base = atomicAdd(B.counter, (unsigned long long)n);
+            base = ((unsigned long long)__builtin_amdgcn_readfirstlane((uint32_t)(base >> 32)) << 32) |
+                   __builtin_amdgcn_readfirstlane((uint32_t)base);
+            if (base + n >= P.path_count) exhausted = true;
+            if (!alive) {
+                const unsigned long long i = base + mbcnt(idle);
+                if (i < P.path_count) {
+                    cnt.vertices++;
+                    const int e = cam_start(P, T, C, P.path_begin + (uint32_t)i);
+                    if (e >= 0) cam_finish<REC>(P, B, tally, C, e);
+                    else alive = true;
+                }
+            }
+        }
+        if (alive) {
+            const int e = cam_step(P, T, SP, tally, cnt, C);
+            if (e >= 0) {
+                cam_finish<REC>(P, B, tally, C, e);
+                alive = false;
+            }
+        }
+    }
+    {
+        uint32_t a = cnt.vertices, b = cnt.scatters, c = cnt.splat_hit;
+        for (int off = 32; off > 0; off >>= 1) {
+            a += __shfl_xor(a, off);
+            b += __shfl_xor(b, off);
+            c += __shfl_xor(c, off);
+        }
+        if (lane == 0u) {
+            atomicAdd(&tally[FPT_T_VERTICES], a);
+            atomicAdd(&tally[FPT_T_SCATTERS], b);
+            atomicAdd(&tally[FPT_T_SPLAT_HIT], c);
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < FPT_N_TALLIES && B.tallies) {
+        uint32_t v = tally[threadIdx.x];
+        if (threadIdx.x == FPT_T_PATHS) {
+            v = 0u;
+            for (int e = 0; e < 10; ++e) v += tally[FPT_T_EXIT0 + e];
+        }
+        if (v) atomicAdd(&B.tallies[threadIdx.x], (unsigned long long)v);
+    }
+}
+
+// -------------------------------------------------------------------------
 // Host-side launchers (called by the C-ABI implementation).
 size_t queue_words() { return (size_t)(kQueueShards + 1) * kShardStride; }  // heads, used-up count
 
 size_t transport_lds_bytes(const KParams& P, int block_threads, int mode) {
-    const int staged = (mode == MODE_ADJ || mode == MODE_REC_ADJ) ? P.table_words : P.off_kap;
+    const int staged = (mode == MODE_ADJ || mode == MODE_REC_ADJ) ? P.off_src : P.off_kap;
     size_t words = kLdsTable + ((staged + 63) & ~63) + P.hist_words;
     if (mode == MODE_FWD && P.geometry == FPT_GEOM_BOX)  // deferred splat rings and merging tables
         words += (size_t)(block_threads / 64) * (kSqWords + kAggWords);
@@ -1877,6 +2181,22 @@ hipError_t launch_transport(const KParams& P, const KBuffers& B, int mode, int g
     case MODE_REC: return launch_m<MODE_REC>(P, B, grid, block, lds, s);
     default: return launch_m<MODE_REC_ADJ>(P, B, grid, block, lds, s);
     }
+}
+
+size_t camera_lds_bytes(const KParams& P) { return (size_t)(kLdsTable + P.table_words) * 4; }
+
+hipError_t camera_occupancy(const KParams& P, bool rec, int block, int* blocks_per_cu) {
+    const void* f = rec ? reinterpret_cast<const void*>(&k_camera<true>)
+                        : reinterpret_cast<const void*>(&k_camera<false>);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, f, block, camera_lds_bytes(P));
+}
+
+hipError_t launch_camera(const KParams& P, const KBuffers& B, bool rec, int grid, int block,
+                         hipStream_t s) {
+    const size_t lds = camera_lds_bytes(P);
+    if (rec) hipLaunchKernelGGL((k_camera<true>), dim3(grid), dim3(block), lds, s, P, B);
+    else hipLaunchKernelGGL((k_camera<false>), dim3(grid), dim3(block), lds, s, P, B);
+    return hipGetLastError();
 }
 
 hipError_t launch_zero_u32(uint32_t* p, size_t n, hipStream_t s) {

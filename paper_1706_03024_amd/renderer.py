@@ -150,6 +150,38 @@ class Scene:
         rec = buf.cpu().numpy().view(RECORD_DTYPE).reshape(n)
         return rec, (None if rg is None else rg.cpu().numpy())
 
+    def camera_paths(self, spp):
+        """Path count of a camera-side render with spp samples per (pixel, bin)."""
+        se = self.desc["sensor"]
+        return spp * se["height"] * se["width"] * self.desc["grid"]["n_bins"]
+
+    def render_camera(self, run: dict, film=None, tallies=None):
+        """fpt_render_camera: the camera-side estimator; accumulates into
+        component 1 of `film` (allocated and zeroed if None).
+        run["total_paths"] must be camera_paths(spp)."""
+        B = max(1, run.get("parity_batches", 1))
+        if film is None:
+            film = self.new_film(B)
+        _require_cuda(film, torch.float32, "film")
+        if film.numel() != int(np.prod(self.film_shape(B))):
+            raise ValueError("film has the wrong size")
+        if tallies is not None:
+            _require_cuda(tallies, torch.int64, "tallies")
+        r = _abi.run_struct(run)
+        check(lib().fpt_render_camera(self._h, C.byref(r), _ptr(film), _ptr(tallies), None, 0,
+                                      _stream()))
+        return film
+
+    def camera_records(self, run: dict, max_vertices=0):
+        """fpt_render_camera with per-path records only (numpy structured array)."""
+        n = run["path_count"]
+        buf = torch.zeros((n, _abi.RECORD_WORDS), dtype=torch.int32, device="cuda")
+        r = _abi.run_struct(run)
+        check(lib().fpt_render_camera(self._h, C.byref(r), None, None, _ptr(buf), max_vertices,
+                                      _stream()))
+        torch.cuda.synchronize()
+        return buf.cpu().numpy().view(RECORD_DTYPE).reshape(n)
+
 
 RECORD_DTYPE = np.dtype([("n_vertices", "<u4"), ("n_scatter", "<u4"), ("n_emit", "<u4"),
                          ("exit_code", "<u4"), ("lambda", "<i4"), ("comp", "<i4"),

@@ -110,3 +110,4 @@ def test_null_arguments_rejected():
     r = _abi.run_struct(workloads.make_run(16))
     assert L.fpt_render(None, C.byref(r), None, None, None) == _abi.E_INVALID
     assert L.fpt_render_adjoint(None, C.byref(r), None, None, None, None) == _abi.E_INVALID
+    assert L.fpt_render_camera(None, C.byref(r), None, None, None, 0, None) == _abi.E_INVALID

@@ -149,6 +149,13 @@ def cornell_config():
     return cornell_scene(), make_run(128 * 128 * 64, seed=0)
 
 
+def camera_config(spp=8):
+    """The Cornell scene rendered camera-side: 128x128 pixels x 101 emission
+    bins x spp samples (13.2M paths at 8 samples)."""
+    scene = cornell_scene()
+    return scene, make_run(spp * 128 * 128 * 101, seed=0)
+
+
 # --------------------------------------------------------------------------
 # Large highly scattering scene: five bimodal dyes, sigma_s up to 1000/mm.
 # --------------------------------------------------------------------------
