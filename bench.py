@@ -38,6 +38,7 @@ PHILOX = 92            # ten rounds of 2 products + 4 xors, four 24-bit conversi
 STEP = PHILOX + 6      # free flight: log, scale, position update
 START = 2 * PHILOX + 25  # light vertex: line choice, point and direction on the quad
 EMISSION = PHILOX + 17   # quantum-yield test, emission CDF inversion
+CAM_START = PHILOX + 90  # camera-side path: pixel of the path index, pixel sample, eye ray, box entry
 
 
 def ops_model(t, n_spheres, geometry):
@@ -54,18 +55,34 @@ def ops_model(t, n_spheres, geometry):
             + conn * (t["splat_hit"] + t["splat_miss"] + t["splat_rr_kill"]))
 
 
-def time_renders(sc, run, steps, warmup, film):
+def camera_ops(t, n_spheres, n_lines):
+    """Algorithmic ALU lane operations of one camera-side render (eq. 12
+    estimator) from its event tallies: the forward walk's per-vertex costs,
+    and per light connection a Philox call, the light point, distance and
+    emitter cosine, one chord per sphere and one transmittance per line."""
+    medium = 25
+    surface = 55 + 15 * n_spheres
+    conn = PHILOX + 29 + 22 * n_spheres + n_lines * (n_spheres + 5)
+    return (CAM_START * t["paths"]
+            + (STEP + medium) * (t["scatters"] + t["dye_abs"] + t["exit_bg"])
+            + (STEP + surface) * (t["crossings"] + t["wall_reflect"] + t["exit_wall"] + t["exit_light"]
+                                  + t["exit_esc_r"])
+            + conn * (t["splat_hit"] + t["splat_miss"]))
+
+
+def time_renders(sc, run, steps, warmup, film, camera=False):
     """Wall time per render over `steps` renders, and the mean durations of
     its transport and deferred-connection launches from the HIP events the
     library records around them on the render stream in the same renders."""
     import torch
+    render = sc.render_camera if camera else sc.render
     for _ in range(warmup):
-        sc.render(run, film=film)
+        render(run, film=film)
     torch.cuda.synchronize()
     sc.set_timing(True)
     t0 = time.perf_counter()
     for _ in range(steps):
-        sc.render(run, film=film)
+        render(run, film=film)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     n, t_ms, d_ms = sc.timing()
@@ -98,6 +115,29 @@ def forward_form(scene, run, steps, warmup, tune_name=None):
     return {"vertices": tal["vertices"], "ms_per_step": ms, "transport_ms": t_ms, "deferred_ms": d_ms,
             "kernel_ms": t_ms + d_ms, "vertices_per_s": tal["vertices"] / (ms / 1e3), "ops": ops,
             "tallies": tal, "tune": tune}
+
+
+def camera_form(steps, warmup):
+    """The camera-side estimator (eq. 12, sec. 4.1) on the Cornell scene:
+    128x128 pixels x 101 emission bins x 8 samples, paths from the eye with a
+    light connection at every collision in a dye sphere."""
+    import torch
+    import paper_1706_03024_amd as fpt
+    import workloads
+    scene, run = workloads.camera_config()
+    sc = fpt.Scene(scene)
+    film = sc.new_film()
+    t = fpt.new_tallies()
+    sc.render_camera(run, tallies=t)
+    torch.cuda.synchronize()
+    tal = fpt.tallies_dict(t)
+    ms, k_ms, _ = time_renders(sc, run, steps, warmup, film, camera=True)
+    sc.close()
+    ops = camera_ops(tal, len(scene["geometry"]["spheres"]), len(scene["light"]["lines"]))
+    return {"vertices": tal["vertices"], "paths": run["path_count"], "ms_per_step": ms,
+            "kernel_ms": k_ms, "vertices_per_s": tal["vertices"] / (ms / 1e3),
+            "light_connections": tal["splat_hit"] + tal["splat_miss"],
+            "alu_frac": ops / (k_ms / 1e3) / 1e12 / ALU_PEAK_TOPS}
 
 
 def alu_frac(form):
@@ -259,7 +299,7 @@ def profile_run(name, steps):
         print(f"profiled {steps} batched renders", flush=True)
         return
     scene, run = {"cornell": workloads.cornell_config, "large": workloads.large_config,
-                  "slab": workloads.slab_config,
+                  "slab": workloads.slab_config, "camera": workloads.camera_config,
                   "adjoint": lambda: workloads.adjoint_config()[:2]}[name]()
     if name == "slab":
         run = dict(run, path_count=1 << 22, total_paths=1 << 22)
@@ -271,6 +311,9 @@ def profile_run(name, steps):
     film = sc.new_film()
     g = torch.ones_like(film) if name == "adjoint" else None
     for _ in range(steps):
+        if name == "camera":
+            sc.render_camera(run, film=film)
+            continue
         sc.render(run, film=film)
         if g is not None:
             sc.render_adjoint(run, g)
@@ -288,7 +331,8 @@ def main():
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--only-headline", action="store_true",
                     help="time only the headline render (for profiler runs)")
-    ap.add_argument("--profile", choices=["cornell", "large", "slab", "batched", "adjoint"],
+    ap.add_argument("--profile", choices=["cornell", "large", "slab", "batched", "adjoint",
+                                          "camera"],
                     help="profiler run: one 256 MiB device copy (traffic calibration) and "
                          "--steps renders of the named workload, nothing else")
     args = ap.parse_args()
@@ -353,6 +397,7 @@ def main():
         if b is not None:
             extra["batched"] = b
         extra["excitation_scan"] = sweep_form(max(3, args.steps // 5), 1)
+        extra["camera_side"] = camera_form(max(3, args.steps // 5), 1)
     line["forms"] = extra
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(scene, run)

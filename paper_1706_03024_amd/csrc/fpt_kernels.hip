@@ -1829,9 +1829,10 @@ __global__ void k_reduce_partials(const float* partials, int nblocks, int np, fl
 // added to the path's sum, which goes to film component 1 once, when the path
 // ends.  Any absorption ends the walk (a dye absorbing at the emission
 // wavelength would be a second emission: K = 1), as do the light quad and the
-// open face.  One lane per path; a wave takes new paths from a global counter
-// for its finished lanes once refill_lanes of them are free.  The whole table
-// image, camera rows included, sits in LDS.
+// open face.  One lane per path.  A wave claims chunks of kCamChunk
+// consecutive paths (one pixel's bins, neighbouring pixels) from a global
+// counter and hands them to its finished lanes once refill_lanes of them are
+// free.  The whole table image, camera rows included, sits in LDS.
 
 // New direction from its polar cosine/sine about +z (frame < 0) or about the
 // inward normal of wall `frame`, azimuth 2 pi u3.
@@ -2042,6 +2043,80 @@ DEV void cam_finish(const KParams& P, const KBuffers& B, uint32_t* tally, const 
     }
 }
 
+constexpr uint32_t kCamChunk = 512;
+constexpr uint32_t kCamBlockMinV = 24;  // paths in a sphere from this vertex on walk in wave rounds
+constexpr int kCamRounds = 8;           // wave rounds per iteration
+
+// One wave round of camera path j inside its sphere: lane k draws vertex
+// v+1+k (the forward's whole-wave round: free flight, scatter test, new
+// direction, positions from the canonical 16-vertex chunk scan), the vertices
+// before the first stop (sphere boundary reached, absorption, a cap) are
+// committed as scatters and each makes its light connection in its own lane;
+// the deposits are summed over the wave.  The stop vertex itself is left to
+// the path's next sequential step.  Returns the number committed.
+DEV int cam_round(const KParams& P, const uint32_t* S, const KSphere* SP, uint32_t* tally,
+                  Counters& cnt, CamLane& C, int j, uint32_t lane) {
+    Lane Q;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        Q.x[c] = rl(C.L.x[c], j);
+        Q.w[c] = rl(C.L.w[c], j);
+        Q.sc[c] = rl(C.L.sc[c], j);
+    }
+    Q.sr2 = rl(C.L.sr2, j);
+    Q.st = rl(C.L.st, j);
+    Q.inv = rl(C.L.inv, j);
+    Q.ss = rl(C.L.ss, j);
+    Q.ndy = rli(C.L.ndy, j);
+    Q.lam = rli(C.L.lam, j);
+    Q.medium = rli(C.L.medium, j);
+    Q.region = rli(C.L.region, j);
+    Q.pid = rlu(C.L.pid, j);
+    Q.v = rlu(C.L.v, j);
+    Q.nsc = rlu(C.L.nsc, j);
+    float wn[3], xk[4], pk[3], win[3];
+    bool stop;
+    deep_half<FPT_GEOM_BOX>(P, Q, Q.v, lane, Q.w, Q.x, wn, xk, pk, win, stop);
+    const uint32_t vk = Q.v + 1u + lane;
+    if (P.max_vertices && vk >= P.max_vertices) stop = true;
+    const uint64_t sm = __ballot(stop);
+    const int kstar = sm ? __ffsll((unsigned long long)sm) - 1 : 64;
+    float dep = 0.f;
+    if ((int)lane < kstar) {
+        cnt.vertices++;
+        cnt.scatters++;
+        if (Q.ndy > 0) {
+            const uint4 r1 = philox(Q.pid, vk, 1u, 0u, P.key0, P.key1);
+            Lane Lk = Q;
+            Lk.x[0] = xk[0];
+            Lk.x[1] = xk[1];
+            Lk.x[2] = xk[2];
+            bool hit;
+            const float q = cam_source(P, S, SP, Lk, u24(r1.x), u24(r1.y), hit);
+            if (hit) {
+                cnt.splat_hit++;
+                dep = P.wscale * q * Q.inv;
+            } else {
+                lds_count(tally, FPT_T_SPLAT_MISS);
+            }
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1) dep += __shfl_xor(dep, off);
+    if (kstar > 0) {
+        const int u = kstar - 1;
+        const float nx0 = rl(xk[0], u), nx1 = rl(xk[1], u), nx2 = rl(xk[2], u);
+        const float nw0 = rl(wn[0], u), nw1 = rl(wn[1], u), nw2 = rl(wn[2], u);
+        if ((int)lane == j) {
+            C.L.x[0] = nx0; C.L.x[1] = nx1; C.L.x[2] = nx2;
+            C.L.w[0] = nw0; C.L.w[1] = nw1; C.L.w[2] = nw2;
+            C.L.v += (uint32_t)kstar;
+            C.L.nsc += (uint32_t)kstar;
+            C.acc += dep;
+        }
+    }
+    return kstar;
+}
+
 template <bool REC>
 __global__ void __launch_bounds__(256) k_camera(const KParams P, const KBuffers B) {
     extern __shared__ uint32_t smem[];
@@ -2061,27 +2136,54 @@ __global__ void __launch_bounds__(256) k_camera(const KParams P, const KBuffers 
     C.L.v = 0u;
     Counters cnt = {0u, 0u, 0u};
     bool alive = false, exhausted = false;
+    bool seq_next = false;  // the lane's last wave round stopped short of 64 vertices
+    uint32_t q_next = 0u, q_end = 0u;  // the wave's current chunk of path indices (uniform)
     for (;;) {
         const uint64_t idle = __ballot(!alive);
         if (exhausted && idle == ~0ull) break;
         if (!exhausted && __popcll(idle) >= (uint32_t)P.refill_lanes) {
-            const uint32_t n = (uint32_t)__popcll(idle);
-            unsigned long long base = 0ull;
-            if (lane == 0u) base = atomicAdd(B.counter, (unsigned long long)n);
-            base = ((unsigned long long)__builtin_amdgcn_readfirstlane((uint32_t)(base >> 32)) << 32) |
-                   __builtin_amdgcn_readfirstlane((uint32_t)base);
-            if (base + n >= P.path_count) exhausted = true;
-            if (!alive) {
-                const unsigned long long i = base + mbcnt(idle);
-                if (i < P.path_count) {
-                    cnt.vertices++;
-                    const int e = cam_start(P, T, C, P.path_begin + (uint32_t)i);
-                    if (e >= 0) cam_finish<REC>(P, B, tally, C, e);
-                    else alive = true;
+            const uint32_t need = (uint32_t)__popcll(idle);
+            const uint32_t rank = mbcnt(idle);  // among the idle lanes
+            uint32_t mine = ~0u;
+            uint32_t took = min(need, q_end - q_next);
+            if (rank < took) mine = q_next + rank;
+            q_next += took;
+            if (took < need) {
+                // the chunk ran dry: claim the next one for the remaining lanes
+                unsigned long long base = 0ull;
+                if (lane == 0u) base = atomicAdd(B.counter, (unsigned long long)kCamChunk);
+                const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(base >> 32));
+                const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)base);
+                if (hi != 0u || lo >= P.path_count) {
+                    exhausted = true;
+                } else {
+                    q_next = lo;
+                    q_end = min(P.path_count, lo + min(kCamChunk, P.path_count - lo));
+                    const uint32_t more = min(need - took, q_end - q_next);
+                    if (rank >= took && rank - took < more) mine = q_next + (rank - took);
+                    q_next += more;
                 }
             }
+            if (!alive && mine != ~0u) {
+                cnt.vertices++;
+                const int e = cam_start(P, T, C, P.path_begin + mine);
+                if (e >= 0) cam_finish<REC>(P, B, tally, C, e);
+                else alive = true;
+            }
         }
-        if (alive) {
+        // paths deep in a sphere walk in wave rounds, up to kCamRounds per
+        // iteration; one whose round stopped short resolves the stop vertex
+        // with a sequential step, one still waiting for a round skips its step
+        uint64_t wait = __ballot(alive && !seq_next && C.L.region >= 0 && C.L.v >= kCamBlockMinV);
+        for (int rd = 0; rd < kCamRounds && wait; ++rd) {
+            const int j = __ffsll((unsigned long long)wait) - 1;
+            if (cam_round(P, T, SP, tally, cnt, C, j, lane) < 64) {
+                wait &= ~(1ull << j);
+                if ((int)lane == j) seq_next = true;
+            }
+        }
+        if (alive && !((wait >> lane) & 1ull)) {
+            seq_next = false;
             const int e = cam_step(P, T, SP, tally, cnt, C);
             if (e >= 0) {
                 cam_finish<REC>(P, B, tally, C, e);
