@@ -48,7 +48,8 @@ class Dye(C.Structure):
 
 class Medium(C.Structure):
     _fields_ = [("sigma_s", C.c_double), ("sigma_a_bg", C.c_double), ("n_dyes", C.c_int32),
-                ("dye", C.c_int32 * MAX_MEDIUM_DYES), ("conc", C.c_double * MAX_MEDIUM_DYES)]
+                ("dye", C.c_int32 * MAX_MEDIUM_DYES), ("conc", C.c_double * MAX_MEDIUM_DYES),
+                ("ior", C.c_double)]
 
 
 class Sphere(C.Structure):
@@ -165,6 +166,7 @@ def make_scene(d):
     for i, md in enumerate(d["media"]):
         sc.media[i].sigma_s = md["sigma_s"]
         sc.media[i].sigma_a_bg = md["sigma_a_bg"]
+        sc.media[i].ior = md.get("ior", 1.0)
         sc.media[i].n_dyes = len(md["dyes"])
         for j, (di, c) in enumerate(md["dyes"]):
             sc.media[i].dye[j] = di

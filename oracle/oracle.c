@@ -632,6 +632,49 @@ static uint32_t rr_bits_of(const uint32_t r[4]) {
     return ((r[0] & 0xFFu) << 16) | ((r[1] & 0xFFu) << 8) | (r[2] & 0xFFu);
 }
 
+/* ------------------------------------------------------------------------- */
+/* Smooth dielectric boundary of a body medium (glass beads and vials, sec. 5:
+ * refractive media; textbook Fresnel equations and Snell's law). */
+
+/* Refractive index of the body medium (1 when index-matched or in a box). */
+static double body_ior(const orc_scene* sc) {
+    if (sc->geom == ORC_GEOM_BOX || sc->geom == ORC_GEOM_INFINITE) return 1.0;
+    double n = sc->media[sc->body_medium].ior;
+    return n > 0.0 ? n : 1.0;
+}
+
+/* Unpolarised reflectance (mean of the s and p intensities) for light going
+ * from index n1 into index n2 with incidence cosine ci > 0; 1 beyond the
+ * critical angle.  *ct receives the transmitted cosine (0 on total internal
+ * reflection). */
+static double fresnel(double ci, double n1, double n2, double* ct) {
+    double eta = n1 / n2;
+    double st2 = eta * eta * (1.0 - ci * ci);
+    if (st2 >= 1.0) { *ct = 0.0; return 1.0; }
+    double c2 = sqrt(1.0 - st2);
+    double rs = (n1 * ci - n2 * c2) / (n1 * ci + n2 * c2);
+    double rp = (n1 * c2 - n2 * ci) / (n1 * c2 + n2 * ci);
+    *ct = c2;
+    return 0.5 * (rs * rs + rp * rp);
+}
+
+/* Outward unit normal of the body's boundary at x, for a path moving along w
+ * (slab: the face it is heading for). */
+static void body_normal(const orc_scene* sc, const double* x, const double* w, double* nrm) {
+    nrm[0] = nrm[1] = nrm[2] = 0.0;
+    if (sc->geom == ORC_GEOM_SLAB) nrm[2] = w[2] > 0.0 ? 1.0 : -1.0;
+    else if (sc->geom == ORC_GEOM_HALFSPACE) nrm[2] = -1.0;
+    else {
+        for (int i = 0; i < 3; ++i) nrm[i] = x[i] - sc->center[i];
+        normalize3(nrm);
+    }
+}
+
+static void mirror(double* w, const double* nrm) {
+    double d = 2.0 * dot3(w, nrm);
+    for (int i = 0; i < 3; ++i) w[i] -= d * nrm[i];
+}
+
 static int region_medium(const orc_scene* sc, int region) {
     if (sc->geom == ORC_GEOM_BOX) return region >= 0 ? sc->spheres[region].medium : -1;
     return sc->body_medium;
@@ -671,11 +714,32 @@ static void run_path(ctx_t* c, uint32_t pid, orc_record* rec, uint32_t max_verti
     while (line < sc->n_lines - 1 && !(u < t->line_cum[line])) ++line;
     for (int i = 0; i < sc->n_lines - 1; ++i) upd_margin(&p.margin, fabs(u - t->line_cum[i]));
     p.lam = t->line_bin[line];
+    double n_b = body_ior(sc);
     if (sc->light == ORC_LIGHT_BEAM) {
         memcpy(p.x, sc->lpos, sizeof p.x);
         memcpy(p.w, sc->ldir, sizeof p.w);
         normalize3(p.w);
         p.region = 0;
+        if (n_b != 1.0) {
+            /* entering a refractive body: Fresnel reflection (the path leaves at
+             * once) or refraction, with uniform 1 of the light vertex */
+            double nrm[3], ct;
+            double ws[3] = {-p.w[0], -p.w[1], -p.w[2]};
+            body_normal(sc, p.x, ws, nrm);
+            double ci = -dot3(p.w, nrm);
+            double R = fresnel(ci, 1.0, n_b, &ct);
+            double ur = unif(r[1]);
+            upd_margin(&p.margin, fabs(ur - R));
+            if (ur < R) {
+                mirror(p.w, nrm);
+                T[ORC_T_WALL_REFLECT]++;
+                exit_code = -2;
+            } else {
+                double eta = 1.0 / n_b;
+                for (int i = 0; i < 3; ++i) p.w[i] = eta * p.w[i] + (eta * ci - ct) * nrm[i];
+                normalize3(p.w);
+            }
+        }
     } else if (sc->light == ORC_LIGHT_POINT) {
         draw(&rng, 0, 1, r1);
         memcpy(p.x, sc->lpos, sizeof p.x);
@@ -692,8 +756,15 @@ static void run_path(ctx_t* c, uint32_t pid, orc_record* rec, uint32_t max_verti
     T[ORC_T_PATHS]++;
     T[ORC_T_VERTICES]++;
     if (sc->light == ORC_LIGHT_QUAD) splat(c, &p, c->qn, 1, rr_bits_of(r));
+    if (exit_code == -2) {
+        /* reflected off the body on entry: escapes from the light vertex */
+        int side = p.w[2] < 0.0 ? 0 : 1;
+        upd_margin(&p.margin, fabs(p.w[2]));
+        tally_escape(c, &p, side);
+        exit_code = side == 0 ? ORC_EXIT_ESC_R : ORC_EXIT_ESC_T;
+    }
 
-    for (;;) {
+    while (exit_code < 0) {
         p.v++;
         if (max_vertices && p.v >= max_vertices) { exit_code = ORC_EXIT_TRUNC; break; }
         /* hard bound on path length: 2^28 vertices, counted as a scatter-cap exit */
@@ -779,6 +850,20 @@ static void run_path(ctx_t* c, uint32_t pid, orc_record* rec, uint32_t max_verti
             else if (sc->geom == ORC_GEOM_BOX && (h.kind == SURF_WALL || h.kind == SURF_ESCAPE) &&
                      h.index >= 0)
                 p.x[h.index / 2] = (h.index % 2) ? sc->box_hi[h.index / 2] : sc->box_lo[h.index / 2];
+        }
+        if (h.kind == SURF_ESCAPE && n_b != 1.0 && isfinite(dd)) {
+            /* the body's dielectric boundary: specular reflection with the
+             * Fresnel probability (total internal reflection beyond the critical
+             * angle), else the path crosses out; the event uniform decides */
+            double nrm[3], ct;
+            body_normal(sc, p.x, p.w, nrm);
+            double R = fresnel(dot3(p.w, nrm), n_b, 1.0, &ct);
+            upd_margin(&p.margin, fabs(u1 - R));
+            if (u1 < R) {
+                mirror(p.w, nrm);
+                T[ORC_T_WALL_REFLECT]++;
+                continue;
+            }
         }
         if (h.kind == SURF_ESCAPE) {
             int side = p.w[2] < 0.0 ? 0 : 1;

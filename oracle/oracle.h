@@ -18,6 +18,10 @@
  *   - dye absorption: quantum-yield test, then re-emission at a wavelength drawn
  *     from the dye's normalised emission spectrum (eq. 10), isotropic (sec. 2.1);
  *   - at most K emissions per path (sec. 4.1: a second emission terminates);
+ *   - a body medium with refractive index n != 1 has a smooth dielectric
+ *     boundary: an entering beam and every path reaching the boundary from
+ *     inside are reflected specularly with the unpolarised Fresnel reflectance
+ *     (1 beyond the critical angle), else cross it (Snell's law on entry);
  *   - spectral film: escape tallies, or a pinhole camera splat at every
  *     realised vertex (eqs. 3-6: transmittance, geometry term 1/r^2).
  *
@@ -76,6 +80,7 @@ typedef struct {
     int32_t n_dyes;
     int32_t dye[ORC_MAX_MEDIUM_DYES];
     double conc[ORC_MAX_MEDIUM_DYES]; /* uM */
+    double ior; /* refractive index; 0 or 1: index-matched to the vacuum around it */
 } orc_medium;
 
 typedef struct {

@@ -226,3 +226,83 @@ def single_scatter_radiance(eye, d, c, rad, sig_s, sig_t, corner, u, v, radiance
         q = quad_irradiance(x, None, corner, u, v, radiance, n=n_quad, medium=(c, rad, sig_t))
         tot += wt * math.exp(-sig_t * (t - t0)) * q
     return sig_s / (4 * math.pi) * tot
+
+
+# ---------------------------------------------------------------- dielectric boundaries
+def fresnel_unpolarised(ci, n1, n2):
+    """Reflectance of a smooth dielectric interface for unpolarised light going
+    from index n1 into n2 at incidence cosine ci: the mean of the s and p
+    intensities in their angle form (Born & Wolf 1.5.2)
+        R_s = sin^2(ti - tt) / sin^2(ti + tt),  R_p = tan^2(ti - tt) / tan^2(ti + tt),
+    with sin tt = (n1/n2) sin ti; 1 beyond the critical angle and
+    ((n1 - n2)/(n1 + n2))^2 at normal incidence (the limit of both)."""
+    ci = min(max(float(ci), 0.0), 1.0)
+    ti = math.acos(ci)
+    st = n1 / n2 * math.sin(ti)
+    if st >= 1.0:
+        return 1.0
+    if ti < 1e-9:
+        return ((n1 - n2) / (n1 + n2)) ** 2
+    tt = math.asin(st)
+    rs = math.sin(ti - tt) ** 2 / math.sin(ti + tt) ** 2
+    rp = math.tan(ti - tt) ** 2 / math.tan(ti + tt) ** 2
+    return 0.5 * (rs + rp)
+
+
+def dielectric_slab_beam(n, ci, sigma, d):
+    """(R, T) of a beam entering a non-scattering, absorbing slab (index n,
+    thickness d, vacuum outside) at incidence cosine ci: incoherent multiple
+    reflections between the faces, reflectance r at every encounter (the same
+    inside, by reciprocity) and attenuation q = exp(-sigma d / ct) per crossing:
+        R = r + (1-r)^2 r q^2 / (1 - r^2 q^2),   T = (1-r)^2 q / (1 - r^2 q^2)."""
+    r = fresnel_unpolarised(ci, 1.0, n)
+    ct = math.sqrt(1.0 - (1.0 - ci * ci) / (n * n))
+    q = math.exp(-sigma * d / ct)
+    den = 1.0 - r * r * q * q
+    return r + (1 - r) ** 2 * r * q * q / den, (1 - r) ** 2 * q / den
+
+
+def dielectric_slab_point(n, sigma, d, zs):
+    """(bottom, top) escape fractions of an isotropic point source at height zs
+    in a non-scattering absorbing slab [0, d] of index n: a ray of direction
+    cosine mu keeps |mu| at every face, reflects with r(|mu|) (1 under total
+    internal reflection) and is attenuated by exp(-sigma L); summing the
+    bounces, a ray heading for the top first escapes there with
+    (1-r) q_a / (1 - r^2 q_d^2) and at the bottom with (1-r) r q_a q_d / (1 - r^2 q_d^2),
+    q_a = exp(-sigma (d - zs)/mu), q_d = exp(-sigma d/mu); averaged over mu
+    uniform in (0, 1] for each hemisphere (weight 1/2)."""
+    def parts(mu, first):
+        r = fresnel_unpolarised(mu, n, 1.0)
+        qa = math.exp(-sigma * first / mu)
+        qd = math.exp(-sigma * d / mu)
+        den = 1.0 - r * r * qd * qd
+        return (1 - r) * qa / den, (1 - r) * r * qa * qd / den
+    mc = math.sqrt(max(0.0, 1.0 - 1.0 / (n * n)))  # critical direction cosine
+    def integ(f):
+        lo = integrate.quad(f, 1e-12, mc, limit=200)[0] if mc > 0 else 0.0
+        return lo + integrate.quad(f, mc, 1.0, limit=200)[0]
+    top = 0.5 * integ(lambda mu: parts(mu, d - zs)[0]) + 0.5 * integ(lambda mu: parts(mu, zs)[1])
+    bot = 0.5 * integ(lambda mu: parts(mu, zs)[0]) + 0.5 * integ(lambda mu: parts(mu, d - zs)[1])
+    return bot, top
+
+
+def dielectric_sphere_point(n, sigma, a, s):
+    """Escape fraction of an isotropic point source at distance s from the
+    centre of a non-scattering absorbing sphere of radius a and index n: a
+    chord's impact parameter b = s sin(psi) is kept at every specular bounce,
+    so the incidence (sin = b/a) is too, and
+        escape = (1 - r) exp(-sigma L1) / (1 - r exp(-sigma C)),
+    L1 = -s mu + sqrt(a^2 - b^2) to the first hit, C = 2 sqrt(a^2 - b^2), r the
+    reflectance at that incidence (1 beyond the critical angle); averaged over
+    mu = cos(psi) uniform in [-1, 1]."""
+    def f(mu):
+        b2 = s * s * (1.0 - mu * mu)
+        h = math.sqrt(a * a - b2)
+        r = fresnel_unpolarised(h / a, n, 1.0)
+        return 0.5 * (1 - r) * math.exp(-sigma * (h - s * mu)) / (1.0 - r * math.exp(-sigma * 2 * h))
+    # the critical impact parameter a/n splits the integrand where r reaches 1
+    pts = []
+    if s > a / n:
+        mc = math.sqrt(1.0 - (a / n / s) ** 2)
+        pts = [-mc, mc]
+    return integrate.quad(f, -1.0, 1.0, points=pts or None, limit=200)[0]

@@ -399,6 +399,34 @@ def t8_halfspace(albedo, sigma_t=1.0):
                        (1 - albedo) * sigma_t, light=_beam())
 
 
+def t9_dielectric_slab_beam(ior, theta_deg, sigma_a=0.5, d=1.0, sigma_s=0.0):
+    """Slab of refractive index `ior` (vacuum outside) hit by a beam at
+    theta_deg from the normal."""
+    th = math.radians(theta_deg)
+    light = {"kind": "beam", "pos": [0.0, 0.0, 0.0], "dir": [math.sin(th), 0.0, math.cos(th)],
+             "lines": [[490.0, 1.0]]}
+    s = _one_medium({"kind": "slab", "z0": 0.0, "z1": d, "medium": 0}, sigma_s, sigma_a, light=light)
+    s["media"][0]["ior"] = float(ior)
+    return s
+
+
+def t10_dielectric_slab_point(ior, sigma_a=0.3, d=1.0, zs=0.3, sigma_s=0.0):
+    """Isotropic point source at height zs inside a refractive slab [0, d]."""
+    light = {"kind": "point", "pos": [0.0, 0.0, zs], "lines": [[490.0, 1.0]]}
+    s = _one_medium({"kind": "slab", "z0": 0.0, "z1": d, "medium": 0}, sigma_s, sigma_a, light=light)
+    s["media"][0]["ior"] = float(ior)
+    return s
+
+
+def t11_dielectric_sphere_point(ior, sigma_a=0.5, radius=1.0, offset=0.8, sigma_s=0.0):
+    """Isotropic point source at `offset` from the centre of a refractive sphere."""
+    light = {"kind": "point", "pos": [0.0, offset, radius], "lines": [[490.0, 1.0]]}
+    s = _one_medium({"kind": "sphere", "center": [0.0, 0.0, radius], "radius": radius, "medium": 0},
+                    sigma_s, sigma_a, light=light)
+    s["media"][0]["ior"] = float(ior)
+    return s
+
+
 def sphere_scene(radius=0.5, sigma_s=20.0, sigma_a_bg=0.01, conc_uM=10.0, lambda_x=490.0):
     s = slab_scene(sigma_s=sigma_s, sigma_a_bg=sigma_a_bg, conc_uM=conc_uM,
                    lambda_x=lambda_x)
