@@ -49,7 +49,7 @@
 extern "C" {
 #endif
 
-#define FPT_ABI_VERSION 1u
+#define FPT_ABI_VERSION 2u
 
 typedef enum {
     FPT_OK = 0,
@@ -114,6 +114,15 @@ typedef struct {
     int32_t n_dyes;       /* 0..FPT_MAX_MEDIUM_DYES */
     int32_t dye[FPT_MAX_MEDIUM_DYES];
     double conc_uM[FPT_MAX_MEDIUM_DYES]; /* >= 0 */
+    double ior;           /* refractive index in [1, 4]; 0 reads as 1.  A body medium
+                             (SLAB/HALFSPACE/SPHERE) with ior != 1 has a smooth dielectric
+                             boundary with the vacuum around it: a beam entering it and a
+                             path reaching it from inside are reflected specularly with the
+                             unpolarised Fresnel reflectance (1 beyond the critical angle),
+                             else cross it (Snell's law on entry; escape tallies do not
+                             depend on the outgoing direction).  Box spheres must be
+                             index-matched (FPT_E_UNSUPPORTED): a straight camera
+                             connection cannot cross a refracting surface. */
 } fpt_medium;
 
 typedef struct {

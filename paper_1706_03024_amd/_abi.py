@@ -57,7 +57,7 @@ class Dye(C.Structure):
 class Medium(C.Structure):
     _fields_ = [("sigma_s_mm", C.c_double), ("sigma_a_bg_mm", C.c_double),
                 ("n_dyes", C.c_int32), ("dye", C.c_int32 * MAX_MEDIUM_DYES),
-                ("conc_uM", C.c_double * MAX_MEDIUM_DYES)]
+                ("conc_uM", C.c_double * MAX_MEDIUM_DYES), ("ior", C.c_double)]
 
 
 class Sphere(C.Structure):
@@ -151,7 +151,7 @@ def lib():
         f = getattr(L, name)
         f.restype = res
         f.argtypes = args
-    if L.fpt_abi_version() != 1:
+    if L.fpt_abi_version() != 2:
         raise FptError(E_INVALID, "libfpt ABI version mismatch")
     _lib = L
     return L
@@ -198,6 +198,7 @@ def scene_desc(d):
     for i, m in enumerate(d["media"]):
         s.media[i].sigma_s_mm = m["sigma_s"]
         s.media[i].sigma_a_bg_mm = m["sigma_a_bg"]
+        s.media[i].ior = m.get("ior", 1.0)
         s.media[i].n_dyes = len(m["dyes"])
         for j, (di, c) in enumerate(m["dyes"]):
             s.media[i].dye[j] = di

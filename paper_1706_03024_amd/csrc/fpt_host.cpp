@@ -169,6 +169,8 @@ int32_t validate(const fpt_scene_desc* d) {
             return set_err(FPT_E_RANGE, "medium %d: sigma_a_bg must be finite and >= 0", m);
         if (md.n_dyes < 0 || md.n_dyes > FPT_MAX_MEDIUM_DYES)
             return set_err(FPT_E_RANGE, "medium %d: %d dyes", m, md.n_dyes);
+        if (!(md.ior == 0.0 || (md.ior >= 1.0 && md.ior <= 4.0)))
+            return set_err(FPT_E_RANGE, "medium %d: refractive index %g outside [1, 4]", m, md.ior);
         for (int j = 0; j < md.n_dyes; ++j) {
             if (md.dye[j] < 0 || md.dye[j] >= d->n_dyes)
                 return set_err(FPT_E_INVALID, "medium %d: dye index %d", m, md.dye[j]);
@@ -235,6 +237,9 @@ int32_t validate(const fpt_scene_desc* d) {
         const fpt_sphere& sp = d->spheres[s];
         if (!finite3(sp.center) || !(sp.radius > 0.0)) return set_err(FPT_E_INVALID, "sphere %d", s);
         if (sp.medium < 0 || sp.medium >= d->n_media) return set_err(FPT_E_INVALID, "sphere %d medium", s);
+        if (d->media[sp.medium].ior != 0.0 && d->media[sp.medium].ior != 1.0)
+            return set_err(FPT_E_UNSUPPORTED, "sphere %d: refractive media need index-matched boundaries in "
+                                              "box scenes (a camera connection cannot cross a refracting surface)", s);
         for (int a = 0; a < 3; ++a)
             if (sp.center[a] - sp.radius <= d->box_lo[a] || sp.center[a] + sp.radius >= d->box_hi[a])
                 return set_err(FPT_E_INVALID, "sphere %d must lie strictly inside the box", s);
@@ -447,6 +452,11 @@ int32_t build_tables(fpt_scene* sc) {
     P.z1 = (float)d.slab_z1;
     for (int a = 0; a < 3; ++a) P.bc[a] = (float)d.body_center[a];
     P.br2 = (float)(d.body_radius * d.body_radius);
+    P.ior = 1.f;
+    if (d.geometry == FPT_GEOM_SLAB || d.geometry == FPT_GEOM_HALFSPACE || d.geometry == FPT_GEOM_SPHERE) {
+        const double n = d.media[d.body_medium].ior;
+        P.ior = n > 0.0 ? (float)n : 1.f;
+    }
     for (int a = 0; a < 3; ++a) {
         P.lo[a] = (float)d.box_lo[a];
         P.hi[a] = (float)d.box_hi[a];

@@ -51,6 +51,7 @@ struct KParams {
     int geometry, body_medium, light, sensor;
     float z0, z1;
     float bc[3], br2;
+    float ior;  // refractive index of the body medium (1: index-matched boundary)
     float lo[3], hi[3];
     int open_face;
     // the open face's plane: unit vectors of its axis and of the two others

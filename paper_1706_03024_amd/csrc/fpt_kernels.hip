@@ -225,6 +225,49 @@ DEV void snap_to_plane(const KParams& P, Lane& L, const Hit& h) {
     }
 }
 
+// Smooth dielectric boundary of a body medium (index n, vacuum outside).
+// Unpolarised reflectance (mean of the s and p Fresnel intensities) from index
+// n1 into n2 at incidence cosine ci >= 0; 1 beyond the critical angle; ct gets
+// the transmitted cosine.
+DEV float fresnel(float ci, float n1, float n2, float& ct) {
+    const float eta = fdiv(n1, n2);
+    const float st2 = eta * eta * (1.f - ci * ci);
+    if (st2 >= 1.f) {
+        ct = 0.f;
+        return 1.f;
+    }
+    const float c2 = fsqrt(1.f - st2);
+    const float rs = fdiv(n1 * ci - n2 * c2, n1 * ci + n2 * c2);
+    const float rp = fdiv(n1 * c2 - n2 * ci, n1 * c2 + n2 * ci);
+    ct = c2;
+    return 0.5f * (rs * rs + rp * rp);
+}
+
+// Outward normal of the body's boundary at x for a path moving along w (the
+// slab face it is heading for).
+template <int GEOM>
+DEV void body_normal(const KParams& P, const float* x, const float* w, float* nb) {
+    nb[0] = nb[1] = 0.f;
+    if constexpr (GEOM == FPT_GEOM_SLAB) {
+        nb[2] = w[2] > 0.f ? 1.f : -1.f;
+    } else if constexpr (GEOM == FPT_GEOM_HALFSPACE) {
+        nb[2] = -1.f;
+    } else {
+        const float d0 = x[0] - P.bc[0], d1 = x[1] - P.bc[1], d2 = x[2] - P.bc[2];
+        const float s = __builtin_amdgcn_rsqf(d0 * d0 + d1 * d1 + d2 * d2);
+        nb[0] = d0 * s;
+        nb[1] = d1 * s;
+        nb[2] = d2 * s;
+    }
+}
+
+DEV void mirror(float* w, const float* nb) {
+    const float d = 2.f * dot3(w, nb);
+    w[0] -= d * nb[0];
+    w[1] -= d * nb[1];
+    w[2] -= d * nb[2];
+}
+
 // Length of the segment x + t wc, t in [0, dist], inside a sphere.  The
 // half-chord squared is r^2 minus the squared distance of the line from the
 // centre, taken from the perpendicular offset o - b wc: the textbook b^2 - |o|^2
@@ -1055,6 +1098,26 @@ DEV void advance(const KParams& P, const KBuffers& B, const WaveCtx& C, WalkStat
     // new path costs no evaluation of the generator of its own.
     int ev = EV_NONE;
     int exit_code = -1;
+    constexpr bool kBody = GEOM == FPT_GEOM_SLAB || GEOM == FPT_GEOM_HALFSPACE || GEOM == FPT_GEOM_SPHERE;
+    // escape through the body boundary or the open face: escape tally by side
+    auto escape = [&]() {
+        const int side = L.w[2] < 0.f ? 0 : 1;
+        exit_code = side == 0 ? FPT_EXIT_ESC_R : FPT_EXIT_ESC_T;
+        if (!pinhole && !(P.fluo_only && L.comp == 0)) {
+            const int idx = ((L.batch * 2 + L.comp) * 2 + side) * P.N + L.lam;
+            if constexpr (MODE == MODE_FWD) {
+                if (lds_hist) atomicAdd(&hist[idx], 1u);
+                else atomicAdd(&B.counts[idx], 1u);
+            }
+            L.splat_sum += P.wscale;
+            if constexpr (ADJ) {
+                const float g = B.gfilm[idx] * P.wscale;
+#pragma unroll
+                for (int i = 0; i < kMaxNP; ++i)
+                    if (i < P.np) G[i] += g * A.S[i * 64];
+            }
+        }
+    };
     if (alive && !full) {
         const bool start = fresh;
         bool step = false;
@@ -1145,23 +1208,25 @@ DEV void advance(const KParams& P, const KBuffers& B, const WaveCtx& C, WalkStat
                     }
                 } else {
                     ev = h.ev;
-                    if (ev == EV_ESC || ev == EV_INF) {
-                        const int side = L.w[2] < 0.f ? 0 : 1;
-                        exit_code = side == 0 ? FPT_EXIT_ESC_R : FPT_EXIT_ESC_T;
-                        if (!pinhole && !(P.fluo_only && L.comp == 0)) {
-                            const int idx = ((L.batch * 2 + L.comp) * 2 + side) * P.N + L.lam;
-                            if constexpr (MODE == MODE_FWD) {
-                                if (lds_hist) atomicAdd(&hist[idx], 1u);
-                                else atomicAdd(&B.counts[idx], 1u);
-                            }
-                            L.splat_sum += P.wscale;
-                            if constexpr (ADJ) {
-                                const float g = B.gfilm[idx] * P.wscale;
-#pragma unroll
-                                for (int i = 0; i < kMaxNP; ++i)
-                                    if (i < P.np) G[i] += g * A.S[i * 64];
+                    bool refl = false;
+                    if constexpr (kBody) {
+                        if (ev == EV_ESC && h.d < kInf && P.ior != 1.f) {
+                            // the body's dielectric boundary: specular reflection with
+                            // the Fresnel probability (total internal reflection beyond
+                            // the critical angle), else the path crosses out; u1 decides
+                            float nb[3], ct;
+                            body_normal<GEOM>(P, L.x, L.w, nb);
+                            if (u1 < fresnel(dot3(L.w, nb), P.ior, 1.f, ct)) {
+                                mirror(L.w, nb);
+                                lds_count(tally, FPT_T_WALL_REFLECT);
+                                refl = true;
                             }
                         }
+                    }
+                    if (refl) {
+                        // the path stays in the body with the mirrored direction
+                    } else if (ev == EV_ESC || ev == EV_INF) {
+                        escape();
                     } else if (ev == EV_LIGHT) {
                         exit_code = FPT_EXIT_LIGHT;
                     } else if (ev == EV_WALL) {
@@ -1206,10 +1271,33 @@ DEV void advance(const KParams& P, const KBuffers& B, const WaveCtx& C, WalkStat
             uint4 r1 = make_uint4(0u, 0u, 0u, 0u);
             if (need1) r1 = philox(L.pid, vc, 1u, 0u, P.key0, P.key1);
             if (start) {
+                bool reflected = false;  // off a refractive body on entry
                 if (P.light == FPT_LIGHT_BEAM) {
                     L.x[0] = P.lpos[0]; L.x[1] = P.lpos[1]; L.x[2] = P.lpos[2];
                     L.w[0] = P.ldir[0]; L.w[1] = P.ldir[1]; L.w[2] = P.ldir[2];
                     L.region = 0;
+                    if constexpr (kBody) {
+                        if (P.ior != 1.f) {
+                            // entering a refractive body: Fresnel reflection (the path
+                            // leaves at once) or refraction by Snell's law; u1 decides
+                            float nb[3], ct;
+                            const float ws[3] = {-L.w[0], -L.w[1], -L.w[2]};
+                            body_normal<GEOM>(P, L.x, ws, nb);
+                            const float ci = -dot3(L.w, nb);
+                            if (u1 < fresnel(ci, 1.f, P.ior, ct)) {
+                                mirror(L.w, nb);
+                                lds_count(tally, FPT_T_WALL_REFLECT);
+                                reflected = true;
+                            } else {
+                                const float eta = __builtin_amdgcn_rcpf(P.ior), k = eta * ci - ct;
+                                float t3[3];
+#pragma unroll
+                                for (int i = 0; i < 3; ++i) t3[i] = eta * L.w[i] + k * nb[i];
+                                const float s = __builtin_amdgcn_rsqf(dot3(t3, t3));
+                                L.w[0] = t3[0] * s; L.w[1] = t3[1] * s; L.w[2] = t3[2] * s;
+                            }
+                        }
+                    }
                 } else {
                     const float ua = u24(r1.x), ub = u24(r1.y);
                     float sp, cp;
@@ -1236,6 +1324,7 @@ DEV void advance(const KParams& P, const KBuffers& B, const WaveCtx& C, WalkStat
                 L.sc[0] = L.sc[1] = L.sc[2] = 0.f;
                 L.sr2 = 0.f;
                 load_medium(P, T, L);
+                if (reflected) escape();
                 if (pinhole && P.light == FPT_LIGHT_QUAD) {
                     pend = PEND_SOURCE;
                     nrm[0] = P.ln[0]; nrm[1] = P.ln[1]; nrm[2] = P.ln[2];

@@ -29,7 +29,7 @@ def test_library_exports_every_declared_symbol():
     assert len(syms) >= 17
     for s in syms:
         assert hasattr(L, s), s
-    assert L.fpt_abi_version() == 1
+    assert L.fpt_abi_version() == 2
     assert L.fpt_status_str(-3) == b"out of memory"
 
 
@@ -69,6 +69,8 @@ def _create_status(scene):
     (lambda s: s["dyes"][0].__setitem__("epsilon", -1.0), _abi.E_RANGE),
     (lambda s: s["media"][0].__setitem__("sigma_s", float("nan")), _abi.E_RANGE),
     (lambda s: s["media"][0].__setitem__("sigma_a_bg", -0.1), _abi.E_RANGE),
+    (lambda s: s["media"][0].__setitem__("ior", 0.5), _abi.E_RANGE),
+    (lambda s: s["media"][0].__setitem__("ior", 4.5), _abi.E_RANGE),
     (lambda s: s["light"].__setitem__("lines", [[900.0, 1.0]]), _abi.E_RANGE),
     (lambda s: s["light"].__setitem__("lines", [[490.0, 0.0]]), _abi.E_INVALID),
     (lambda s: s["grid"].__setitem__("n_bins", 1), _abi.E_RANGE),
@@ -100,6 +102,9 @@ def test_invalid_box_descriptors_rejected():
     assert _create_status(s)[0] == _abi.E_RANGE
     s = workloads.cornell_scene(8, 8)
     s["sensor"]["eye"] = [0.0, 0.0, 0.0]
+    assert _create_status(s)[0] == _abi.E_UNSUPPORTED
+    s = workloads.cornell_scene(8, 8)
+    s["media"][1]["ior"] = 1.5   # refracting sphere: no straight camera connection through it
     assert _create_status(s)[0] == _abi.E_UNSUPPORTED
 
 
