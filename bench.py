@@ -41,11 +41,13 @@ EMISSION = PHILOX + 17   # quantum-yield test, emission CDF inversion
 CAM_START = PHILOX + 90  # camera-side path: pixel of the path index, pixel sample, eye ray, box entry
 
 
-def ops_model(t, n_spheres, geometry):
+def ops_model(t, n_spheres, geometry, refractive=False):
     """Algorithmic ALU lane operations of one render from its event tallies."""
     open_geo = geometry in ("slab", "halfspace", "infinite", "sphere")
     medium = 14 if geometry in ("slab", "halfspace", "infinite") else 25   # boundary distance, event, direction
     surface = 4 if open_geo else 55 + 15 * n_spheres   # walls, light quad, sphere entries
+    if open_geo and refractive:
+        surface += 30   # boundary normal, Fresnel reflectance, mirror
     conn = 118 + 21 * n_spheres                          # camera connection and transmittance
     return (START * t["paths"]
             + (STEP + medium) * (t["scatters"] + t["dye_abs"] + t["exit_bg"])
@@ -110,7 +112,7 @@ def forward_form(scene, run, steps, warmup, tune_name=None):
     ms, t_ms, d_ms = time_renders(sc, run, steps, warmup, film)
     geo = scene["geometry"]["kind"]
     nsph = len(scene["geometry"].get("spheres", [])) if geo == "box" else 0
-    ops = ops_model(tal, nsph, geo)
+    ops = ops_model(tal, nsph, geo, refractive=scene["media"][scene["geometry"].get("medium", 0)].get("ior", 1.0) != 1.0)
     sc.close()
     return {"vertices": tal["vertices"], "ms_per_step": ms, "transport_ms": t_ms, "deferred_ms": d_ms,
             "kernel_ms": t_ms + d_ms, "vertices_per_s": tal["vertices"] / (ms / 1e3), "ops": ops,
@@ -389,6 +391,14 @@ def main():
         sl = forward_form(s1, r1, max(5, args.steps // 5), 2, tune_name="slab-2^22")
         extra["fwd_slab_2^22"] = {k: sl[k] for k in ("vertices", "ms_per_step", "vertices_per_s")}
         extra["fwd_slab_2^22"]["alu_frac"] = alu_frac(sl)
+        # the same slab behind a water boundary (n = 1.33): Fresnel reflection
+        # and total internal reflection at both faces
+        s1w = workloads.deepcopy(s1)
+        s1w["media"][0]["ior"] = 1.33
+        sw = forward_form(s1w, r1, max(5, args.steps // 5), 2, tune_name="slab-2^22")
+        extra["fwd_slab_water_2^22"] = {k: sw[k] for k in ("vertices", "ms_per_step", "vertices_per_s")}
+        extra["fwd_slab_water_2^22"]["alu_frac"] = alu_frac(sw)
+        extra["fwd_slab_water_2^22"]["boundary_reflections"] = sw["tallies"]["wall_reflect"]
         try:
             extra["fwd_adjoint"] = adjoint_form(max(3, args.steps // 10), 1)
         except Exception as e:  # reported, not hidden
