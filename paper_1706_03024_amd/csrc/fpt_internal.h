@@ -41,9 +41,6 @@ struct KParams {
     int off_rho;    // float [6][N]
     int off_kap;    // float [n_media][kap_stride][N]: d sigma_a / d conc per slot
     int kap_stride;
-    // camera-side estimator (box + pinhole + quad light), at the end of the image:
-    int off_src;    // float [n_media][N][n_lines]: w_l sum_d QY_d pmf_d(k) sigma_a,d(lambda_l) / (4 pi^2)
-    int off_csig;   // float [n_spheres][n_lines]: sigma_t of sphere s's medium at line l
     int n_media, n_dyes, n_spheres, n_lines;
     KSphere spheres[FPT_MAX_SPHERES];
     float line_cum[FPT_MAX_LINES];
@@ -51,7 +48,6 @@ struct KParams {
     int geometry, body_medium, light, sensor;
     float z0, z1;
     float bc[3], br2;
-    float ior;  // refractive index of the body medium (1: index-matched boundary)
     float lo[3], hi[3];
     int open_face;
     // the open face's plane: unit vectors of its axis and of the two others
@@ -62,7 +58,6 @@ struct KParams {
     float lu_inv2, lv_inv2;
     float eye[3], cf[3], cr[3], cu[3];
     float inv_tanx, inv_tany;
-    float tanx, tany;
     int W, H;
     float splat_norm;  // N_pix / A_img
     int film_u32;      // film element indices fit 32 bits (deposits merge per wave)
@@ -82,6 +77,14 @@ struct KParams {
     int max_segments;      // long paths served per block round: 1, 2 or 4
     int wide_rounds;       // forward: deep paths walk 128 vertices per round (0 off); a path is
                            // deep after any full round (1) or a full whole-wave round (2)
+    // Fields added after the rest: the box forward kernel keeps the earlier ones in
+    // scalar registers, and moving them (by inserting fields before them) changed
+    // its scalar-register spills enough to cost 9 % of its instructions.
+    // camera-side estimator (box + pinhole + quad light), at the end of the image:
+    int off_src;    // float [n_media][N][n_lines]: w_l sum_d QY_d pmf_d(k) sigma_a,d(lambda_l) / (4 pi^2)
+    int off_csig;   // float [n_spheres][n_lines]: sigma_t of sphere s's medium at line l
+    float tanx, tany;
+    float ior;  // refractive index of the body medium (1: index-matched boundary)
 };
 
 struct KBuffers {
