@@ -119,7 +119,7 @@ def forward_form(scene, run, steps, warmup, tune_name=None):
             "tallies": tal, "tune": tune}
 
 
-def camera_form(steps, warmup):
+def camera_form(steps, warmup, cpu=False):
     """The camera-side estimator (eq. 12, sec. 4.1) on the Cornell scene:
     128x128 pixels x 101 emission bins x 8 samples, paths from the eye with a
     light connection at every collision in a dye sphere."""
@@ -136,10 +136,31 @@ def camera_form(steps, warmup):
     ms, k_ms, _ = time_renders(sc, run, steps, warmup, film, camera=True)
     sc.close()
     ops = camera_ops(tal, len(scene["geometry"]["spheres"]), len(scene["light"]["lines"]))
-    return {"vertices": tal["vertices"], "paths": run["path_count"], "ms_per_step": ms,
-            "kernel_ms": k_ms, "vertices_per_s": tal["vertices"] / (ms / 1e3),
-            "light_connections": tal["splat_hit"] + tal["splat_miss"],
-            "alu_frac": ops / (k_ms / 1e3) / 1e12 / ALU_PEAK_TOPS}
+    out = {"vertices": tal["vertices"], "paths": run["path_count"], "ms_per_step": ms,
+           "kernel_ms": k_ms, "vertices_per_s": tal["vertices"] / (ms / 1e3),
+           "light_connections": tal["splat_hit"] + tal["splat_miss"],
+           "alu_frac": ops / (k_ms / 1e3) / 1e12 / ALU_PEAK_TOPS}
+    if cpu:
+        out["cpu_oracle"] = camera_cpu_sample(scene, run)
+    return out
+
+
+def camera_cpu_sample(scene, run, chunks=256, chunk=8192):
+    """The camera-side oracle (1 thread, fp64) on a bounded sample of the
+    same job: `chunks` runs of `chunk` consecutive paths spread evenly over the
+    path index range (pixels top to bottom, all samples)."""
+    import oracle
+    n = run["path_count"]
+    verts, dt = 0, 0.0
+    for i in range(chunks):
+        begin = (n - chunk) * i // max(1, chunks - 1)
+        t0 = time.perf_counter()
+        o = oracle.render_camera(scene, dict(run, path_begin=begin, path_count=chunk), film=False)
+        dt += time.perf_counter() - t0
+        verts += int(o["tallies"][1])
+    return {"value": verts / dt, "unit": "path vertices/s", "cores": 1, "kind": "oracle",
+            "sample": f"{chunks} ranges of {chunk} paths spread over the {n}-path job "
+                      f"({verts} vertices, {dt:.1f} s, fp64, 1 thread)"}
 
 
 def alu_frac(form):
@@ -407,7 +428,7 @@ def main():
         if b is not None:
             extra["batched"] = b
         extra["excitation_scan"] = sweep_form(max(3, args.steps // 5), 1)
-        extra["camera_side"] = camera_form(max(3, args.steps // 5), 1)
+        extra["camera_side"] = camera_form(max(3, args.steps // 5), 1, cpu=not args.no_cpu_baseline)
     line["forms"] = extra
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(scene, run)
