@@ -726,6 +726,9 @@ int32_t batch_build_items(fpt_batch* bt) {
     K.slot_words = batch_slot_words(bt->hist_words, bt->max_table_words);
     K.counts = bt->d_counts;
     K.item_counter = bt->d_counter;
+    K.refractive = 0;
+    for (int i = 0; i < bt->n; ++i)
+        if (bt->params[i].ior != 1.f) K.refractive = 1;
     int b = bt->tune.block_threads > 0 ? bt->tune.block_threads : 256;
     bt->block = std::max(64, std::min(256, (b / 64) * 64));
     int per_cu = 0;

@@ -122,6 +122,7 @@ struct KBatch {
     uint32_t* counts;               // [n_instances][hist_words] escape counts
     unsigned long long* tallies;    // [n_instances][FPT_N_TALLIES] or null
     unsigned long long* item_counter;
+    int refractive;                 // some instance has a refracting body boundary
 };
 
 }  // namespace fpt

@@ -1044,7 +1044,10 @@ DEV void assign_path(WalkState& W, uint32_t pid) {
 // One iteration of the walk for every live lane: wave-cooperative blocks for
 // long paths, one segment of the walk, the convergent splat section and the
 // bookkeeping of paths that ended.
-template <int GEOM, int MODE>
+// REFR: the body medium has a refracting boundary (index != 1).  A separate
+// instantiation, because the Fresnel code costs registers (and with them
+// occupancy) even in launches that never run it.
+template <int GEOM, int MODE, bool REFR>
 DEV void advance(const KParams& P, const KBuffers& B, const WaveCtx& C, WalkState& W, AdjView& A,
                  float* G, bool exhausted) {
     constexpr bool DEFER = (GEOM == FPT_GEOM_BOX && MODE == MODE_FWD);  // queued splats
@@ -1121,7 +1124,7 @@ DEV void advance(const KParams& P, const KBuffers& B, const WaveCtx& C, WalkStat
     // new path costs no evaluation of the generator of its own.
     int ev = EV_NONE;
     int exit_code = -1;
-    constexpr bool kBody = GEOM == FPT_GEOM_SLAB || GEOM == FPT_GEOM_HALFSPACE || GEOM == FPT_GEOM_SPHERE;
+    constexpr bool kBody = REFR && (GEOM == FPT_GEOM_SLAB || GEOM == FPT_GEOM_HALFSPACE || GEOM == FPT_GEOM_SPHERE);
     // escape through the body boundary or the open face: escape tally by side
     auto escape = [&]() {
         const int side = L.w[2] < 0.f ? 0 : 1;
@@ -1498,7 +1501,7 @@ DEV void advance(const KParams& P, const KBuffers& B, const WaveCtx& C, WalkStat
 
 // -------------------------------------------------------------------------
 // The persistent transport kernel.
-template <int GEOM, int MODE>
+template <int GEOM, int MODE, bool REFR>
 __global__ void __launch_bounds__(256) k_transport(const KParams P, const KBuffers B) {
     constexpr bool ADJ = (MODE == MODE_ADJ || MODE == MODE_REC_ADJ);
     constexpr bool REC = (MODE == MODE_REC || MODE == MODE_REC_ADJ);
@@ -1617,7 +1620,7 @@ __global__ void __launch_bounds__(256) k_transport(const KParams P, const KBuffe
         }
         if (__ballot(W.alive) == 0ull && !exhausted) continue;
         // with every lane done and the queue exhausted this only drains the splats
-        advance<GEOM, MODE>(P, B, C, W, A, G, exhausted);
+        advance<GEOM, MODE, REFR>(P, B, C, W, A, G, exhausted);
         if (exhausted && __ballot(W.alive) == 0ull) break;
     }
 
@@ -1706,6 +1709,7 @@ DEV void batch_flush(const KBatch& Bt, int inst, uint32_t* tally, uint32_t* hist
     wave_sync();
 }
 
+template <bool REFR>
 __global__ void __launch_bounds__(256) k_batch(const KBatch Bt) {
     extern __shared__ uint32_t smem[];
     const int wave = threadIdx.x >> 6;
@@ -1805,8 +1809,8 @@ __global__ void __launch_bounds__(256) k_batch(const KBatch Bt) {
             if (done && pending < 0 && lo >= hi) break;
             continue;
         }
-        if (P.geometry == FPT_GEOM_SLAB) advance<FPT_GEOM_SLAB, MODE_FWD>(P, Bd, C, W, A, G, false);
-        else advance<FPT_GEOM_SPHERE, MODE_FWD>(P, Bd, C, W, A, G, false);
+        if (P.geometry == FPT_GEOM_SLAB) advance<FPT_GEOM_SLAB, MODE_FWD, REFR>(P, Bd, C, W, A, G, false);
+        else advance<FPT_GEOM_SPHERE, MODE_FWD, REFR>(P, Bd, C, W, A, G, false);
     }
     if (cur >= 0) batch_flush(Bt, cur, tally, hist, W.cnt, lane);
 }
@@ -1876,12 +1880,16 @@ int batch_slot_words(int hist_words, int max_table_words) {
 }
 
 hipError_t batch_occupancy(const KBatch& Bt, int block, int* n) {
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, reinterpret_cast<const void*>(&k_batch), block,
-                                                        batch_lds_bytes(Bt, block));
+    const void* f = Bt.refractive ? reinterpret_cast<const void*>(&k_batch<true>)
+                                  : reinterpret_cast<const void*>(&k_batch<false>);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, f, block, batch_lds_bytes(Bt, block));
 }
 
 hipError_t launch_batch(const KBatch& Bt, int grid, int block, hipStream_t s) {
-    hipLaunchKernelGGL(k_batch, dim3(grid), dim3(block), batch_lds_bytes(Bt, block), s, Bt);
+    if (Bt.refractive)
+        hipLaunchKernelGGL((k_batch<true>), dim3(grid), dim3(block), batch_lds_bytes(Bt, block), s, Bt);
+    else
+        hipLaunchKernelGGL((k_batch<false>), dim3(grid), dim3(block), batch_lds_bytes(Bt, block), s, Bt);
     return hipGetLastError();
 }
 
@@ -2346,7 +2354,10 @@ size_t transport_lds_bytes(const KParams& P, int block_threads, int mode) {
 template <int GEOM, int MODE>
 static hipError_t launch_t(const KParams& P, const KBuffers& B, int grid, int block, size_t lds,
                            hipStream_t s) {
-    hipLaunchKernelGGL((k_transport<GEOM, MODE>), dim3(grid), dim3(block), lds, s, P, B);
+    if (P.ior != 1.f)
+        hipLaunchKernelGGL((k_transport<GEOM, MODE, true>), dim3(grid), dim3(block), lds, s, P, B);
+    else
+        hipLaunchKernelGGL((k_transport<GEOM, MODE, false>), dim3(grid), dim3(block), lds, s, P, B);
     return hipGetLastError();
 }
 
@@ -2357,25 +2368,31 @@ static hipError_t launch_m(const KParams& P, const KBuffers& B, int grid, int bl
     case FPT_GEOM_SLAB: return launch_t<FPT_GEOM_SLAB, MODE>(P, B, grid, block, lds, s);
     case FPT_GEOM_HALFSPACE: return launch_t<FPT_GEOM_HALFSPACE, MODE>(P, B, grid, block, lds, s);
     case FPT_GEOM_SPHERE: return launch_t<FPT_GEOM_SPHERE, MODE>(P, B, grid, block, lds, s);
-    case FPT_GEOM_INFINITE: return launch_t<FPT_GEOM_INFINITE, MODE>(P, B, grid, block, lds, s);
-    default: return launch_t<FPT_GEOM_BOX, MODE>(P, B, grid, block, lds, s);
+    case FPT_GEOM_INFINITE:
+        hipLaunchKernelGGL((k_transport<FPT_GEOM_INFINITE, MODE, false>), dim3(grid), dim3(block), lds, s, P, B);
+        return hipGetLastError();
+    default:
+        hipLaunchKernelGGL((k_transport<FPT_GEOM_BOX, MODE, false>), dim3(grid), dim3(block), lds, s, P, B);
+        return hipGetLastError();
     }
 }
 
-template <int GEOM, int MODE>
+template <int GEOM, int MODE, bool REFR>
 static hipError_t occ_t(const KParams& P, int block, int* n) {
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, reinterpret_cast<const void*>(&k_transport<GEOM, MODE>),
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(n, reinterpret_cast<const void*>(&k_transport<GEOM, MODE, REFR>),
                                                         block, transport_lds_bytes(P, block, MODE));
 }
 
 template <int MODE>
 static hipError_t occ_m(const KParams& P, int block, int* n) {
+    const bool r = P.ior != 1.f;
     switch (P.geometry) {
-    case FPT_GEOM_SLAB: return occ_t<FPT_GEOM_SLAB, MODE>(P, block, n);
-    case FPT_GEOM_HALFSPACE: return occ_t<FPT_GEOM_HALFSPACE, MODE>(P, block, n);
-    case FPT_GEOM_SPHERE: return occ_t<FPT_GEOM_SPHERE, MODE>(P, block, n);
-    case FPT_GEOM_INFINITE: return occ_t<FPT_GEOM_INFINITE, MODE>(P, block, n);
-    default: return occ_t<FPT_GEOM_BOX, MODE>(P, block, n);
+    case FPT_GEOM_SLAB: return r ? occ_t<FPT_GEOM_SLAB, MODE, true>(P, block, n) : occ_t<FPT_GEOM_SLAB, MODE, false>(P, block, n);
+    case FPT_GEOM_HALFSPACE:
+        return r ? occ_t<FPT_GEOM_HALFSPACE, MODE, true>(P, block, n) : occ_t<FPT_GEOM_HALFSPACE, MODE, false>(P, block, n);
+    case FPT_GEOM_SPHERE: return r ? occ_t<FPT_GEOM_SPHERE, MODE, true>(P, block, n) : occ_t<FPT_GEOM_SPHERE, MODE, false>(P, block, n);
+    case FPT_GEOM_INFINITE: return occ_t<FPT_GEOM_INFINITE, MODE, false>(P, block, n);
+    default: return occ_t<FPT_GEOM_BOX, MODE, false>(P, block, n);
     }
 }
 
