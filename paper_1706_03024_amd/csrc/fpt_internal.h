@@ -117,7 +117,7 @@ struct KBatch {
     const KWorkItem* items;         // [n_items], largest expected cost first
     int n_items;
     int n_instances;
-    int slot_words;                 // LDS words per wave: params | tally | histogram | table
+    int slot_words;                 // LDS words per wave: tally | histogram | table
     int hist_words;                 // 4 * n_bins
     uint32_t* counts;               // [n_instances][hist_words] escape counts
     unsigned long long* tallies;    // [n_instances][FPT_N_TALLIES] or null
