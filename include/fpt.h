@@ -49,7 +49,7 @@
 extern "C" {
 #endif
 
-#define FPT_ABI_VERSION 2u
+#define FPT_ABI_VERSION 3u
 
 typedef enum {
     FPT_OK = 0,
@@ -70,7 +70,8 @@ typedef enum {
 #define FPT_MAX_GRAD_PARAMS 16
 #define FPT_N_TALLIES 20
 
-enum { FPT_SPECTRUM_NONE = 0, FPT_SPECTRUM_GAUSS_MIX = 1, FPT_SPECTRUM_PIECEWISE_LINEAR = 2 };
+enum { FPT_SPECTRUM_NONE = 0, FPT_SPECTRUM_GAUSS_MIX = 1, FPT_SPECTRUM_PIECEWISE_LINEAR = 2,
+       FPT_SPECTRUM_TABULATED = 3 };
 enum { FPT_GEOM_SLAB = 0, FPT_GEOM_HALFSPACE = 1, FPT_GEOM_SPHERE = 2, FPT_GEOM_INFINITE = 3,
        FPT_GEOM_BOX = 4 };
 enum { FPT_LIGHT_BEAM = 0, FPT_LIGHT_POINT = 1, FPT_LIGHT_QUAD = 2 };
@@ -91,14 +92,18 @@ enum { FPT_T_PATHS = 0, FPT_T_VERTICES = 1, FPT_T_SCATTERS = 2, FPT_T_DYE_ABS = 
        FPT_T_SPLAT_HIT = 7, FPT_T_SPLAT_MISS = 8, FPT_T_SPLAT_RR_KILL = 9,
        FPT_T_EXIT0 = 10 /* + exit code */ };
 
-/* A spectrum on nm: a Gaussian mixture sum_i value_i exp(-(l-center_i)^2/(2 width_i^2))
- * or a piecewise-linear curve through (center_i, value_i), constant beyond the ends. */
+/* A spectrum on nm: a Gaussian mixture sum_i value_i exp(-(l-center_i)^2/(2 width_i^2)),
+ * a piecewise-linear curve through (center_i, value_i), constant beyond the ends, or
+ * TABULATED: one value per point of the scene's grid (measured spectra, e.g. a dye
+ * database sampled on the grid), table[k] at lambda_k. */
 typedef struct {
     int32_t kind; /* FPT_SPECTRUM_* */
-    int32_t n;    /* 1..FPT_MAX_SPECTRUM_TERMS */
+    int32_t n;    /* 1..FPT_MAX_SPECTRUM_TERMS; TABULATED: n_bins */
     double center_nm[FPT_MAX_SPECTRUM_TERMS];
     double value[FPT_MAX_SPECTRUM_TERMS];
     double width_nm[FPT_MAX_SPECTRUM_TERMS];
+    const double* table; /* TABULATED: host array of n finite values, read (and copied by
+                            fpt_scene_create) during the call only; NULL otherwise */
 } fpt_spectrum;
 
 typedef struct {

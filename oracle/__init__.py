@@ -38,7 +38,8 @@ def build(verbose=False):
 
 class Spectrum(C.Structure):
     _fields_ = [("kind", C.c_int32), ("n", C.c_int32), ("x", C.c_double * MAX_TERMS),
-                ("y", C.c_double * MAX_TERMS), ("s", C.c_double * MAX_TERMS)]
+                ("y", C.c_double * MAX_TERMS), ("s", C.c_double * MAX_TERMS),
+                ("tab", C.c_void_p)]
 
 
 class Dye(C.Structure):
@@ -130,7 +131,7 @@ class OracleError(RuntimeError):
     pass
 
 
-def _spectrum(dst, spec):
+def _spectrum(dst, spec, keep):
     if spec is None:
         dst.kind = 0
         dst.n = 0
@@ -147,19 +148,27 @@ def _spectrum(dst, spec):
         dst.n = len(knots)
         for i, (nm, v) in enumerate(knots):
             dst.x[i], dst.y[i] = nm, v
+    elif "table" in spec:
+        vals = np.ascontiguousarray(spec["table"], dtype=np.float64)
+        keep.append(vals)
+        dst.kind = 3
+        dst.n = len(vals)
+        dst.tab = vals.ctypes.data
     else:
         raise OracleError(f"unknown spectrum {spec}")
 
 
 def make_scene(d):
     sc = Scene()
+    keep = []   # tabulated spectra: arrays the struct points at, alive with it
+    sc._keep = keep
     g = d["grid"]
     sc.n_bins, sc.lo_nm, sc.hi_nm = g["n_bins"], g["lo_nm"], g["hi_nm"]
     sc.natural_base = 1 if d.get("absorptivity_base", "decadic") == "natural" else 0
     sc.n_dyes = len(d["dyes"])
     for i, dy in enumerate(d["dyes"]):
-        _spectrum(sc.dyes[i].absorption, dy["absorption"])
-        _spectrum(sc.dyes[i].emission, dy["emission"])
+        _spectrum(sc.dyes[i].absorption, dy["absorption"], keep)
+        _spectrum(sc.dyes[i].emission, dy["emission"], keep)
         sc.dyes[i].epsilon = dy["epsilon"]
         sc.dyes[i].qy = dy["qy"]
     sc.n_media = len(d["media"])
@@ -189,7 +198,7 @@ def make_scene(d):
         sc.box_hi[:] = geo["hi"]
         sc.open_face = geo["open_face"]
         for f, w in enumerate(geo["walls"]):
-            _spectrum(sc.walls[f], w)
+            _spectrum(sc.walls[f], w, keep)
         sc.n_spheres = len(geo["spheres"])
         for i, sp in enumerate(geo["spheres"]):
             sc.spheres[i].center[:] = sp["center"]

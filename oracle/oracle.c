@@ -80,7 +80,9 @@ typedef struct {
     double line_cum[ORC_MAX_LINES];
 } tables_t;
 
-static double eval_spectrum(const orc_spectrum* s, double lam) {
+/* Value at grid point k (wavelength lam): tabulated spectra are given on the grid. */
+static double eval_spectrum(const orc_spectrum* s, double lam, int k) {
+    if (s->kind == ORC_SPEC_TAB) return s->tab[k];
     if (s->kind == ORC_SPEC_GAUSS) {
         double v = 0.0;
         for (int i = 0; i < s->n; ++i) {
@@ -103,8 +105,15 @@ static double eval_spectrum(const orc_spectrum* s, double lam) {
     return 0.0;
 }
 
-static int check_spectrum(const orc_spectrum* s, int allow_none) {
+static int check_spectrum(const orc_spectrum* s, int allow_none, int n_bins) {
     if (s->kind == ORC_SPEC_NONE) return allow_none ? 0 : fail("spectrum missing");
+    if (s->kind == ORC_SPEC_TAB) {
+        if (!s->tab || s->n != n_bins) return fail("tabulated spectrum needs n_bins values");
+        for (int k = 0; k < n_bins; ++k)
+            if (!isfinite(s->tab[k])) return fail("spectrum not finite");
+        return 0;
+    }
+    if (s->kind != ORC_SPEC_GAUSS && s->kind != ORC_SPEC_PWL) return fail("unknown spectrum kind");
     if (s->n < 1 || s->n > ORC_MAX_TERMS) return fail("spectrum term count out of range");
     for (int i = 0; i < s->n; ++i) {
         if (!isfinite(s->x[i]) || !isfinite(s->y[i])) return fail("spectrum not finite");
@@ -137,7 +146,8 @@ static int validate(const orc_scene* sc) {
     if (sc->n_media < 0 || sc->n_media > ORC_MAX_MEDIA) return fail("n_media out of range");
     for (int d = 0; d < sc->n_dyes; ++d) {
         const orc_dye* dy = &sc->dyes[d];
-        if (check_spectrum(&dy->absorption, 0) || check_spectrum(&dy->emission, 0)) return -1;
+        if (check_spectrum(&dy->absorption, 0, sc->n_bins) || check_spectrum(&dy->emission, 0, sc->n_bins))
+            return -1;
         if (!(dy->qy >= 0.0 && dy->qy <= 1.0)) return fail("qy outside [0,1]");
         if (!(dy->epsilon >= 0.0) || !isfinite(dy->epsilon)) return fail("epsilon < 0");
     }
@@ -161,7 +171,7 @@ static int validate(const orc_scene* sc) {
     if (sc->geom == ORC_GEOM_BOX) {
         if (sc->light != ORC_LIGHT_QUAD) return fail("box scenes need a quad light");
         for (int f = 0; f < 6; ++f)
-            if (f != sc->open_face && check_spectrum(&sc->walls[f], 0)) return -1;
+            if (f != sc->open_face && check_spectrum(&sc->walls[f], 0, sc->n_bins)) return -1;
         if (sc->n_spheres < 0 || sc->n_spheres > ORC_MAX_SPHERES) return fail("n_spheres");
         for (int s = 0; s < sc->n_spheres; ++s) {
             const orc_sphere* sp = &sc->spheres[s];
@@ -202,8 +212,8 @@ static int build_tables(const orc_scene* sc, tables_t* t) {
         const orc_dye* dy = &sc->dyes[d];
         double amax = 0.0, esum = 0.0;
         for (int k = 0; k < N; ++k) {
-            double a = eval_spectrum(&dy->absorption, t->lambda[k]);
-            double e = eval_spectrum(&dy->emission, t->lambda[k]);
+            double a = eval_spectrum(&dy->absorption, t->lambda[k], k);
+            double e = eval_spectrum(&dy->emission, t->lambda[k], k);
             if (a < 0.0 || e < 0.0) { free_tables(t); return fail("negative spectrum value"); }
             t->a_hat[d * N + k] = a;
             t->pmf[d * N + k] = e;
@@ -241,7 +251,7 @@ static int build_tables(const orc_scene* sc, tables_t* t) {
     if (sc->geom == ORC_GEOM_BOX) {
         for (int f = 0; f < 6; ++f) {
             for (int k = 0; k < N; ++k) {
-                double r = (f == sc->open_face) ? 0.0 : eval_spectrum(&sc->walls[f], t->lambda[k]);
+                double r = (f == sc->open_face) ? 0.0 : eval_spectrum(&sc->walls[f], t->lambda[k], k);
                 if (!(r >= 0.0 && r <= 1.0)) { free_tables(t); return fail("wall rho outside [0,1]"); }
                 t->rho[f * N + k] = r;
             }

@@ -44,7 +44,7 @@
 #define ORC_MAX_BINS 2048
 #define ORC_MAX_PARAMS (ORC_MAX_MEDIA * ORC_MAX_MEDIUM_DYES + ORC_MAX_DYES + ORC_MAX_MEDIA)
 
-enum { ORC_SPEC_NONE = 0, ORC_SPEC_GAUSS = 1, ORC_SPEC_PWL = 2 };
+enum { ORC_SPEC_NONE = 0, ORC_SPEC_GAUSS = 1, ORC_SPEC_PWL = 2, ORC_SPEC_TAB = 3 };
 enum { ORC_GEOM_SLAB = 0, ORC_GEOM_HALFSPACE = 1, ORC_GEOM_SPHERE = 2,
        ORC_GEOM_INFINITE = 3, ORC_GEOM_BOX = 4 };
 enum { ORC_LIGHT_BEAM = 0, ORC_LIGHT_POINT = 1, ORC_LIGHT_QUAD = 2 };
@@ -67,6 +67,7 @@ typedef struct {
     double x[ORC_MAX_TERMS]; /* Gaussian mean (nm) or knot position (nm) */
     double y[ORC_MAX_TERMS]; /* Gaussian weight or knot value */
     double s[ORC_MAX_TERMS]; /* Gaussian standard deviation (nm) */
+    const double* tab;       /* ORC_SPEC_TAB: n = n_bins values, one per grid point */
 } orc_spectrum;
 
 typedef struct {

@@ -9,6 +9,8 @@ from __future__ import annotations
 import ctypes as C
 import os
 
+import numpy as np
+
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libfpt.so")
 
@@ -23,7 +25,7 @@ MAX_GRAD_PARAMS = 16
 N_TALLIES = 20
 
 OK, E_INVALID, E_RANGE, E_NOMEM, E_DEVICE, E_UNSUPPORTED = 0, -1, -2, -3, -4, -5
-SPECTRUM_GAUSS_MIX, SPECTRUM_PIECEWISE_LINEAR = 1, 2
+SPECTRUM_GAUSS_MIX, SPECTRUM_PIECEWISE_LINEAR, SPECTRUM_TABULATED = 1, 2, 3
 GEOM = {"slab": 0, "halfspace": 1, "sphere": 2, "infinite": 3, "box": 4}
 LIGHT = {"beam": 0, "point": 1, "quad": 2}
 SENSOR = {"escape": 0, "pinhole": 1}
@@ -46,7 +48,7 @@ class FptError(RuntimeError):
 class Spectrum(C.Structure):
     _fields_ = [("kind", C.c_int32), ("n", C.c_int32),
                 ("center_nm", C.c_double * MAX_TERMS), ("value", C.c_double * MAX_TERMS),
-                ("width_nm", C.c_double * MAX_TERMS)]
+                ("width_nm", C.c_double * MAX_TERMS), ("table", C.c_void_p)]
 
 
 class Dye(C.Structure):
@@ -151,7 +153,7 @@ def lib():
         f = getattr(L, name)
         f.restype = res
         f.argtypes = args
-    if L.fpt_abi_version() != 2:
+    if L.fpt_abi_version() != 3:
         raise FptError(E_INVALID, "libfpt ABI version mismatch")
     _lib = L
     return L
@@ -163,7 +165,7 @@ def check(status):
 
 
 # ---------------------------------------------------------------- marshalling
-def _spectrum(dst, spec):
+def _spectrum(dst, spec, keep):
     if spec is None:
         dst.kind = 0
         dst.n = 0
@@ -178,20 +180,30 @@ def _spectrum(dst, spec):
         dst.n = len(spec["pwl"])
         for i, (nm, v) in enumerate(spec["pwl"]):
             dst.center_nm[i], dst.value[i] = nm, v
+    elif "table" in spec:
+        vals = np.ascontiguousarray(spec["table"], dtype=np.float64)
+        keep.append(vals)
+        dst.kind = SPECTRUM_TABULATED
+        dst.n = len(vals)
+        dst.table = vals.ctypes.data
     else:
         raise FptError(E_INVALID, f"unknown spectrum {spec!r}")
 
 
 def scene_desc(d):
-    """Scene dictionary (see the workloads module) -> fpt_scene_desc."""
+    """Scene dictionary (see the workloads module) -> fpt_scene_desc.  The
+    struct keeps the arrays of tabulated spectra alive (attribute _keep); the
+    library copies them at fpt_scene_create / fpt_batch_create."""
     s = SceneDesc()
+    keep = []
+    s._keep = keep
     g = d["grid"]
     s.n_bins, s.lo_nm, s.hi_nm = g["n_bins"], g["lo_nm"], g["hi_nm"]
     s.absorptivity_base = 1 if d.get("absorptivity_base", "decadic") == "natural" else 0
     s.n_dyes = len(d["dyes"])
     for i, y in enumerate(d["dyes"]):
-        _spectrum(s.dyes[i].absorption, y["absorption"])
-        _spectrum(s.dyes[i].emission, y["emission"])
+        _spectrum(s.dyes[i].absorption, y["absorption"], keep)
+        _spectrum(s.dyes[i].emission, y["emission"], keep)
         s.dyes[i].epsilon_M_cm = y["epsilon"]
         s.dyes[i].qy = y["qy"]
     s.n_media = len(d["media"])
@@ -217,7 +229,7 @@ def scene_desc(d):
         s.box_hi[:] = geo["hi"]
         s.open_face = geo["open_face"]
         for f, w in enumerate(geo["walls"]):
-            _spectrum(s.walls[f], w)
+            _spectrum(s.walls[f], w, keep)
         s.n_spheres = len(geo["spheres"])
         for i, sp in enumerate(geo["spheres"]):
             s.spheres[i].center[:] = sp["center"]

@@ -10,6 +10,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <deque>
 #include <vector>
 
 #include "fpt.h"
@@ -89,7 +90,19 @@ double spectrum_at(const fpt_spectrum& s, double lam) {
     return s.value[i - 1] + (lam - x0) / (x1 - x0) * (s.value[i] - s.value[i - 1]);
 }
 
-int32_t check_spectrum(const fpt_spectrum& s, const char* what) {
+// Value at grid point k (wavelength lam).
+double spectrum_on_grid(const fpt_spectrum& s, double lam, int k) {
+    return s.kind == FPT_SPECTRUM_TABULATED ? s.table[k] : spectrum_at(s, lam);
+}
+
+int32_t check_spectrum(const fpt_spectrum& s, const char* what, int n_bins) {
+    if (s.kind == FPT_SPECTRUM_TABULATED) {
+        if (!s.table) return set_err(FPT_E_INVALID, "%s: tabulated spectrum without a table", what);
+        if (s.n != n_bins) return set_err(FPT_E_RANGE, "%s: %d tabulated values for %d grid points", what, s.n, n_bins);
+        for (int k = 0; k < s.n; ++k)
+            if (!std::isfinite(s.table[k])) return set_err(FPT_E_INVALID, "%s: non-finite tabulated value", what);
+        return FPT_OK;
+    }
     if (s.kind != FPT_SPECTRUM_GAUSS_MIX && s.kind != FPT_SPECTRUM_PIECEWISE_LINEAR)
         return set_err(FPT_E_INVALID, "%s: unknown spectrum kind %d", what, s.kind);
     if (s.n < 1 || s.n > FPT_MAX_SPECTRUM_TERMS)
@@ -139,6 +152,7 @@ struct fpt_scene {
     fpt_tune tune;
     std::vector<float> h_st, h_cdf, h_rho;
     std::vector<int> h_line_bin;
+    std::deque<std::vector<double>> tabs;  // copies of tabulated spectra the descriptor points at
 };
 
 namespace {
@@ -155,8 +169,8 @@ int32_t validate(const fpt_scene_desc* d) {
     for (int i = 0; i < d->n_dyes; ++i) {
         const fpt_dye& y = d->dyes[i];
         int32_t rc;
-        if ((rc = check_spectrum(y.absorption, "dye absorption")) != FPT_OK) return rc;
-        if ((rc = check_spectrum(y.emission, "dye emission")) != FPT_OK) return rc;
+        if ((rc = check_spectrum(y.absorption, "dye absorption", d->n_bins)) != FPT_OK) return rc;
+        if ((rc = check_spectrum(y.emission, "dye emission", d->n_bins)) != FPT_OK) return rc;
         if (!(y.qy >= 0.0 && y.qy <= 1.0)) return set_err(FPT_E_RANGE, "dye %d: qy %g outside [0,1]", i, y.qy);
         if (!(y.epsilon_M_cm >= 0.0) || !std::isfinite(y.epsilon_M_cm))
             return set_err(FPT_E_RANGE, "dye %d: epsilon must be finite and >= 0", i);
@@ -226,7 +240,7 @@ int32_t validate(const fpt_scene_desc* d) {
     if (d->open_face < 0 || d->open_face > 5) return set_err(FPT_E_INVALID, "open_face %d", d->open_face);
     for (int f = 0; f < 6; ++f) {
         if (f == d->open_face) continue;
-        int32_t rc = check_spectrum(d->walls[f], "wall");
+        int32_t rc = check_spectrum(d->walls[f], "wall", d->n_bins);
         if (rc != FPT_OK) return rc;
     }
     if (d->light != FPT_LIGHT_QUAD) return set_err(FPT_E_UNSUPPORTED, "box scenes need a quad light");
@@ -292,8 +306,8 @@ int32_t build_tables(fpt_scene* sc) {
     for (int i = 0; i < d.n_dyes; ++i) {
         double peak = 0.0, area = 0.0;
         for (int k = 0; k < N; ++k) {
-            const double a = spectrum_at(d.dyes[i].absorption, lam[k]);
-            const double e = spectrum_at(d.dyes[i].emission, lam[k]);
+            const double a = spectrum_on_grid(d.dyes[i].absorption, lam[k], k);
+            const double e = spectrum_on_grid(d.dyes[i].emission, lam[k], k);
             if (a < 0.0 || e < 0.0) return set_err(FPT_E_INVALID, "dye %d: negative spectrum value", i);
             ahat[(size_t)i * N + k] = a;
             cdf[(size_t)i * N + k] = e;
@@ -396,7 +410,7 @@ int32_t build_tables(fpt_scene* sc) {
     if (d.geometry == FPT_GEOM_BOX) {
         for (int f = 0; f < 6; ++f) {
             for (int k = 0; k < N; ++k) {
-                const double r = (f == d.open_face) ? 0.0 : spectrum_at(d.walls[f], lam[k]);
+                const double r = (f == d.open_face) ? 0.0 : spectrum_on_grid(d.walls[f], lam[k], k);
                 if (!(r >= 0.0 && r <= 1.0)) return set_err(FPT_E_RANGE, "wall %d reflectance outside [0,1]", f);
                 img[P.off_rho + f * N + k] = fbits((float)r);
                 sc->h_rho[(size_t)f * N + k] = (float)r;
@@ -772,6 +786,17 @@ int32_t fpt_scene_create(const fpt_scene_desc* desc, fpt_scene** out) {
     fpt_scene* sc = new (std::nothrow) fpt_scene();
     if (!sc) return set_err(FPT_E_NOMEM, "host allocation");
     sc->desc = *desc;
+    // tabulated spectra are borrowed for the call: keep copies and point at them
+    auto own = [sc](fpt_spectrum& s) {
+        if (s.kind != FPT_SPECTRUM_TABULATED) return;
+        sc->tabs.emplace_back(s.table, s.table + s.n);
+        s.table = sc->tabs.back().data();
+    };
+    for (int i = 0; i < sc->desc.n_dyes; ++i) {
+        own(sc->desc.dyes[i].absorption);
+        own(sc->desc.dyes[i].emission);
+    }
+    for (int f = 0; f < 6; ++f) own(sc->desc.walls[f]);
     std::memset(&sc->tune, 0, sizeof sc->tune);
     if ((rc = build_tables(sc)) != FPT_OK) {
         delete sc;

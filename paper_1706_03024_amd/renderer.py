@@ -224,7 +224,9 @@ class Batch:
         self.runs = runs
         self.n = n
         self.n_bins = scenes[0]["grid"]["n_bins"]
-        self._descs = (_abi.SceneDesc * n)(*[_abi.scene_desc(s) for s in scenes])
+        descs = [_abi.scene_desc(s) for s in scenes]
+        self._descs = (_abi.SceneDesc * n)(*descs)
+        self._desc_keep = [d._keep for d in descs]   # tabulated spectra, until created
         self._runs = (_abi.Run * n)(*[_abi.run_struct(r) for r in runs])
         t = None
         if tune is not None:

@@ -29,7 +29,7 @@ def test_library_exports_every_declared_symbol():
     assert len(syms) >= 17
     for s in syms:
         assert hasattr(L, s), s
-    assert L.fpt_abi_version() == 2
+    assert L.fpt_abi_version() == 3
     assert L.fpt_status_str(-3) == b"out of memory"
 
 
@@ -70,6 +70,9 @@ def _create_status(scene):
     (lambda s: s["media"][0].__setitem__("sigma_s", float("nan")), _abi.E_RANGE),
     (lambda s: s["media"][0].__setitem__("sigma_a_bg", -0.1), _abi.E_RANGE),
     (lambda s: s["media"][0].__setitem__("ior", 0.5), _abi.E_RANGE),
+    (lambda s: s["dyes"][0].__setitem__("absorption", {"table": [1.0] * 100}), _abi.E_RANGE),
+    (lambda s: s["dyes"][0].__setitem__("emission", {"table": [1.0] * 100 + [float("nan")]}),
+     _abi.E_INVALID),
     (lambda s: s["media"][0].__setitem__("ior", 4.5), _abi.E_RANGE),
     (lambda s: s["light"].__setitem__("lines", [[900.0, 1.0]]), _abi.E_RANGE),
     (lambda s: s["light"].__setitem__("lines", [[490.0, 0.0]]), _abi.E_INVALID),

@@ -289,3 +289,22 @@ def test_halfspace_albedo(albedo):
     assert t["exit_scap"] == 0
     R = cf.halfspace_albedo(albedo)
     assert abs(binom_z(t["exit_esc_r"], n, R)) < 4.5
+
+
+def test_tabulated_spectra_reproduce_the_analytic_scene():
+    """Tabulated spectra are read on the grid points: the Cornell scene with
+    every dye spectrum and wall reflectance sampled on its grid has the same
+    tables (to the rounding of evaluating the same Gaussians in another
+    language) and walks every path the same way."""
+    s = workloads.cornell_scene(8, 8)
+    t = workloads.tabulated_scene(s)
+    ta, tb = oracle.tables(s), oracle.tables(t)
+    for k in ta:
+        np.testing.assert_allclose(np.asarray(tb[k], float), np.asarray(ta[k], float),
+                                   rtol=1e-13, atol=1e-300)
+    run = workloads.make_run(1 << 12, seed=6)
+    a = oracle.render(s, run, records=True)
+    b = oracle.render(t, run, records=True)
+    assert np.array_equal(a["records"]["exit_code"], b["records"]["exit_code"])
+    assert np.array_equal(a["records"]["n_vertices"], b["records"]["n_vertices"])
+    np.testing.assert_allclose(b["film"], a["film"], rtol=1e-9, atol=1e-300)

@@ -459,3 +459,39 @@ def dark_box_scene(sphere_medium=None, width=32, height=32, n_bins=101, lines=No
 
 def deepcopy(x):
     return copy.deepcopy(x)
+
+
+def tabulate(scene, spectrum):
+    """The spectrum sampled on the scene's grid, as a tabulated spectrum (the
+    form measured spectra take).  Pure sampling of the analytic description."""
+    g = scene["grid"]
+    n, lo, hi = g["n_bins"], g["lo_nm"], g["hi_nm"]
+    lam = [lo + (hi - lo) * k / (n - 1) for k in range(n)]
+    if "gauss" in spectrum:
+        vals = [sum(w * math.exp(-0.5 * ((x - mu) / sd) ** 2) for mu, sd, w in spectrum["gauss"])
+                for x in lam]
+    else:
+        knots = spectrum["pwl"]
+        vals = []
+        for x in lam:
+            if x <= knots[0][0]:
+                vals.append(knots[0][1])
+            elif x >= knots[-1][0]:
+                vals.append(knots[-1][1])
+            else:
+                i = next(j for j in range(1, len(knots)) if x <= knots[j][0])
+                (x0, y0), (x1, y1) = knots[i - 1], knots[i]
+                vals.append(y0 + (x - x0) / (x1 - x0) * (y1 - y0))
+    return {"table": vals}
+
+
+def tabulated_scene(scene):
+    """Every dye spectrum and wall reflectance of `scene` as a tabulated spectrum."""
+    s = copy.deepcopy(scene)
+    for d in s["dyes"]:
+        d["absorption"] = tabulate(s, d["absorption"])
+        d["emission"] = tabulate(s, d["emission"])
+    geo = s["geometry"]
+    if geo["kind"] == "box":
+        geo["walls"] = [None if w is None else tabulate(s, w) for w in geo["walls"]]
+    return s
