@@ -294,6 +294,14 @@ def measured_traffic(workload):
     return None if w is None else w["bytes_per_launch"]
 
 
+def hbm_rate(form, workload, ms):
+    """HBM bytes per launch from the recorded counter runs (while the kernel
+    source matches them) over the launch time, in GB/s; 8000 GB/s is the peak."""
+    t = measured_traffic(workload)
+    if t is not None and ms > 0:
+        form["hbm_gb_per_s"] = t / (ms / 1e3) / 1e9
+
+
 def profile_run(name, steps):
     """Kernels for a profiler: a plain device copy of COPY_BYTES (reads and
     writes that many bytes; calibrates FETCH_SIZE / WRITE_SIZE) and `steps`
@@ -407,11 +415,13 @@ def main():
         big = forward_form(s3, r3, max(2, args.steps // 25), 1)
         extra["fwd_large"] = {k: big[k] for k in ("vertices", "ms_per_step", "vertices_per_s")}
         extra["fwd_large"]["alu_frac"] = alu_frac(big)
+        hbm_rate(extra["fwd_large"], "large", big["kernel_ms"])
         s1, r1 = workloads.slab_config()
         r1 = dict(r1, path_count=1 << 22, total_paths=1 << 22)
         sl = forward_form(s1, r1, max(5, args.steps // 5), 2, tune_name="slab-2^22")
         extra["fwd_slab_2^22"] = {k: sl[k] for k in ("vertices", "ms_per_step", "vertices_per_s")}
         extra["fwd_slab_2^22"]["alu_frac"] = alu_frac(sl)
+        hbm_rate(extra["fwd_slab_2^22"], "slab", sl["kernel_ms"])
         # the same slab behind a water boundary (n = 1.33): Fresnel reflection
         # and total internal reflection at both faces
         s1w = workloads.deepcopy(s1)
@@ -427,8 +437,10 @@ def main():
         b = batched_form(max(3, args.steps // 10), 1)
         if b is not None:
             extra["batched"] = b
+            hbm_rate(b, "batched", b["ms_per_step"])
         extra["excitation_scan"] = sweep_form(max(3, args.steps // 5), 1)
         extra["camera_side"] = camera_form(max(3, args.steps // 5), 1, cpu=not args.no_cpu_baseline)
+        hbm_rate(extra["camera_side"], "camera", extra["camera_side"]["kernel_ms"])
     line["forms"] = extra
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(scene, run)
