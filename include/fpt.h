@@ -199,7 +199,9 @@ typedef struct {
 
 /* Launch shape knobs; all-zero = library defaults.  Results never depend on them. */
 typedef struct {
-    int32_t block_threads;  /* 64..256, multiple of 64 */
+    int32_t block_threads;  /* 64..256, multiple of 64; halved (to 128, then 64) where the
+                               scene's table image and per-wave buffers would exceed the
+                               160 KiB of LDS one workgroup may hold */
     int32_t blocks_per_cu;  /* persistent blocks per compute unit */
     int32_t refill_lanes;   /* a wave refills dead lanes once this many are dead (1..64;
                                default 48 with a camera, 60 with escape sensors, 8 batched) */
@@ -273,7 +275,10 @@ int32_t fpt_scene_timing(fpt_scene* scene, int32_t* renders, float* transport_ms
 /* Forward render.  Accumulates (+=) into film_dev (device, fp32, film shape)
  * and tallies_dev (device, FPT_N_TALLIES uint64; optional, may be NULL).
  * Escape films are integer counts scaled by parity_batches/total_paths at the
- * end of the call; camera films are fp32 atomic sums.  Asynchronous. */
+ * end of the call; camera films are fp32 atomic sums.  Asynchronous.
+ * FPT_E_UNSUPPORTED, before any launch, if the scene's table image does not
+ * fit in LDS beside one wave's buffers (e.g. 8 media with 4 dyes each at 1024
+ * bins); the same holds for the adjoint and the records hook. */
 int32_t fpt_render(fpt_scene* scene, const fpt_run* run, float* film_dev, uint64_t* tallies_dev,
                    void* hip_stream);
 
@@ -337,7 +342,10 @@ int32_t fpt_scene_tables(const fpt_scene* scene, float* sigma_t, float* emis_cdf
  * chunk) work items from a device queue; the launch sequence is captured in a
  * hipGraph on the first render and replayed after.  runs[i] gives instance
  * i's seed, instance key and path count.  Films: [n][2][2][n_bins] fp32,
- * accumulated; tallies: [n][FPT_N_TALLIES] uint64 (optional). */
+ * accumulated; tallies: [n][FPT_N_TALLIES] uint64 (optional).  Every wave
+ * holds one instance's tables and histogram in LDS: blocks get fewer waves
+ * where the tuned size would not fit, and FPT_E_UNSUPPORTED is returned if
+ * one wave's slot does not fit on its own. */
 int32_t fpt_batch_create(const fpt_scene_desc* descs, const fpt_run* runs, int32_t n,
                          const fpt_tune* tune, fpt_batch** out);
 int32_t fpt_batch_render(fpt_batch* batch, float* films_dev, uint64_t* tallies_dev,

@@ -660,6 +660,23 @@ int block_for(const fpt_scene* sc) {
     return b;
 }
 
+// LDS one workgroup may allocate on gfx950.
+constexpr size_t kLdsLimit = 160u * 1024u;
+
+// Block size of a transport launch: the tuned one, halved (to 128, then 64
+// threads) while the table image and the per-wave LDS areas do not fit; a scene
+// whose image does not fit beside even one wave is refused before any launch.
+int32_t transport_block(const fpt_scene* sc, const KParams& P, int mode, int* block) {
+    int b = block_for(sc);
+    while (b > 64 && transport_lds_bytes(P, b, mode) > kLdsLimit) b = b > 128 ? 128 : 64;
+    const size_t need = transport_lds_bytes(P, b, mode);
+    if (need > kLdsLimit)
+        return set_err(FPT_E_UNSUPPORTED, "table image of %d words needs %zu bytes of LDS per workgroup (limit %zu)",
+                       P.table_words, need, kLdsLimit);
+    *block = b;
+    return FPT_OK;
+}
+
 }  // namespace
 
 struct fpt_batch {
@@ -744,7 +761,14 @@ int32_t batch_build_items(fpt_batch* bt) {
     for (int i = 0; i < bt->n; ++i)
         if (bt->params[i].ior != 1.f) K.refractive = 1;
     int b = bt->tune.block_threads > 0 ? bt->tune.block_threads : 256;
-    bt->block = std::max(64, std::min(256, (b / 64) * 64));
+    b = std::max(64, std::min(256, (b / 64) * 64));
+    // every wave holds a whole slot (tables, histogram, tally): fewer waves
+    // per block where the slots of the tuned size do not fit
+    while (b > 64 && batch_lds_bytes(K, b) > kLdsLimit) b = b > 128 ? 128 : 64;
+    if (batch_lds_bytes(K, b) > kLdsLimit)
+        return set_err(FPT_E_UNSUPPORTED, "instance slot of %d words needs %zu bytes of LDS (limit %zu)",
+                       K.slot_words, batch_lds_bytes(K, b), kLdsLimit);
+    bt->block = b;
     int per_cu = 0;
     HIP_TRY(batch_occupancy(K, bt->block, &per_cu), "batch occupancy");
     if (bt->tune.blocks_per_cu > 0) per_cu = std::min(per_cu, bt->tune.blocks_per_cu);
@@ -934,8 +958,9 @@ int32_t fpt_render(fpt_scene* sc, const fpt_run* run, float* film, uint64_t* tal
     fill_run(sc, run, B, &P);
     const bool escape = sc->desc.sensor == FPT_SENSOR_ESCAPE;
     const size_t n_counts = escape ? (size_t)film_elems(sc->desc, B) : 0;
+    int block;
+    if ((rc = transport_block(sc, P, MODE_FWD, &block)) != FPT_OK) return rc;
     if ((rc = ensure_scratch(sc, n_counts, 0)) != FPT_OK) return rc;
-    const int block = block_for(sc);
     int grid;
     if ((rc = grid_for(sc, P, MODE_FWD, block, run->path_count, &grid)) != FPT_OK) return rc;
     KBuffers Bf;
@@ -986,7 +1011,8 @@ int32_t fpt_render_adjoint(fpt_scene* sc, const fpt_run* run, const float* gfilm
     hipStream_t s = (hipStream_t)stream;
     KParams P;
     fill_run(sc, run, B, &P);
-    const int block = block_for(sc);
+    int block;
+    if ((rc = transport_block(sc, P, MODE_ADJ, &block)) != FPT_OK) return rc;
     int grid;
     if ((rc = grid_for(sc, P, MODE_ADJ, block, run->path_count, &grid)) != FPT_OK) return rc;
     if ((rc = ensure_scratch(sc, 0, (size_t)grid * kMaxNP)) != FPT_OK) return rc;
@@ -1018,7 +1044,8 @@ int32_t fpt_render_records(fpt_scene* sc, const fpt_run* run, fpt_path_record* r
     fill_run(sc, run, B, &P);
     P.max_vertices = max_vertices;
     const int mode = gfilm ? MODE_REC_ADJ : MODE_REC;
-    const int block = block_for(sc);
+    int block;
+    if ((rc = transport_block(sc, P, mode, &block)) != FPT_OK) return rc;
     int grid;
     if ((rc = grid_for(sc, P, mode, block, run->path_count, &grid)) != FPT_OK) return rc;
     KBuffers Bf;
@@ -1052,8 +1079,9 @@ int32_t fpt_render_camera(fpt_scene* sc, const fpt_run* run, float* film, uint64
     P.wscale = (float)((double)B / (double)(run->total_paths / per_sample));
     P.max_vertices = max_vertices;
     P.refill_lanes = sc->tune.refill_lanes > 0 ? std::min(64, sc->tune.refill_lanes) : 32;
-    if (camera_lds_bytes(P) > 160u * 1024u)
-        return set_err(FPT_E_UNSUPPORTED, "table image of %d words exceeds LDS", P.table_words);
+    if (camera_lds_bytes(P) > kLdsLimit)
+        return set_err(FPT_E_UNSUPPORTED, "table image of %d words needs %zu bytes of LDS per workgroup (limit %zu)",
+                       P.table_words, camera_lds_bytes(P), kLdsLimit);
     const bool records = rec != nullptr;
     const int block = block_for(sc);
     int per_cu = 0;

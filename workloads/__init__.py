@@ -457,6 +457,38 @@ def dark_box_scene(sphere_medium=None, width=32, height=32, n_bins=101, lines=No
     }
 
 
+def maximal_scene(n_bins=101, width=16):
+    """The box at every descriptor maximum the ABI allows: 8 spheres, each of
+    its own medium; 8 dyes, 4 in every medium; 8 light lines; a 16-term
+    absorption spectrum.  Spheres of radius 0.22 sit at (+-0.5, +-0.5, +-0.5);
+    scattering 4-32/mm, concentrations 2-16 uM."""
+    dyes = []
+    for i in range(8):
+        a_mean, e_mean = 380.0 + 45.0 * i, 420.0 + 45.0 * i
+        absorption = gauss((a_mean, 18.0, 1.0), (a_mean - 30.0, 25.0, 0.3))
+        if i == 0:   # the most terms a spectrum may have
+            absorption = gauss(*[(360.0 + 8.0 * j, 6.0 + j, 1.0 / (1 + j)) for j in range(16)])
+        dyes.append({"absorption": absorption, "emission": gauss((e_mean, 22.0, 1.0)),
+                     "epsilon": 2e4 + 8e3 * i, "qy": 0.3 + 0.08 * i})
+    media, spheres = [], []
+    for m in range(8):
+        media.append({"sigma_s": 4.0 * (m + 1), "sigma_a_bg": 0.02,
+                      "dyes": [[(m + j) % 8, 2.0 * (1 + (m + 3 * j) % 8)] for j in range(4)]})
+        c = [0.5 if m & 1 else -0.5, 0.5 if m & 2 else -0.5, 0.5 if m & 4 else -0.5]
+        spheres.append({"center": c, "radius": 0.22, "medium": m})
+    lines = [(400.0 + 50.0 * i, 1.0 + 0.25 * i) for i in range(8)]
+    return {
+        "grid": grid(n_bins),
+        "absorptivity_base": "decadic",
+        "dyes": dyes,
+        "media": media,
+        "geometry": {"kind": "box", "lo": [-1.0, -1.0, -1.0], "hi": [1.0, 1.0, 1.0],
+                     "open_face": 5, "walls": _box_walls(), "spheres": spheres},
+        "light": _quad_light(lines),
+        "sensor": _pinhole(width, width),
+    }
+
+
 def deepcopy(x):
     return copy.deepcopy(x)
 
