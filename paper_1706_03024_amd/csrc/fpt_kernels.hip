@@ -2168,7 +2168,12 @@ DEV void cam_finish(const KParams& P, const KBuffers& B, uint32_t* tally, const 
     }
 }
 
-constexpr uint32_t kCamChunk = 512;
+// Paths per claim: 128 consecutive paths (a pixel's bins and part of the next).
+// Measured on the 128x128x101x8 job: 512 took 3.88 ms, 256 2.83, 192 2.55,
+// 160 2.50, 128 2.46, 96 2.59, 64 3.27 (more claims on the one counter); the
+// last chunks of larger claims left a few waves with hundreds of paths to walk
+// while the rest of the chip had run out.
+constexpr uint32_t kCamChunk = 128;
 constexpr uint32_t kCamBlockMinV = 24;  // paths in a sphere from this vertex on walk in wave rounds
 constexpr int kCamRounds = 8;           // wave rounds per iteration
 
