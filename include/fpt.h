@@ -204,11 +204,12 @@ typedef struct {
                                160 KiB of LDS one workgroup may hold */
     int32_t blocks_per_cu;  /* persistent blocks per compute unit */
     int32_t refill_lanes;   /* a wave refills dead lanes once this many are dead (1..64;
-                               default 48 with a camera, 60 with escape sensors, 8 batched) */
+                               default 48 with a camera (adjoint 32, camera-side
+                               estimator 32), 60 with escape sensors, 8 batched) */
     int32_t chunk_paths;    /* batched: paths per work item */
     int32_t block_min_vertices; /* paths in a medium with this many vertices walk in wave-wide
-                                   blocks (default 2 with a camera, 8 with escape sensors,
-                                   64 batched) */
+                                   blocks (default 2 with a camera (adjoint 8), 8 with
+                                   escape sensors, 64 batched) */
     int32_t block_segments; /* paths per block round: 1, 2 or 4 (default 4, batched 2); paths
                                whose last round ran full width always get a whole wave */
     int32_t wide_rounds;    /* forward renders: such paths walk 128 vertices per round;
