@@ -190,8 +190,14 @@ def adjoint_form(steps, warmup):
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) / steps * 1e3
     sc.close()
+    # the adjoint replays the forward walk event for event (same random
+    # numbers, same connections): both launches do at least the forward's
+    # operations; the gradient arithmetic on top of them is not counted
+    ops = 2 * ops_model(tal, len(scene["geometry"]["spheres"]), "box")
     return {"vertices": tal["vertices"], "ms_per_step": ms,
-            "vertices_per_s": tal["vertices"] / (ms / 1e3)}
+            "vertices_per_s": tal["vertices"] / (ms / 1e3),
+            "alu_frac": ops / (ms / 1e3) / 1e12 / ALU_PEAK_TOPS,
+            "alu_frac_counts": "the replayed walk in both launches; gradient arithmetic not counted"}
 
 
 def batched_form(steps, warmup):
@@ -207,7 +213,7 @@ def batched_form(steps, warmup):
     b.close()
     b = fpt.Batch(scenes, runs, tune={k: v for k, v in tune.items() if k != "ms"})
     films = b.new_films()
-    tal = b.count_vertices()
+    ops, tal = batch_ops(b, scenes)
     for _ in range(warmup):
         b.render(films)
     torch.cuda.synchronize()
@@ -218,7 +224,26 @@ def batched_form(steps, warmup):
     ms = (time.perf_counter() - t0) / steps * 1e3
     b.close()
     return {"vertices": tal, "ms_per_step": ms, "vertices_per_s": tal / (ms / 1e3),
-            "instances": len(scenes), "tune": tune}
+            "instances": len(scenes), "tune": tune,
+            "alu_frac": ops / (ms / 1e3) / 1e12 / ALU_PEAK_TOPS}
+
+
+def batch_ops(b, scenes):
+    """Lane operations and vertices of one batched render, from every
+    instance's own event tallies and geometry."""
+    import torch
+    import paper_1706_03024_amd as fpt
+    t = fpt.new_tallies(len(scenes))
+    b.render(b.new_films(), t)
+    torch.cuda.synchronize()
+    ops = verts = 0
+    for i, s in enumerate(scenes):
+        ti = fpt.tallies_dict(t[i])
+        geo = s["geometry"]
+        refr = s["media"][geo.get("medium", 0)].get("ior", 1.0) != 1.0
+        ops += ops_model(ti, 0, geo["kind"], refractive=refr)
+        verts += ti["vertices"]
+    return ops, verts
 
 
 def sweep_form(steps, warmup):
@@ -230,7 +255,7 @@ def sweep_form(steps, warmup):
     scenes, runs = workloads.excitation_scan()
     b = fpt.Batch(scenes, runs)
     films = b.new_films()
-    tal = b.count_vertices()
+    ops, tal = batch_ops(b, scenes)
     for _ in range(warmup):
         b.render(films)
     torch.cuda.synchronize()
@@ -241,7 +266,7 @@ def sweep_form(steps, warmup):
     ms = (time.perf_counter() - t0) / steps * 1e3
     b.close()
     return {"vertices": tal, "ms_per_step": ms, "vertices_per_s": tal / (ms / 1e3),
-            "instances": len(scenes)}
+            "instances": len(scenes), "alu_frac": ops / (ms / 1e3) / 1e12 / ALU_PEAK_TOPS}
 
 
 def cpu_baseline(scene, run, target_s=12.0):
