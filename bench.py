@@ -360,7 +360,7 @@ def profile_run(name, steps):
     if name == "slab":
         run = dict(run, path_count=1 << 22, total_paths=1 << 22)
     sc = fpt.Scene(scene)
-    tune_name = {"cornell": "cornell-128-64spp", "slab": "slab-2^22"}.get(name)
+    tune_name = {"cornell": "cornell-128-64spp", "slab": "slab-2^22", "large": "large-512-1024spp"}.get(name)
     if tune_name:
         print(f"launch shape: {autotune.autotune(tune_name, scene=sc, run=run, measure=False)} "
               f"(device {autotune.device_tag()})", flush=True)
@@ -437,7 +437,7 @@ def main():
     extra = {}
     if not args.no_extra:
         s3, r3 = workloads.large_config()
-        big = forward_form(s3, r3, max(2, args.steps // 25), 1)
+        big = forward_form(s3, r3, max(2, args.steps // 25), 1, tune_name="large-512-1024spp")
         extra["fwd_large"] = {k: big[k] for k in ("vertices", "ms_per_step", "vertices_per_s")}
         extra["fwd_large"]["alu_frac"] = alu_frac(big)
         hbm_rate(extra["fwd_large"], "large", big["kernel_ms"])

@@ -262,11 +262,16 @@ def test_cornell_full_size_sampled():
 
 
 def test_large_scene_sampled_replay():
-    """Large 5-sphere scene (301 bins, sigma_s up to 1000/mm): 4096 sampled paths,
-    first 256 vertices, replay against the oracle."""
+    """Large 5-sphere scene (301 bins, sigma_s up to 1000/mm), in the
+    benchmark's launch shape: 4096 sampled paths, first 256 vertices, replay
+    against the oracle."""
+    from paper_1706_03024_amd import autotune
     scene, run = workloads.large_config()
     sub = dict(run, path_begin=123456789, path_count=4096)
-    g = _records(scene, sub, max_vertices=256)
+    sc = _fpt().Scene(scene)
+    autotune.autotune("large-512-1024spp", scene=sc, run=run, measure=False)  # the cached shape, if any
+    g, _ = sc.records(sub, max_vertices=256)
+    sc.close()
     o = oracle.render(scene, sub, records=True, max_vertices=256)["records"]
     rep = compare_records(g, o, scale=1.0, sigma_t_max=1000.0)
     print(rep)
