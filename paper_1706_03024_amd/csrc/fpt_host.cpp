@@ -18,6 +18,7 @@
 
 namespace fpt {
 size_t transport_lds_bytes(const KParams& P, int block_threads, int mode);
+size_t splat_jobs_lds_bytes(const KParams& P);
 hipError_t launch_transport(const KParams& P, const KBuffers& B, int mode, int grid, int block,
                             hipStream_t s);
 hipError_t transport_occupancy(const KParams& P, int mode, int block, int* blocks_per_cu);
@@ -669,7 +670,10 @@ constexpr size_t kLdsLimit = 160u * 1024u;
 int32_t transport_block(const fpt_scene* sc, const KParams& P, int mode, int* block) {
     int b = block_for(sc);
     while (b > 64 && transport_lds_bytes(P, b, mode) > kLdsLimit) b = b > 128 ? 128 : 64;
-    const size_t need = transport_lds_bytes(P, b, mode);
+    size_t need = transport_lds_bytes(P, b, mode);
+    // forward pinhole renders also launch the deferred-connection kernel (four waves)
+    if (mode == MODE_FWD && P.geometry == FPT_GEOM_BOX && P.sensor == FPT_SENSOR_PINHOLE)
+        need = std::max(need, splat_jobs_lds_bytes(P));
     if (need > kLdsLimit)
         return set_err(FPT_E_UNSUPPORTED, "table image of %d words needs %zu bytes of LDS per workgroup (limit %zu)",
                        P.table_words, need, kLdsLimit);

@@ -1861,9 +1861,12 @@ __global__ void __launch_bounds__(256) k_splat_jobs(const KParams P, const KBuff
         atomicAdd(&B.tallies[threadIdx.x], (unsigned long long)tally[threadIdx.x]);
 }
 
+size_t splat_jobs_lds_bytes(const KParams& P) {
+    return (size_t)(kLdsTable + ((P.off_kap + 63) & ~63) + 4 * kAggWords) * 4;
+}
+
 hipError_t launch_splat_jobs(const KParams& P, const KBuffers& B, int grid, hipStream_t s) {
-    const size_t lds = (size_t)(kLdsTable + ((P.off_kap + 63) & ~63) + 4 * kAggWords) * 4;
-    hipLaunchKernelGGL(k_splat_jobs, dim3(grid), dim3(256), lds, s, P, B);
+    hipLaunchKernelGGL(k_splat_jobs, dim3(grid), dim3(256), splat_jobs_lds_bytes(P), s, P, B);
     return hipGetLastError();
 }
 
