@@ -1275,7 +1275,7 @@ int32_t fpt_autotune(fpt_scene* sc, const fpt_run* run, fpt_batch* bt, fpt_tune*
     const int blocks[2] = {128, 256};
     if (sc) {
         for (int b : blocks)
-            for (int r : {16, 32, 48, 60})
+            for (int r : {16, 32, 40, 48, 60})
                 for (int m : {1, 2, 8})
                     for (int g : {2, 4})
                         for (int wr : {1, 2}) cand.push_back(fpt_tune{b, 0, r, 0, m, g, wr});
@@ -1312,24 +1312,34 @@ int32_t fpt_autotune(fpt_scene* sc, const fpt_run* run, fpt_batch* bt, fpt_tune*
         return FPT_OK;
     };
     // a short screen of every candidate, then the best few again with more
-    // renders, so the choice is not decided by one lucky measurement
+    // renders, so the choice is not decided by one lucky measurement; short
+    // jobs get more renders per candidate (at least ~5 ms screened and ~50 ms
+    // re-timed, in three interleaved passes over the finalists)
+    float probe = 0.f;
+    rc = time_cand(saved, 1, &probe);
+    const int screen_reps = rc == FPT_OK ? std::max(3, std::min(200, (int)std::ceil(5.f / std::max(probe, 1e-3f)))) : 3;
+    const int final_reps = rc == FPT_OK ? std::max(4, std::min(600, (int)std::ceil(17.f / std::max(probe, 1e-3f)))) : 4;
     std::vector<std::pair<float, size_t>> screen;
     for (size_t i = 0; i < cand.size() && rc == FPT_OK; ++i) {
         float ms = 0.f;
-        rc = time_cand(cand[i], 3, &ms);
+        rc = time_cand(cand[i], screen_reps, &ms);
         screen.push_back({ms, i});
     }
     if (rc == FPT_OK) {
         std::sort(screen.begin(), screen.end());
         const size_t keep = std::min<size_t>(screen.size(), 6);
-        for (size_t k = 0; k < keep && rc == FPT_OK; ++k) {
-            float ms = 0.f;
-            rc = time_cand(cand[screen[k].second], 12, &ms);
-            if (rc == FPT_OK && ms < best) {
-                best = ms;
+        std::vector<float> total(keep, 0.f);
+        for (int pass = 0; pass < 3 && rc == FPT_OK; ++pass)
+            for (size_t k = 0; k < keep && rc == FPT_OK; ++k) {
+                float ms = 0.f;
+                rc = time_cand(cand[screen[k].second], final_reps, &ms);
+                total[k] += ms / 3.f;
+            }
+        for (size_t k = 0; k < keep && rc == FPT_OK; ++k)
+            if (total[k] < best) {
+                best = total[k];
                 best_t = cand[screen[k].second];
             }
-        }
     }
     if (sc) sc->tune = saved;
     else {
