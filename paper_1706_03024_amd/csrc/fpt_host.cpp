@@ -1284,7 +1284,7 @@ int32_t fpt_autotune(fpt_scene* sc, const fpt_run* run, fpt_batch* bt, fpt_tune*
             for (int r : {8, 32})
                 for (int m : {16, 64})
                     for (int g : {1, 2})
-                        for (int c : {1024, 4096}) cand.push_back(fpt_tune{b, 0, r, c, m, g, 0});
+                        for (int c : {512, 1024, 4096}) cand.push_back(fpt_tune{b, 0, r, c, m, g, 0});
     }
     float best = 1e30f;
     fpt_tune best_t = saved;
