@@ -252,8 +252,12 @@ def sweep_form(steps, warmup):
     import torch
     import paper_1706_03024_amd as fpt
     import workloads
+    from paper_1706_03024_amd import autotune
     scenes, runs = workloads.excitation_scan()
     b = fpt.Batch(scenes, runs)
+    tune = autotune.autotune("excitation-scan-81", batch=b)
+    b.close()
+    b = fpt.Batch(scenes, runs, tune={k: v for k, v in tune.items() if k != "ms"})
     films = b.new_films()
     ops, tal = batch_ops(b, scenes)
     for _ in range(warmup):
@@ -266,7 +270,8 @@ def sweep_form(steps, warmup):
     ms = (time.perf_counter() - t0) / steps * 1e3
     b.close()
     return {"vertices": tal, "ms_per_step": ms, "vertices_per_s": tal / (ms / 1e3),
-            "instances": len(scenes), "alu_frac": ops / (ms / 1e3) / 1e12 / ALU_PEAK_TOPS}
+            "instances": len(scenes), "tune": tune,
+            "alu_frac": ops / (ms / 1e3) / 1e12 / ALU_PEAK_TOPS}
 
 
 def cpu_baseline(scene, run, target_s=12.0):
