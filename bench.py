@@ -321,7 +321,35 @@ def measured_traffic(workload):
     if rec.get("kernel_source") != kernel_source_hash():
         return None
     w = rec.get("workloads", {}).get(workload)
-    return None if w is None else w["bytes_per_launch"]
+    return None if w is None else w.get("bytes_per_launch")
+
+
+FP32_PEAK_TFLOPS = 157.3   # MI355X vector FP32 (packed FMA)
+
+
+def measured_fp32(workload):
+    """FP32 FLOPs issued per launch (per step for the forward+adjoint pair)
+    from the recorded SQ_INSTS_VALU_FLOPS_FP32 counter runs (wave instructions,
+    FMA = 2, x 64 lanes: every lane of an issued instruction is counted), or
+    None when the kernel source has changed since they were taken."""
+    try:
+        with open(TRAFFIC_JSON) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_source") != kernel_source_hash():
+        return None
+    w = rec.get("workloads", {}).get(workload)
+    return None if w is None else w.get("fp32_flops_per_launch")
+
+
+def fp32_rate(form, workload, ms):
+    """Issued FP32 FLOP rate over the launch time and its fraction of the
+    MI355X FP32 vector peak."""
+    f = measured_fp32(workload)
+    if f and ms > 0:
+        form["fp32_tflops"] = f / (ms / 1e3) / 1e12
+        form["fp32_frac"] = form["fp32_tflops"] / FP32_PEAK_TFLOPS
 
 
 def hbm_rate(form, workload, ms):
@@ -439,6 +467,7 @@ def main():
                      "kernel_ms": head["kernel_ms"], "transport_ms": head["transport_ms"],
                      "deferred_ms": head["deferred_ms"], "ops_per_launch": head["ops"]},
     }
+    fp32_rate(line["roofline"], "cornell", head["kernel_ms"])
     extra = {}
     if not args.no_extra:
         s3, r3 = workloads.large_config()
@@ -446,12 +475,14 @@ def main():
         extra["fwd_large"] = {k: big[k] for k in ("vertices", "ms_per_step", "vertices_per_s")}
         extra["fwd_large"]["alu_frac"] = alu_frac(big)
         hbm_rate(extra["fwd_large"], "large", big["kernel_ms"])
+        fp32_rate(extra["fwd_large"], "large", big["kernel_ms"])
         s1, r1 = workloads.slab_config()
         r1 = dict(r1, path_count=1 << 22, total_paths=1 << 22)
         sl = forward_form(s1, r1, max(5, args.steps // 5), 2, tune_name="slab-2^22")
         extra["fwd_slab_2^22"] = {k: sl[k] for k in ("vertices", "ms_per_step", "vertices_per_s")}
         extra["fwd_slab_2^22"]["alu_frac"] = alu_frac(sl)
         hbm_rate(extra["fwd_slab_2^22"], "slab", sl["kernel_ms"])
+        fp32_rate(extra["fwd_slab_2^22"], "slab", sl["kernel_ms"])
         # the same slab behind a water boundary (n = 1.33): Fresnel reflection
         # and total internal reflection at both faces
         s1w = workloads.deepcopy(s1)
@@ -462,15 +493,18 @@ def main():
         extra["fwd_slab_water_2^22"]["boundary_reflections"] = sw["tallies"]["wall_reflect"]
         try:
             extra["fwd_adjoint"] = adjoint_form(max(3, args.steps // 10), 1)
+            fp32_rate(extra["fwd_adjoint"], "adjoint", extra["fwd_adjoint"]["ms_per_step"])
         except Exception as e:  # reported, not hidden
             extra["fwd_adjoint"] = {"error": str(e)}
         b = batched_form(max(3, args.steps // 10), 1)
         if b is not None:
             extra["batched"] = b
             hbm_rate(b, "batched", b["ms_per_step"])
+            fp32_rate(b, "batched", b["ms_per_step"])
         extra["excitation_scan"] = sweep_form(max(3, args.steps // 5), 1)
         extra["camera_side"] = camera_form(max(3, args.steps // 5), 1, cpu=not args.no_cpu_baseline)
         hbm_rate(extra["camera_side"], "camera", extra["camera_side"]["kernel_ms"])
+        fp32_rate(extra["camera_side"], "camera", extra["camera_side"]["kernel_ms"])
     line["forms"] = extra
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(scene, run)
