@@ -296,6 +296,42 @@ def cpu_baseline(scene, run, target_s=12.0):
                       f"({verts} vertices, {dt:.1f} s, fp64, 1 thread)"}
 
 
+def _oracle_worker(task):
+    """One host process of the all-cores oracle figure: renders consecutive
+    chunks of its own path range (from its start again once done) until its
+    time budget is spent; returns vertices, paths and its busy time."""
+    scene, run, begin, count, budget = task
+    import oracle
+    t0 = time.perf_counter()
+    verts = done = 0
+    while time.perf_counter() - t0 < budget:
+        k = done % count
+        n = count - k   # whole ranges: each call also allocates the film
+        o = oracle.render(scene, dict(run, path_begin=begin + k, path_count=n))
+        verts += int(o["tallies"][1])
+        done += n
+    return verts, done, time.perf_counter() - t0
+
+
+def cpu_all_cores(scene, run, budget_s=8.0):
+    """The oracle on every host core the job may use (at most 16): one fresh
+    process per core on disjoint path ranges of the same job, aggregate
+    vertices per second of wall time.  Run before the GPU is touched."""
+    import multiprocessing as mp
+    P = max(1, min(16, os.cpu_count() or 1))
+    span = run["path_count"] // P
+    ctx = mp.get_context("spawn")
+    with ctx.Pool(P) as pool:
+        res = pool.map(_oracle_worker, [(scene, run, i * span, span, budget_s) for i in range(P)])
+    verts = sum(r[0] for r in res)
+    paths = sum(r[1] for r in res)
+    # the processes run concurrently: the aggregate rate is the sum of theirs
+    rate = sum(r[0] / r[2] for r in res)
+    return {"value": rate, "unit": "path vertices/s", "cores": P, "kind": "oracle",
+            "sample": f"{P} concurrent processes, each on its own 1/{P} of the same job's light paths "
+                      f"(repeated until ~{budget_s:.0f} s): {paths} paths, {verts} vertices, fp64"}
+
+
 COPY_BYTES = 256 << 20
 TRAFFIC_JSON = os.path.join(ROOT, "profiles", "traffic.json")
 
@@ -430,8 +466,12 @@ def main():
               "sharding of this path is a design note, not a measured configuration.",
               file=sys.stderr)
         sys.exit(2)
-    import torch
     import workloads
+    all_cores = None
+    if not (args.profile or args.only_headline or args.no_cpu_baseline):
+        # host processes start before anything touches the GPU
+        all_cores = cpu_all_cores(*workloads.cornell_config())
+    import torch
     torch.cuda.set_device(int(os.environ.get("LOCAL_RANK", 0)))
     if args.profile:
         profile_run(args.profile, args.steps)
@@ -508,6 +548,7 @@ def main():
     line["forms"] = extra
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(scene, run)
+        line["cpu_baseline_all_cores"] = all_cores
     print(json.dumps(line, default=float), flush=True)
 
 
