@@ -163,6 +163,44 @@ def camera_cpu_sample(scene, run, chunks=256, chunk=8192):
                       f"({verts} vertices, {dt:.1f} s, fp64, 1 thread)"}
 
 
+def oracle_sample(scene, run, target_s=2.0, grad=False):
+    """The oracle (1 thread, fp64) on the first paths of a job, doubled until
+    one render takes about target_s/2 (path ids are independent, so the first
+    ones are a fair sample); with grad, the path-replay gradient too."""
+    import numpy as np
+    import oracle
+    n, dt, verts = 1024, 0.0, 0
+    g = np.ones(oracle.film_shape(scene, run.get("parity_batches", 1))) if grad else None
+    while True:
+        t0 = time.perf_counter()
+        o = oracle.render(scene, dict(run, path_count=n), film=grad, grad_film=g)
+        dt = time.perf_counter() - t0
+        verts = int(o["tallies"][1])
+        if dt >= target_s / 2 or n >= run["path_count"]:
+            break
+        n = min(run["path_count"], 2 * n)
+    return {"value": verts / dt, "unit": "path vertices/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {n} of {run['path_count']} paths of the same job ({verts} vertices, "
+                      f"{dt:.1f} s, fp64, 1 thread{', with the gradient' if grad else ''})"}
+
+
+def batch_oracle_sample(scenes, runs, every=16, paths=2048):
+    """The oracle (1 thread, fp64) on every `every`-th instance of a batch, the
+    first `paths` paths of each."""
+    import oracle
+    verts, dt, k = 0, 0.0, 0
+    for s, r in list(zip(scenes, runs))[::every]:
+        n = min(paths, r["path_count"])
+        t0 = time.perf_counter()
+        o = oracle.render(s, dict(r, path_count=n), film=False)
+        dt += time.perf_counter() - t0
+        verts += int(o["tallies"][1])
+        k += 1
+    return {"value": verts / dt, "unit": "path vertices/s", "cores": 1, "kind": "oracle",
+            "sample": f"{k} of {len(scenes)} instances (every {every}th), the first {paths} paths of each "
+                      f"({verts} vertices, {dt:.1f} s, fp64, 1 thread)"}
+
+
 def alu_frac(form):
     return form["ops"] / (form["kernel_ms"] / 1e3) / 1e12 / ALU_PEAK_TOPS
 
@@ -513,6 +551,8 @@ def main():
         s3, r3 = workloads.large_config()
         big = forward_form(s3, r3, max(2, args.steps // 25), 1, tune_name="large-512-1024spp")
         extra["fwd_large"] = {k: big[k] for k in ("vertices", "ms_per_step", "vertices_per_s")}
+        if not args.no_cpu_baseline:
+            extra["fwd_large"]["cpu_oracle"] = oracle_sample(s3, r3)
         extra["fwd_large"]["alu_frac"] = alu_frac(big)
         hbm_rate(extra["fwd_large"], "large", big["kernel_ms"])
         fp32_rate(extra["fwd_large"], "large", big["kernel_ms"])
@@ -520,6 +560,8 @@ def main():
         r1 = dict(r1, path_count=1 << 22, total_paths=1 << 22)
         sl = forward_form(s1, r1, max(5, args.steps // 5), 2, tune_name="slab-2^22")
         extra["fwd_slab_2^22"] = {k: sl[k] for k in ("vertices", "ms_per_step", "vertices_per_s")}
+        if not args.no_cpu_baseline:
+            extra["fwd_slab_2^22"]["cpu_oracle"] = oracle_sample(s1, r1)
         extra["fwd_slab_2^22"]["alu_frac"] = alu_frac(sl)
         hbm_rate(extra["fwd_slab_2^22"], "slab", sl["kernel_ms"])
         fp32_rate(extra["fwd_slab_2^22"], "slab", sl["kernel_ms"])
@@ -534,11 +576,16 @@ def main():
         try:
             extra["fwd_adjoint"] = adjoint_form(max(3, args.steps // 10), 1)
             fp32_rate(extra["fwd_adjoint"], "adjoint", extra["fwd_adjoint"]["ms_per_step"])
+            if not args.no_cpu_baseline:
+                sa, ra = workloads.adjoint_config()[:2]
+                extra["fwd_adjoint"]["cpu_oracle"] = oracle_sample(sa, ra, grad=True)
         except Exception as e:  # reported, not hidden
             extra["fwd_adjoint"] = {"error": str(e)}
         b = batched_form(max(3, args.steps // 10), 1)
         if b is not None:
             extra["batched"] = b
+            if not args.no_cpu_baseline:
+                b["cpu_oracle"] = batch_oracle_sample(*workloads.batch_config())
             hbm_rate(b, "batched", b["ms_per_step"])
             fp32_rate(b, "batched", b["ms_per_step"])
         extra["excitation_scan"] = sweep_form(max(3, args.steps // 5), 1)
