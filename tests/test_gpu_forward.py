@@ -85,6 +85,32 @@ def test_slab_replay_all_paths():
     print(rep)
 
 
+def test_slab_full_size_sampled():
+    """The benchmark's 2^22-path slab in its launch shape: sampled path ranges
+    replay against the oracle, and the escape film equals the exits."""
+    import torch
+    from paper_1706_03024_amd import autotune
+    fpt = _fpt()
+    scene, run = workloads.slab_config()
+    n = 1 << 22
+    run = dict(run, path_count=n, total_paths=n)
+    sc = fpt.Scene(scene)
+    autotune.autotune("slab-2^22", scene=sc, run=run, measure=False)  # the cached shape, if any
+    t = fpt.new_tallies()
+    film = sc.render(run, tallies=t)
+    rec, _ = sc.records(run)
+    torch.cuda.synchronize()
+    td = fpt.tallies_dict(t)
+    f = film.cpu().numpy().astype(np.float64)[0]
+    sc.close()
+    assert td["paths"] == n
+    assert abs(f.sum() * n - (td["exit_esc_r"] + td["exit_esc_t"])) <= 1e-3 * n
+    for begin in (0, n // 2 - 2048, n - 4096):
+        sub = dict(run, path_begin=begin, path_count=4096)
+        o = oracle.render(scene, sub, records=True)["records"]
+        compare_records(rec[begin:begin + 4096], o, scale=1.0)
+
+
 def test_slab_statistical_parity():
     """Independent seeds: GPU film (2^20 paths) vs oracle film (2^16 paths),
     per-bin multinomial z-scores."""
