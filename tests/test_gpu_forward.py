@@ -85,13 +85,16 @@ def test_slab_replay_all_paths():
     print(rep)
 
 
-def test_slab_full_size_sampled():
-    """The benchmark's 2^22-path slab in its launch shape: sampled path ranges
-    replay against the oracle, and the escape film equals the exits."""
+@pytest.mark.parametrize("ior", [1.0, 1.33])
+def test_slab_full_size_sampled(ior):
+    """The benchmark's 2^22-path slab in its launch shape, index-matched and
+    behind a water boundary: sampled path ranges replay against the oracle,
+    and the escape film equals the exits."""
     import torch
     from paper_1706_03024_amd import autotune
     fpt = _fpt()
     scene, run = workloads.slab_config()
+    scene["media"][0]["ior"] = ior
     n = 1 << 22
     run = dict(run, path_count=n, total_paths=n)
     sc = fpt.Scene(scene)
