@@ -49,7 +49,7 @@
 extern "C" {
 #endif
 
-#define FPT_ABI_VERSION 3u
+#define FPT_ABI_VERSION 4u
 
 typedef enum {
     FPT_OK = 0,
@@ -180,7 +180,8 @@ typedef struct {
 } fpt_scene_desc;
 
 /* One render call: paths [path_begin, path_begin + path_count) of a job of
- * total_paths paths (total_paths <= 2^32).  Every path carries power
+ * total_paths paths (total_paths <= 2^32, path_count < 2^32: path ids are
+ * 32-bit counters of the random stream).  Every path carries power
  * parity_batches / total_paths; with parity_batches = B > 1 the film gains a
  * leading axis of B slices and path p goes to slice p % B, so each slice is an
  * independent estimate of the whole film (for batch-mean standard errors). */
@@ -235,18 +236,34 @@ const char* fpt_status_str(int32_t status);
 const char* fpt_last_error(void);
 
 /* Validate `desc`, build the spectral tables in fp64 (rounded to fp32) and
- * upload them to the current device (synchronous).  *out is library-owned;
- * free with fpt_scene_destroy.  Errors: FPT_E_INVALID / FPT_E_RANGE for bad
- * descriptors (nothing allocated), FPT_E_NOMEM, FPT_E_DEVICE. */
+ * upload them to the current device (synchronous).  The tables are the
+ * transport coefficients of sec. 4.1: per medium and grid point
+ * sigma_t = sigma_s + sigma_a,bg + sum_d sigma_a,d (the extinction of the
+ * free-flight density, eqs. 5-6), the cumulative event thresholds of the
+ * scatter / absorber choice, each dye's emission CDF (the normalised emission
+ * spectrum of eq. 10, one-bin step) and the walls' reflectance.  All device
+ * scratch a render of this scene can need (path queue, escape counters for up
+ * to 64 parity slices, adjoint partial sums, and for pinhole box scenes the
+ * deferred-connection slices: 40 KiB per wave the transport kernel can keep
+ * resident, ~170 MB on a 256-CU device) is reserved here, so renders never
+ * allocate.  *out is library-owned; free with fpt_scene_destroy.  Errors:
+ * FPT_E_INVALID / FPT_E_RANGE for bad descriptors (nothing allocated),
+ * FPT_E_NOMEM, FPT_E_DEVICE. */
 int32_t fpt_scene_create(const fpt_scene_desc* desc, fpt_scene** out);
 void fpt_scene_destroy(fpt_scene* scene);
 
-/* Replace the differentiable parameters and rebuild the tables (synchronous
- * with respect to the device).  Host arrays, each optional (NULL = unchanged):
- * conc_uM[sum over media of n_dyes] in (medium, dye slot) order, qy[n_dyes],
- * sigma_s_mm[n_media]. */
+/* Replace the differentiable parameters (sec. 4.1: dye concentrations and
+ * quantum yields, and each medium's scattering coefficient) and rebuild the
+ * tables.  Host arrays, each optional (NULL = unchanged): conc_uM[sum over
+ * media of n_dyes] in (medium, dye slot) order, qy[n_dyes], sigma_s_mm[n_media];
+ * read during the call only.  The tables are rebuilt on the host and uploaded
+ * asynchronously on `hip_stream`: work already enqueued there sees the old
+ * parameters, work enqueued after the call the new ones (renders on other
+ * streams must be ordered by the caller).  The host blocks only while a
+ * previous upload of this scene is still reading the staging buffer.  On an
+ * invalid value nothing changes (FPT_E_RANGE / FPT_E_INVALID). */
 int32_t fpt_scene_set_params(fpt_scene* scene, const double* conc_uM, const double* qy,
-                             const double* sigma_s_mm);
+                             const double* sigma_s_mm, void* hip_stream);
 
 /* Film layout: ESCAPE [B][2 comp][2 side (R, T)][n_bins];
  * PINHOLE [B][2 comp][height][width][n_bins]; comp 0 = not yet emitted,
@@ -273,8 +290,17 @@ int32_t fpt_scene_set_tune(fpt_scene* scene, const fpt_tune* tune);
 int32_t fpt_scene_set_timing(fpt_scene* scene, int32_t enable);
 int32_t fpt_scene_timing(fpt_scene* scene, int32_t* renders, float* transport_ms, float* deferred_ms);
 
-/* Forward render.  Accumulates (+=) into film_dev (device, fp32, film shape)
+/* Forward render: the analog walk of sec. 4.1 from the light, every path an
+ * unbiased sample of the fluorescent RTE (eqs. 1-2 with the inelastic kernel
+ * of eq. 10): light vertex (line chosen by power, point and direction on the
+ * emitter), free flight t = -ln(1-u)/sigma_t (eqs. 5-6), scatter / absorber
+ * choice, isotropic scatter (eq. 2), dye absorption with a quantum-yield test
+ * and re-emission at a wavelength from the emission spectrum (eq. 10),
+ * Lambertian walls, and into the film either the escape tallies or, at every
+ * realised vertex, a pinhole connection with transmittance and the geometry
+ * term (eqs. 3-6).  Accumulates (+=) into film_dev (device, fp32, film shape)
  * and tallies_dev (device, FPT_N_TALLIES uint64; optional, may be NULL).
+ * Allocates nothing (the scene's reserved scratch; one stream at a time).
  * Escape films are integer counts scaled by parity_batches/total_paths at the
  * end of the call; camera films are fp32 atomic sums.  Asynchronous.
  * FPT_E_UNSUPPORTED, before any launch, if the scene's table image does not
@@ -283,10 +309,15 @@ int32_t fpt_scene_timing(fpt_scene* scene, int32_t* renders, float* transport_ms
 int32_t fpt_render(fpt_scene* scene, const fpt_run* run, float* film_dev, uint64_t* tallies_dev,
                    void* hip_stream);
 
-/* Path-replay adjoint: replays the same paths (same random numbers) and
- * accumulates into grad_dev (device, fp32[fpt_grad_param_count]) the gradient
- * of <grad_film, film> with respect to the parameters, using the
- * likelihood-ratio form d E[v] = E[v d log p(path) + d v].  grad_film_dev
+/* Path-replay adjoint of fpt_render: replays the same paths (same random
+ * numbers) and accumulates into grad_dev (device, fp32[fpt_grad_param_count])
+ * the gradient of <grad_film, film> with respect to the parameters, using the
+ * likelihood-ratio form d E[v] = E[v d log p(path) + d v] over the path
+ * density of eq. 12's estimator (sec. 4.3): p is the product of the sampled
+ * events' probabilities -- sigma_event e^{-sigma_t t} per collision (eqs. 5-6),
+ * e^{-sigma_t l} per pass-through, QY or 1-QY per dye absorption (sec. 4.1) --
+ * and v the splat value, whose transmittance (eq. 5) depends on the parameters
+ * through sigma_t along the camera connection.  grad_film_dev
  * (device, film shape) is read only.  Stores no path state; memory use is
  * independent of path length.  tallies_dev optional.  Asynchronous.
  * FPT_E_UNSUPPORTED if the parameter count exceeds FPT_MAX_GRAD_PARAMS. */
@@ -353,11 +384,26 @@ int32_t fpt_batch_render(fpt_batch* batch, float* films_dev, uint64_t* tallies_d
                          void* hip_stream);
 void fpt_batch_destroy(fpt_batch* batch);
 
-/* Times candidate launch shapes for `scene` and `run` on the current device
- * (synchronous; renders into a scratch film) and writes the fastest to *out.
- * batch may be NULL (then the plain render is tuned, else the batched one). */
-int32_t fpt_autotune(fpt_scene* scene, const fpt_run* run, fpt_batch* batch, fpt_tune* out,
-                     float* best_ms);
+/* Launch-shape autotuner.  Times candidate shapes for `scene` and `run` on
+ * the current device (synchronous; renders into a scratch film it allocates)
+ * and writes the fastest to *out and its mean render time to *best_ms
+ * (optional).  batch may be NULL (then the plain render is tuned, else the
+ * batched one; scene and run are then ignored).  With cache_path (a JSON file
+ * mapping "<workload>@<arch>x<CUs>cu" to the fpt_tune fields and "ms"), the
+ * cached entry for `workload` on this device is returned without measuring if
+ * present, and a measured one is written back (the file is rewritten whole,
+ * through a temporary file).  Flags: FPT_TUNE_FORCE measures even when cached;
+ * FPT_TUNE_CACHED_ONLY never measures and returns the all-zero tune (the
+ * library defaults) with *best_ms = 0 when nothing is cached; with it and a
+ * cache, scene, run and batch may all be NULL (a plain lookup).  Results of a
+ * render never depend on its launch shape.  Errors: FPT_E_INVALID (NULL
+ * arguments, a malformed or unwritable cache), render errors of the
+ * candidates. */
+#define FPT_TUNE_FORCE 1u
+#define FPT_TUNE_CACHED_ONLY 2u
+int32_t fpt_autotune(fpt_scene* scene, const fpt_run* run, fpt_batch* batch,
+                     const char* cache_path, const char* workload, uint32_t flags,
+                     fpt_tune* out, float* best_ms);
 
 #ifdef __cplusplus
 }

@@ -83,7 +83,9 @@ class Run(C.Structure):
                 ("path_begin", C.c_uint64), ("path_count", C.c_uint64),
                 ("total_paths", C.c_uint64), ("max_emissions", C.c_uint32),
                 ("fluorescence_only", C.c_int32), ("excitation_scatter", C.c_int32),
-                ("parity_batches", C.c_uint32), ("splat_rr", C.c_double)]
+                ("parity_batches", C.c_uint32), ("splat_rr", C.c_double),
+                ("perturb_eta", C.c_double), ("perturb_pattern", C.c_uint32),
+                ("pad_", C.c_uint32)]
 
 
 class Record(C.Structure):
@@ -255,6 +257,8 @@ def make_run(r):
     ru.excitation_scatter = 1 if r["excitation_scatter"] else 0
     ru.parity_batches = r["parity_batches"]
     ru.splat_rr = r["splat_rr"]
+    ru.perturb_eta = r.get("perturb_eta", 0.0)
+    ru.perturb_pattern = r.get("perturb_pattern", 0)
     return ru
 
 
@@ -307,6 +311,62 @@ def render(scene, run, film=True, grad_film=None, records=False, record_grad=Fal
         out["records"] = rec
     if rg is not None:
         out["record_grad"] = rg
+    return out
+
+
+INT_FIELDS = ("n_vertices", "n_scatter", "n_emit", "exit_code", "lambda", "comp")
+
+
+def replay_condition(scene, run, max_vertices=0, grad_film=None, camera=False,
+                     eta=2.0 ** -23, patterns=(1, 2), scale=1.0):
+    """Per-path records and their condition numbers, for replay comparisons.
+
+    Renders the path range plainly and again with every position and direction
+    the walk computes scaled coordinate-wise by 1 +- eta (eta = one fp32 ulp at
+    1; signs hashed per path, vertex and coordinate; one run per pattern).  For
+    each record field the condition number is the largest change between a
+    perturbed run and the plain one, divided by eta times the field's size
+    (positions: at least `scale`; directions: at least 1; splat sums and
+    per-path gradients: their own magnitude, gradients as vectors).  A walk
+    whose every vertex state carries a relative error d moves that field by
+    about kappa * d.  Paths whose integer outcome changes under the
+    perturbation are flagged `unstable` (a decision within about eta of its
+    threshold).  Returns a dict: 'records', optionally 'record_grad', and
+    'kappa_pos', 'kappa_dir', 'kappa_splat', optionally 'kappa_grad' (each
+    float64[path_count]), 'unstable' (bool[path_count])."""
+    def once(extra):
+        r = dict(run, **extra)
+        if camera:
+            return render_camera(scene, r, records=True, max_vertices=max_vertices)
+        return render(scene, r, grad_film=grad_film, records=True,
+                      record_grad=grad_film is not None, max_vertices=max_vertices)
+
+    base = once({})
+    rec = base["records"]
+    n = len(rec)
+    out = {"records": rec, "unstable": np.zeros(n, bool),
+           "kappa_pos": np.zeros(n), "kappa_dir": np.zeros(n), "kappa_splat": np.zeros(n)}
+    g0 = base.get("record_grad")
+    if g0 is not None:
+        out["record_grad"] = g0
+        out["kappa_grad"] = np.zeros(n)
+    for pat in patterns:
+        o = once({"perturb_eta": eta, "perturb_pattern": pat})
+        pr = o["records"]
+        for f in INT_FIELDS:
+            out["unstable"] |= pr[f].astype(np.int64) != rec[f].astype(np.int64)
+        for f, floor in (("pos", scale), ("dir", 1.0)):
+            k = (np.abs(pr[f] - rec[f]) / (eta * np.maximum(np.abs(rec[f]), floor))).max(1)
+            out["kappa_" + f] = np.maximum(out["kappa_" + f], k)
+        d = np.abs(pr["splat_sum"] - rec["splat_sum"])
+        a = np.abs(rec["splat_sum"])
+        k = np.where(d == 0, 0.0, d / (eta * np.maximum(a, 1e-300)))
+        out["kappa_splat"] = np.maximum(out["kappa_splat"], k)
+        if g0 is not None:
+            d = np.linalg.norm(o["record_grad"] - g0, axis=1)
+            a = np.linalg.norm(g0, axis=1)
+            k = np.where(d == 0, 0.0, d / (eta * np.maximum(a, 1e-300)))
+            out["kappa_grad"] = np.maximum(out["kappa_grad"], k)
     return out
 
 

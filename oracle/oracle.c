@@ -485,10 +485,34 @@ typedef struct {
     int lam, region, medium, comp;
     uint32_t n_scatter, n_emit, v;
     uint32_t batch;
+    uint32_t pid;
     double S[ORC_MAX_PARAMS]; /* running score: d/dtheta log p(path prefix) */
     double splat_sum;
     double margin;
 } path_t;
+
+/* Conditioning probe (orc_run.perturb_eta): scale each entry of a freshly
+ * computed vector -- a position (slot 0), a direction (slot 1), the running
+ * score (slot 2), the path's gradient sum (slot 3) or a point drawn on the
+ * light for a connection (slot 4) -- by 1 +- eta, the sign
+ * from a 64-bit mix (splitmix64 finaliser) of path, vertex, slot, entry and
+ * pattern.  No effect when eta is 0. */
+static void perturb_vec(const ctx_t* c, const path_t* p, int slot, double* a, int n) {
+    double eta = c->run->perturb_eta;
+    if (!(eta > 0.0)) return;
+    for (int i = 0; i < n; ++i) {
+        uint64_t z = ((uint64_t)p->pid << 32) ^ ((uint64_t)p->v << 10) ^ (uint64_t)(slot * 32 + i) ^
+                     ((uint64_t)c->run->perturb_pattern << 56);
+        z += 0x9E3779B97F4A7C15ull;
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        z ^= z >> 31;
+        a[i] *= (z & 1u) ? 1.0 + eta : 1.0 - eta;
+    }
+}
+static void perturb3(const ctx_t* c, const path_t* p, int slot, double* a) {
+    perturb_vec(c, p, slot, a, 3);
+}
 
 static void deposit(ctx_t* c, path_t* p, int64_t idx, double v, const double* dv) {
     c->film[idx] += v;
@@ -500,6 +524,7 @@ static void deposit(ctx_t* c, path_t* p, int64_t idx, double v, const double* dv
             c->grad[i] += gi;
             if (c->pgrad) c->pgrad[i] += gi;
         }
+        if (c->pgrad) perturb_vec(c, p, 3, c->pgrad, c->n_params);
     }
 }
 
@@ -711,6 +736,7 @@ static void run_path(ctx_t* c, uint32_t pid, orc_record* rec, uint32_t max_verti
     rng.pid = pid;
     path_t p;
     memset(&p, 0, sizeof p);
+    p.pid = pid;
     p.batch = pid % (run->parity_batches ? run->parity_batches : 1);
     p.margin = INFINITY;
     double L = scene_scale(sc);
@@ -748,18 +774,22 @@ static void run_path(ctx_t* c, uint32_t pid, orc_record* rec, uint32_t max_verti
                 double eta = 1.0 / n_b;
                 for (int i = 0; i < 3; ++i) p.w[i] = eta * p.w[i] + (eta * ci - ct) * nrm[i];
                 normalize3(p.w);
+                perturb3(c, &p, 1, p.w);
             }
         }
     } else if (sc->light == ORC_LIGHT_POINT) {
         draw(&rng, 0, 1, r1);
         memcpy(p.x, sc->lpos, sizeof p.x);
         iso_dir(unif(r1[0]), unif(r1[1]), p.w);
+        perturb3(c, &p, 1, p.w);
         p.region = 0;
     } else {
         double a = unif(r[1]), b = unif(r[2]);
         for (int i = 0; i < 3; ++i) p.x[i] = sc->lpos[i] + a * sc->lu[i] + b * sc->lv[i];
+        perturb3(c, &p, 0, p.x);
         draw(&rng, 0, 1, r1);
         cos_dir(c->qn, c->qt1, unif(r1[0]), unif(r1[1]), p.w);
+        perturb3(c, &p, 1, p.w);
         p.region = -1;
     }
     p.medium = region_medium(sc, p.region);
@@ -793,7 +823,9 @@ static void run_path(ctx_t* c, uint32_t pid, orc_record* rec, uint32_t max_verti
         if (tf < h.d) {
             /* collision inside the medium */
             for (int i = 0; i < 3; ++i) p.x[i] += tf * p.w[i];
+            perturb3(c, &p, 0, p.x);
             score_path_length(c, &p, tf);
+            if (c->gfilm) perturb_vec(c, &p, 2, p.S, c->n_params);
             const orc_medium* md = &sc->media[p.medium];
             double s = u1 * st;
             double thr = md->sigma_s;
@@ -806,6 +838,7 @@ static void run_path(ctx_t* c, uint32_t pid, orc_record* rec, uint32_t max_verti
                 if (!run->excitation_scatter && p.n_emit == 0) { exit_code = ORC_EXIT_EXCSCAT; break; }
                 if (p.n_scatter > run->max_scatter) { exit_code = ORC_EXIT_SCAP; break; }
                 iso_dir(u2, u3, p.w);
+                perturb3(c, &p, 1, p.w);
                 splat(c, &p, NULL, 0, rr_bits_of(r));
                 continue;
             }
@@ -843,6 +876,7 @@ static void run_path(ctx_t* c, uint32_t pid, orc_record* rec, uint32_t max_verti
             if (k > 0) upd_margin(&p.margin, fabs(ul - cdf[k - 1]));
             p.lam = k;
             iso_dir(u2, u3, p.w);
+            perturb3(c, &p, 1, p.w);
             p.n_emit++;
             p.comp = 1;
             T[ORC_T_EMISSIONS]++;
@@ -853,7 +887,9 @@ static void run_path(ctx_t* c, uint32_t pid, orc_record* rec, uint32_t max_verti
         double dd = h.d;
         if (isfinite(dd)) {
             for (int i = 0; i < 3; ++i) p.x[i] += dd * p.w[i];
+            perturb3(c, &p, 0, p.x);
             score_path_length(c, &p, dd);
+            if (c->gfilm) perturb_vec(c, &p, 2, p.S, c->n_params);
             /* a point on a planar boundary lies exactly on its plane */
             if (sc->geom == ORC_GEOM_SLAB) p.x[2] = p.w[2] < 0.0 ? sc->z0 : sc->z1;
             else if (sc->geom == ORC_GEOM_HALFSPACE) p.x[2] = sc->z0;
@@ -871,6 +907,7 @@ static void run_path(ctx_t* c, uint32_t pid, orc_record* rec, uint32_t max_verti
             upd_margin(&p.margin, fabs(u1 - R));
             if (u1 < R) {
                 mirror(p.w, nrm);
+                perturb3(c, &p, 1, p.w);
                 T[ORC_T_WALL_REFLECT]++;
                 continue;
             }
@@ -894,6 +931,7 @@ static void run_path(ctx_t* c, uint32_t pid, orc_record* rec, uint32_t max_verti
             double n[3], t1[3];
             face_frame(h.index, n, t1);
             cos_dir(n, t1, u2, u3, p.w);
+            perturb3(c, &p, 1, p.w);
             splat(c, &p, n, 0, rr_bits_of(r));
             continue;
         }
@@ -925,7 +963,8 @@ int32_t orc_render(const orc_scene* sc, const orc_run* run, double* film, uint64
     if (!sc || !run) return fail("null argument");
     if (run->total_paths == 0 || run->path_begin + run->path_count > run->total_paths)
         return fail("path range outside total_paths");
-    if (run->total_paths > 0xFFFFFFFFull) return fail("total_paths exceeds 2^32");
+    if (run->total_paths > (1ull << 32)) return fail("total_paths exceeds 2^32");
+    if (run->path_count > 0xFFFFFFFFull) return fail("path_count must be below 2^32");
     if (gfilm && !grad) return fail("gfilm needs grad");
     if (rec_grad && !gfilm) return fail("rec_grad needs gfilm");
     tables_t t;
@@ -1031,10 +1070,9 @@ static double cam_source(ctx_t* c, path_t* p, int k, double ua, double ub) {
     int N = t->N, m = p->medium;
     const orc_medium* md = &sc->media[m];
     double xn[3], d[3];
-    for (int i = 0; i < 3; ++i) {
-        xn[i] = sc->lpos[i] + ua * sc->lu[i] + ub * sc->lv[i];
-        d[i] = xn[i] - p->x[i];
-    }
+    for (int i = 0; i < 3; ++i) xn[i] = sc->lpos[i] + ua * sc->lu[i] + ub * sc->lv[i];
+    perturb3(c, p, 4, xn);
+    for (int i = 0; i < 3; ++i) d[i] = xn[i] - p->x[i];
     double r2 = dot3(d, d), r = sqrt(r2);
     double cos_n = -dot3(c->qn, d) / r; /* the light emits along +qn */
     upd_margin(&p->margin, fabs(cos_n));
@@ -1075,6 +1113,7 @@ static void run_camera_path(ctx_t* c, uint32_t pid, uint32_t spp, orc_record* re
     rng.pid = pid;
     path_t p;
     memset(&p, 0, sizeof p);
+    p.pid = pid;
     p.margin = INFINITY;
     int k = (int)(pid % (uint32_t)N);
     uint32_t pix = (pid / (uint32_t)N) % (uint32_t)(W * H);
@@ -1098,6 +1137,7 @@ static void run_camera_path(ctx_t* c, uint32_t pid, uint32_t spp, orc_record* re
     double yi = 1.0 - 2.0 * (py + unif(r[1])) / H;
     for (int i = 0; i < 3; ++i) p.w[i] = c->cf[i] + xi * c->tanx * c->cr[i] + yi * c->tany * c->cu[i];
     normalize3(p.w);
+    perturb3(c, &p, 1, p.w);
     T[ORC_T_PATHS]++;
     T[ORC_T_VERTICES]++;
     {
@@ -1131,6 +1171,7 @@ static void run_camera_path(ctx_t* c, uint32_t pid, uint32_t spp, orc_record* re
             exit_code = ORC_EXIT_ESC_T;
         } else {
             for (int i = 0; i < 3; ++i) p.x[i] = sc->eye[i] + t_in * p.w[i];
+            perturb3(c, &p, 0, p.x);
             p.x[oa] = plane;
         }
     }
@@ -1150,6 +1191,7 @@ static void run_camera_path(ctx_t* c, uint32_t pid, uint32_t spp, orc_record* re
             upd_margin(&p.margin, fabs(tf - h.d) / fmax(fmax(tf, h.d), L));
         if (tf < h.d) {
             for (int i = 0; i < 3; ++i) p.x[i] += tf * p.w[i];
+            perturb3(c, &p, 0, p.x);
             const orc_medium* md = &sc->media[p.medium];
             if (md->n_dyes > 0) {
                 /* a candidate emission vertex: connect to the light */
@@ -1165,6 +1207,7 @@ static void run_camera_path(ctx_t* c, uint32_t pid, uint32_t spp, orc_record* re
                 p.n_scatter++;
                 if (p.n_scatter > run->max_scatter) { exit_code = ORC_EXIT_SCAP; break; }
                 iso_dir(u2, u3, p.w);
+                perturb3(c, &p, 1, p.w);
                 continue;
             }
             thr += md->sigma_a_bg;
@@ -1178,6 +1221,7 @@ static void run_camera_path(ctx_t* c, uint32_t pid, uint32_t spp, orc_record* re
         double dd = h.d;
         if (isfinite(dd)) {
             for (int i = 0; i < 3; ++i) p.x[i] += dd * p.w[i];
+            perturb3(c, &p, 0, p.x);
             if ((h.kind == SURF_WALL || h.kind == SURF_ESCAPE) && h.index >= 0)
                 p.x[h.index / 2] = (h.index % 2) ? sc->box_hi[h.index / 2] : sc->box_lo[h.index / 2];
         }
@@ -1190,6 +1234,7 @@ static void run_camera_path(ctx_t* c, uint32_t pid, uint32_t spp, orc_record* re
             double n[3], t1[3];
             face_frame(h.index, n, t1);
             cos_dir(n, t1, u2, u3, p.w);
+            perturb3(c, &p, 1, p.w);
             T[ORC_T_WALL_REFLECT]++;
             continue;
         }
@@ -1226,7 +1271,8 @@ int32_t orc_render_camera(const orc_scene* sc, const orc_run* run, double* film,
         return fail("total_paths must be spp * width * height * n_bins");
     if (run->path_begin + run->path_count > run->total_paths)
         return fail("path range outside total_paths");
-    if (run->total_paths > 0xFFFFFFFFull) return fail("total_paths exceeds 2^32");
+    if (run->total_paths > (1ull << 32)) return fail("total_paths exceeds 2^32");
+    if (run->path_count > 0xFFFFFFFFull) return fail("path_count must be below 2^32");
     uint32_t spp = (uint32_t)(run->total_paths / per_sample);
     tables_t t;
     if (build_tables(sc, &t)) return -1;

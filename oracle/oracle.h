@@ -126,6 +126,17 @@ typedef struct {
                                    before emitting (direct excitation only) */
     uint32_t parity_batches;    /* B >= 1: film slice = path_id % B */
     double splat_rr;            /* transmittance roulette threshold, 0 = off */
+    /* Conditioning probe for replay comparisons (0 = off, the plain walk).  With
+     * perturb_eta > 0 every position and direction the walk computes is scaled,
+     * coordinate by coordinate, by (1 +- perturb_eta) with a sign hashed from
+     * (path, vertex, coordinate, perturb_pattern) right after it is computed
+     * (a coordinate set exactly on a planar boundary stays exact).  Comparing
+     * such a run with the plain one measures how much a relative error of that
+     * size at every vertex moves each record field: the path's condition
+     * number, which bounds what any fp32 walk of the same path can reproduce. */
+    double perturb_eta;
+    uint32_t perturb_pattern;
+    uint32_t pad_;
 } orc_run;
 
 typedef struct {

@@ -112,6 +112,8 @@ class PathRecord(C.Structure):
 
 
 RECORD_WORDS = C.sizeof(PathRecord) // 4
+ABI_VERSION = 4
+TUNE_FORCE, TUNE_CACHED_ONLY = 1, 2
 
 _lib = None
 
@@ -131,7 +133,7 @@ def lib():
         "fpt_last_error": (C.c_char_p, []),
         "fpt_scene_create": (C.c_int32, [C.POINTER(SceneDesc), C.POINTER(vp)]),
         "fpt_scene_destroy": (None, [vp]),
-        "fpt_scene_set_params": (C.c_int32, [vp, vp, vp, vp]),
+        "fpt_scene_set_params": (C.c_int32, [vp, vp, vp, vp, vp]),
         "fpt_film_shape": (C.c_int32, [vp, C.c_uint32, C.POINTER(C.c_int64), C.POINTER(C.c_int32)]),
         "fpt_grad_param_count": (C.c_int32, [vp]),
         "fpt_scene_set_tune": (C.c_int32, [vp, C.POINTER(Tune)]),
@@ -146,14 +148,14 @@ def lib():
                                          C.POINTER(Tune), C.POINTER(vp)]),
         "fpt_batch_render": (C.c_int32, [vp, vp, vp, vp]),
         "fpt_batch_destroy": (None, [vp]),
-        "fpt_autotune": (C.c_int32, [vp, C.POINTER(Run), vp, C.POINTER(Tune),
-                                     C.POINTER(C.c_float)]),
+        "fpt_autotune": (C.c_int32, [vp, C.POINTER(Run), vp, C.c_char_p, C.c_char_p, C.c_uint32,
+                                     C.POINTER(Tune), C.POINTER(C.c_float)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
         f.restype = res
         f.argtypes = args
-    if L.fpt_abi_version() != 3:
+    if L.fpt_abi_version() != ABI_VERSION:
         raise FptError(E_INVALID, "libfpt ABI version mismatch")
     _lib = L
     return L

@@ -31,14 +31,20 @@ def params_of(desc):
 
 
 class FluorRender(torch.autograd.Function):
-    """film = render(scene; theta).  Gradients flow to theta only."""
+    """film = render(scene; theta).  Gradients flow to theta only.
+
+    The path-replay gradient is valid only with the parameters the forward
+    pass rendered with, so backward() sets the scene to this forward's theta
+    for the replay and restores whatever the scene held before (another
+    forward may have run on the same scene in between)."""
 
     @staticmethod
     def forward(ctx, theta, scene: Scene, run: dict, adjoint_run: dict | None = None):
-        conc, qy, ss = split_params(scene.desc, theta.detach().cpu().numpy())
-        scene.set_params(conc, qy, ss)
+        th = theta.detach().cpu().numpy().astype(np.float64)
+        scene.set_params(*split_params(scene.desc, th))
         film = scene.render(run)
         ctx.scene = scene
+        ctx.theta = th
         ctx.run = adjoint_run if adjoint_run is not None else run
         ctx.theta_dtype = theta.dtype
         ctx.theta_device = theta.device
@@ -46,7 +52,14 @@ class FluorRender(torch.autograd.Function):
 
     @staticmethod
     def backward(ctx, grad_film):
-        g = ctx.scene.render_adjoint(ctx.run, grad_film.contiguous().float())
+        sc = ctx.scene
+        held = sc.theta.copy()
+        swap = not np.array_equal(held, ctx.theta)
+        if swap:
+            sc.set_params(*split_params(sc.desc, ctx.theta))
+        g = sc.render_adjoint(ctx.run, grad_film.contiguous().float())
+        if swap:
+            sc.set_params(*split_params(sc.desc, held))
         return g.to(ctx.theta_device, ctx.theta_dtype), None, None, None
 
 

@@ -2,13 +2,13 @@
 
 fpt_autotune times candidate shapes (block size, refill threshold, wave-block
 trigger, and for batches the work-item size) on the device and returns the
-fastest; results never depend on the shape.  The cache is keyed by the
-workload's name and the device's architecture and compute-unit count.
+fastest; results never depend on the shape.  The library owns the JSON cache
+(keyed by the workload's name and the device's architecture and compute-unit
+count); this module only passes its path and applies the result.
 """
 from __future__ import annotations
 
 import ctypes as C
-import json
 import os
 
 import torch
@@ -28,45 +28,31 @@ def device_tag():
     return f"{p.gcnArchName.split(':')[0]}x{p.multi_processor_count}cu"
 
 
-def _key(name):
-    return f"{name}@{device_tag()}"
-
-
-def _load(path):
-    try:
-        with open(path) as f:
-            return json.load(f)
-    except (OSError, ValueError):
-        return {}
-
-
 def autotune(name, scene=None, run=None, batch=None, cache_path=DEFAULT_CACHE, force=False,
              measure=True):
-    """Returns the tune dict for `name`, measuring it if the cache lacks it
-    (unless measure=False: then the library defaults, returned as None), and
-    applies it to `scene` (plain render) or returns it for a new Batch."""
-    cache = _load(cache_path)
-    key = _key(name)
-    if key in cache and not force:
-        best = cache[key]
-    elif not measure:
+    """fpt_autotune for workload `name`: the cached shape for this device, or
+    a measured one (written to the cache) unless measure=False, in which case
+    an uncached workload returns None (library defaults).  Applies the shape
+    to `scene` (plain render) or returns it for a new Batch."""
+    out = _abi.Tune()
+    ms = C.c_float()
+    flags = (_abi.TUNE_FORCE if force else 0) | (0 if measure else _abi.TUNE_CACHED_ONLY)
+    path = cache_path.encode() if cache_path else None
+    if batch is not None:
+        check(lib().fpt_autotune(None, None, batch.handle, path, name.encode(), flags,
+                                 C.byref(out), C.byref(ms)))
+    elif scene is not None:
+        r = _abi.run_struct(run)
+        check(lib().fpt_autotune(scene.handle, C.byref(r), None, path, name.encode(), flags,
+                                 C.byref(out), C.byref(ms)))
+    else:   # a lookup only
+        check(lib().fpt_autotune(None, None, None, path, name.encode(),
+                                 flags | _abi.TUNE_CACHED_ONLY, C.byref(out), C.byref(ms)))
+        measure = False
+    best = {f: int(getattr(out, f)) for f in FIELDS}
+    best["ms"] = float(ms.value)
+    if not measure and best["ms"] == 0.0 and not any(best[f] for f in FIELDS):
         return None
-    else:
-        out = _abi.Tune()
-        ms = C.c_float()
-        if batch is not None:
-            check(lib().fpt_autotune(None, None, batch.handle, C.byref(out), C.byref(ms)))
-        else:
-            r = _abi.run_struct(run)
-            check(lib().fpt_autotune(scene.handle, C.byref(r), None, C.byref(out), C.byref(ms)))
-        best = {f: int(getattr(out, f)) for f in FIELDS}
-        best["ms"] = float(ms.value)
-        cache[key] = best
-        try:
-            with open(cache_path, "w") as f:
-                json.dump(cache, f, indent=1, sort_keys=True)
-        except OSError:
-            pass
     if scene is not None:
         scene.set_tune(**{f: best.get(f, 0) for f in FIELDS})
     return best

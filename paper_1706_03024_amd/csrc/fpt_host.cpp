@@ -11,6 +11,7 @@
 #include <new>
 #include <string>
 #include <deque>
+#include <map>
 #include <vector>
 
 #include "fpt.h"
@@ -138,15 +139,18 @@ struct fpt_scene {
     std::vector<uint32_t> image;
     KParams base;
     uint32_t* d_tables = nullptr;
-    uint32_t* d_counts = nullptr;
-    size_t counts_cap = 0;
-    unsigned long long* d_counter = nullptr;
-    unsigned long long* d_tally = nullptr;  // scratch tallies when the caller passes none
-    float* d_partials = nullptr;
-    size_t partials_cap = 0;
-    uint32_t* d_sjobs = nullptr;  // deferred pinhole connections, kSjobSlice entries per wave
-    size_t sjob_waves = 0;        // waves d_sjobs has slices for
+    // device scratch, reserved once at creation for the largest launch any
+    // launch shape gives on this device (renders never allocate)
+    uint32_t* d_counts = nullptr;  // escape counts, up to 64 parity slices
+    size_t counts_words = 0;
+    unsigned long long* d_counter = nullptr;  // path queue heads
+    float* d_partials = nullptr;   // adjoint per-block partial gradients
+    size_t partials_blocks = 0;
+    uint32_t* d_sjobs = nullptr;   // deferred pinhole connections, kSjobSlice entries per wave
+    size_t sjob_waves = 0;         // waves d_sjobs has slices for
     uint32_t* d_sjob_counts = nullptr;
+    uint32_t* h_stage = nullptr;   // pinned staging of the table image (fpt_scene_set_params)
+    hipEvent_t staged = nullptr;   // the last upload from h_stage has completed
     bool timing = false;             // record events around launches (fpt_scene_set_timing)
     std::vector<hipEvent_t> events;  // 3 per timed render: transport start, end, deferred end
     int timed = 0;
@@ -564,6 +568,8 @@ int32_t check_run(const fpt_scene* sc, const fpt_run* run, uint32_t* B) {
         return set_err(FPT_E_RANGE, "total_paths must be in [1, 2^32]");
     if (run->path_begin > run->total_paths || run->path_count > run->total_paths - run->path_begin)
         return set_err(FPT_E_RANGE, "path range outside total_paths");
+    // path ids are 32-bit: a job of 2^32 paths is rendered in at least two calls
+    if (run->path_count > 0xFFFFFFFFull) return set_err(FPT_E_RANGE, "path_count must be below 2^32");
     const uint32_t b = run->parity_batches ? run->parity_batches : 1u;
     if (b > 64) return set_err(FPT_E_RANGE, "parity_batches %u > 64", b);
     if (!(run->splat_rr >= 0.0 && run->splat_rr <= 1.0)) return set_err(FPT_E_RANGE, "splat_rr outside [0,1]");
@@ -579,7 +585,7 @@ void fill_run(const fpt_scene* sc, const fpt_run* run, uint32_t B, KParams* P) {
     P->key0 = (uint32_t)run->seed;
     P->key1 = (uint32_t)(run->seed >> 32) ^ run->instance;
     P->path_begin = (uint32_t)run->path_begin;
-    P->path_count = (uint32_t)std::min<uint64_t>(run->path_count, 0xFFFFFFFFull);
+    P->path_count = (uint32_t)run->path_count;  // below 2^32 (check_run)
     P->batches = B;
     // film element indices below 2^32 - 1: deposits merge per wave
     P->film_u32 = sc->desc.sensor == FPT_SENSOR_PINHOLE &&
@@ -605,28 +611,59 @@ void fill_run(const fpt_scene* sc, const fpt_run* run, uint32_t B, KParams* P) {
     P->wide_rounds = sc->tune.wide_rounds < 0 ? 0 : (sc->tune.wide_rounds > 0 ? sc->tune.wide_rounds : (pin ? 1 : 2));
 }
 
-int32_t ensure_scratch(fpt_scene* sc, size_t counts, size_t partials) {
-    if (!sc->d_counter) HIP_TRY(hipMalloc(&sc->d_counter, queue_words() * 8), "hipMalloc(path queue)");
-    if (!sc->d_tally) HIP_TRY(hipMalloc(&sc->d_tally, FPT_N_TALLIES * 8), "hipMalloc(tally)");
-    if (counts > sc->counts_cap) {
-        if (sc->d_counts) (void)hipFree(sc->d_counts);
-        sc->d_counts = nullptr;
-        sc->counts_cap = 0;
-        HIP_TRY(hipMalloc(&sc->d_counts, counts * 4), "hipMalloc(counts)");
-        sc->counts_cap = counts;
-    }
-    if (partials > sc->partials_cap) {
-        if (sc->d_partials) (void)hipFree(sc->d_partials);
-        sc->d_partials = nullptr;
-        sc->partials_cap = 0;
-        HIP_TRY(hipMalloc(&sc->d_partials, partials * 4), "hipMalloc(partials)");
-        sc->partials_cap = partials;
+// Deferred-connection entries per transport wave (20 bytes each).
+constexpr uint32_t kSjobSlice = 2048;
+
+// Largest persistent grid (blocks) and wave count of a transport launch in
+// `mode` over every block size a tune may ask for, at the kernel's occupancy on
+// this device; 0 where the scene's tables do not fit in LDS for that mode.
+int32_t max_launch(const fpt_scene* sc, const KParams& P0, int mode, size_t* blocks, size_t* waves) {
+    KParams P = P0;
+    P.hist_words = 0;  // the LDS histogram only lowers occupancy
+    *blocks = *waves = 0;
+    for (int b = 64; b <= 256; b += 64) {
+        if (transport_lds_bytes(P, b, mode) > 160u * 1024u) continue;
+        int per_cu = 0;
+        HIP_TRY(transport_occupancy(P, mode, b, &per_cu), "occupancy query");
+        const size_t g = (size_t)sc->n_cu * (size_t)std::max(per_cu, 1);
+        *blocks = std::max(*blocks, g);
+        *waves = std::max(*waves, g * (size_t)(b / 64));
     }
     return FPT_OK;
 }
 
-// Deferred-connection entries per transport wave (20 bytes each).
-constexpr uint32_t kSjobSlice = 2048;
+// Device scratch of a scene, sized once for every launch it can make.
+int32_t reserve_scratch(fpt_scene* sc) {
+    HIP_TRY(hipMalloc(&sc->d_counter, queue_words() * 8), "hipMalloc(path queue)");
+    if (sc->desc.sensor == FPT_SENSOR_ESCAPE) {
+        sc->counts_words = (size_t)film_elems(sc->desc, 64);
+        HIP_TRY(hipMalloc(&sc->d_counts, sc->counts_words * 4), "hipMalloc(counts)");
+    }
+    fpt_run r;
+    std::memset(&r, 0, sizeof r);
+    r.path_count = r.total_paths = 1;
+    KParams P;
+    fill_run(sc, &r, 1, &P);
+    size_t blocks = 0, waves = 0;
+    int32_t rc = max_launch(sc, P, MODE_ADJ, &blocks, &waves);
+    if (rc != FPT_OK) return rc;
+    if (blocks) {
+        HIP_TRY(hipMalloc(&sc->d_partials, blocks * kMaxNP * 4), "hipMalloc(partials)");
+        sc->partials_blocks = blocks;
+    }
+    if (sc->desc.geometry == FPT_GEOM_BOX && sc->desc.sensor == FPT_SENSOR_PINHOLE) {
+        if ((rc = max_launch(sc, P, MODE_FWD, &blocks, &waves)) != FPT_OK) return rc;
+        if (waves) {
+            HIP_TRY(hipMalloc(&sc->d_sjobs, waves * 5 * kSjobSlice * 4), "hipMalloc(deferred splats)");
+            HIP_TRY(hipMalloc(&sc->d_sjob_counts, waves * 4), "hipMalloc(deferred splat counts)");
+            sc->sjob_waves = waves;
+        }
+    }
+    HIP_TRY(hipHostMalloc((void**)&sc->h_stage, std::max<size_t>(4, sc->image.size() * 4), hipHostMallocDefault),
+            "hipHostMalloc(table staging)");
+    HIP_TRY(hipEventCreateWithFlags(&sc->staged, hipEventDisableTiming), "hipEventCreate");
+    return FPT_OK;
+}
 
 // Grid for a persistent launch: fill every CU at the kernel's occupancy, but
 // never more lanes than paths.
@@ -836,7 +873,7 @@ int32_t fpt_scene_create(const fpt_scene_desc* desc, fpt_scene** out) {
         delete sc;
         return hip_err(e, "device query");
     }
-    if ((rc = upload_tables(sc)) != FPT_OK || (rc = ensure_scratch(sc, 0, 0)) != FPT_OK) {
+    if ((rc = upload_tables(sc)) != FPT_OK || (rc = reserve_scratch(sc)) != FPT_OK) {
         fpt_scene_destroy(sc);
         return rc;
     }
@@ -849,15 +886,20 @@ void fpt_scene_destroy(fpt_scene* sc) {
     if (sc->d_tables) (void)hipFree(sc->d_tables);
     if (sc->d_counts) (void)hipFree(sc->d_counts);
     if (sc->d_counter) (void)hipFree(sc->d_counter);
-    if (sc->d_tally) (void)hipFree(sc->d_tally);
     if (sc->d_partials) (void)hipFree(sc->d_partials);
+    if (sc->staged) {
+        (void)hipEventSynchronize(sc->staged);
+        (void)hipEventDestroy(sc->staged);
+    }
+    if (sc->h_stage) (void)hipHostFree(sc->h_stage);
     if (sc->d_sjobs) (void)hipFree(sc->d_sjobs);
     if (sc->d_sjob_counts) (void)hipFree(sc->d_sjob_counts);
     for (hipEvent_t e : sc->events) (void)hipEventDestroy(e);
     delete sc;
 }
 
-int32_t fpt_scene_set_params(fpt_scene* sc, const double* conc, const double* qy, const double* sigma_s) {
+int32_t fpt_scene_set_params(fpt_scene* sc, const double* conc, const double* qy, const double* sigma_s,
+                             void* stream) {
     if (!sc) return set_err(FPT_E_INVALID, "NULL scene");
     fpt_scene_desc d = sc->desc;
     int k = 0;
@@ -877,8 +919,16 @@ int32_t fpt_scene_set_params(fpt_scene* sc, const double* conc, const double* qy
         build_tables(sc);
         return rc;
     }
-    HIP_TRY(hipDeviceSynchronize(), "synchronise before table upload");
-    return upload_tables(sc);
+    // stream-ordered upload through the pinned staging buffer: launches already
+    // on `stream` read the old tables, later ones the new; the host waits only
+    // for the previous upload out of the staging buffer
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(hipEventSynchronize(sc->staged), "wait for the previous table upload");
+    std::memcpy(sc->h_stage, sc->image.data(), sc->image.size() * 4);
+    HIP_TRY(hipMemcpyAsync(sc->d_tables, sc->h_stage, sc->image.size() * 4, hipMemcpyHostToDevice, s),
+            "upload tables");
+    HIP_TRY(hipEventRecord(sc->staged, s), "hipEventRecord");
+    return FPT_OK;
 }
 
 int32_t fpt_film_shape(const fpt_scene* sc, uint32_t batches, int64_t dims[5], int32_t* ndims) {
@@ -964,7 +1014,7 @@ int32_t fpt_render(fpt_scene* sc, const fpt_run* run, float* film, uint64_t* tal
     const size_t n_counts = escape ? (size_t)film_elems(sc->desc, B) : 0;
     int block;
     if ((rc = transport_block(sc, P, MODE_FWD, &block)) != FPT_OK) return rc;
-    if ((rc = ensure_scratch(sc, n_counts, 0)) != FPT_OK) return rc;
+    if (n_counts > sc->counts_words) return set_err(FPT_E_RANGE, "escape film of %zu counters", n_counts);
     int grid;
     if ((rc = grid_for(sc, P, MODE_FWD, block, run->path_count, &grid)) != FPT_OK) return rc;
     KBuffers Bf;
@@ -977,16 +1027,9 @@ int32_t fpt_render(fpt_scene* sc, const fpt_run* run, float* film, uint64_t* tal
     const bool defer = sc->desc.sensor == FPT_SENSOR_PINHOLE;
     const size_t waves = (size_t)grid * (block / 64);
     if (defer) {
-        if (waves > sc->sjob_waves) {
-            if (sc->d_sjobs) (void)hipFree(sc->d_sjobs);
-            if (sc->d_sjob_counts) (void)hipFree(sc->d_sjob_counts);
-            sc->d_sjobs = nullptr;
-            sc->d_sjob_counts = nullptr;
-            sc->sjob_waves = 0;
-            HIP_TRY(hipMalloc(&sc->d_sjobs, waves * 5 * kSjobSlice * 4), "hipMalloc(deferred splats)");
-            HIP_TRY(hipMalloc(&sc->d_sjob_counts, waves * 4), "hipMalloc(deferred splat counts)");
-            sc->sjob_waves = waves;
-        }
+        // slices were reserved for the largest wave count at scene creation
+        if (waves > sc->sjob_waves)
+            return set_err(FPT_E_DEVICE, "%zu transport waves exceed the %zu reserved", waves, sc->sjob_waves);
         Bf.sjobs = sc->d_sjobs;
         Bf.sjob_counts = sc->d_sjob_counts;
         Bf.sjob_slice = kSjobSlice;
@@ -1026,7 +1069,8 @@ int32_t fpt_render_adjoint(fpt_scene* sc, const fpt_run* run, const float* gfilm
     if ((rc = transport_block(sc, P, MODE_ADJ, &block)) != FPT_OK) return rc;
     int grid;
     if ((rc = grid_for(sc, P, MODE_ADJ, block, run->path_count, &grid)) != FPT_OK) return rc;
-    if ((rc = ensure_scratch(sc, 0, (size_t)grid * kMaxNP)) != FPT_OK) return rc;
+    if ((size_t)grid > sc->partials_blocks)
+        return set_err(FPT_E_DEVICE, "%d adjoint blocks exceed the %zu reserved", grid, sc->partials_blocks);
     KBuffers Bf;
     std::memset(&Bf, 0, sizeof Bf);
     Bf.tables = sc->d_tables;
@@ -1254,8 +1298,185 @@ void fpt_batch_destroy(fpt_batch* bt) {
     delete bt;
 }
 
-int32_t fpt_autotune(fpt_scene* sc, const fpt_run* run, fpt_batch* bt, fpt_tune* out, float* best_ms) {
-    if (!out || (!sc && !bt) || (sc && !run)) return set_err(FPT_E_INVALID, "NULL argument");
+}  // extern "C"
+
+namespace {
+
+// Launch-shape cache: a JSON object mapping "<workload>@<device>" to an object
+// of the fpt_tune fields and "ms" (numbers).  Only this shape is read; fields
+// other than those are ignored.
+struct CachedTune {
+    fpt_tune t;
+    double ms;
+};
+
+void skip_ws(const char*& p) {
+    while (*p == ' ' || *p == '\n' || *p == '\r' || *p == '\t') ++p;
+}
+
+bool parse_string(const char*& p, std::string* out) {
+    skip_ws(p);
+    if (*p != '"') return false;
+    ++p;
+    out->clear();
+    while (*p && *p != '"') {
+        if (*p == '\\') return false;  // keys of this cache never need escapes
+        out->push_back(*p++);
+    }
+    if (*p != '"') return false;
+    ++p;
+    return true;
+}
+
+bool expect(const char*& p, char c) {
+    skip_ws(p);
+    if (*p != c) return false;
+    ++p;
+    return true;
+}
+
+bool parse_cache(const std::string& text, std::map<std::string, CachedTune>* out) {
+    const char* p = text.c_str();
+    skip_ws(p);
+    if (!*p) return true;  // an empty file is an empty cache
+    if (!expect(p, '{')) return false;
+    skip_ws(p);
+    if (*p == '}') return true;
+    for (;;) {
+        std::string key, field;
+        if (!parse_string(p, &key) || !expect(p, ':') || !expect(p, '{')) return false;
+        CachedTune ct;
+        std::memset(&ct.t, 0, sizeof ct.t);
+        ct.ms = 0.0;
+        skip_ws(p);
+        if (*p != '}') {
+            for (;;) {
+                if (!parse_string(p, &field) || !expect(p, ':')) return false;
+                skip_ws(p);
+                char* end = nullptr;
+                const double v = std::strtod(p, &end);
+                if (end == p) return false;
+                p = end;
+                if (field == "ms") ct.ms = v;
+                else if (field == "block_threads") ct.t.block_threads = (int32_t)v;
+                else if (field == "blocks_per_cu") ct.t.blocks_per_cu = (int32_t)v;
+                else if (field == "refill_lanes") ct.t.refill_lanes = (int32_t)v;
+                else if (field == "chunk_paths") ct.t.chunk_paths = (int32_t)v;
+                else if (field == "block_min_vertices") ct.t.block_min_vertices = (int32_t)v;
+                else if (field == "block_segments") ct.t.block_segments = (int32_t)v;
+                else if (field == "wide_rounds") ct.t.wide_rounds = (int32_t)v;
+                skip_ws(p);
+                if (*p == ',') { ++p; continue; }
+                if (*p == '}') break;
+                return false;
+            }
+        }
+        ++p;  // '}'
+        (*out)[key] = ct;
+        skip_ws(p);
+        if (*p == ',') { ++p; continue; }
+        if (*p == '}') return true;
+        return false;
+    }
+}
+
+int32_t read_cache(const char* path, std::map<std::string, CachedTune>* cache) {
+    FILE* f = std::fopen(path, "rb");
+    if (!f) return FPT_OK;  // no cache yet
+    std::string text;
+    char buf[4096];
+    size_t n;
+    while ((n = std::fread(buf, 1, sizeof buf, f)) > 0) text.append(buf, n);
+    std::fclose(f);
+    if (!parse_cache(text, cache)) return set_err(FPT_E_INVALID, "malformed tune cache %s", path);
+    return FPT_OK;
+}
+
+// Rewrites the cache (keys and fields sorted), through a temporary file.
+int32_t write_cache(const char* path, const std::map<std::string, CachedTune>& cache) {
+    const std::string tmp = std::string(path) + ".tmp";
+    FILE* f = std::fopen(tmp.c_str(), "wb");
+    if (!f) return set_err(FPT_E_INVALID, "cannot write tune cache %s", tmp.c_str());
+    std::fputs("{", f);
+    bool first = true;
+    for (const auto& kv : cache) {
+        const fpt_tune& t = kv.second.t;
+        std::fprintf(f,
+                     "%s\n \"%s\": {\n  \"block_min_vertices\": %d,\n  \"block_segments\": %d,\n"
+                     "  \"block_threads\": %d,\n  \"blocks_per_cu\": %d,\n  \"chunk_paths\": %d,\n"
+                     "  \"ms\": %.9g,\n  \"refill_lanes\": %d,\n  \"wide_rounds\": %d\n }",
+                     first ? "" : ",", kv.first.c_str(), t.block_min_vertices, t.block_segments,
+                     t.block_threads, t.blocks_per_cu, t.chunk_paths, kv.second.ms, t.refill_lanes,
+                     t.wide_rounds);
+        first = false;
+    }
+    std::fputs("\n}", f);
+    const bool ok = std::fclose(f) == 0;
+    if (!ok || std::rename(tmp.c_str(), path) != 0)
+        return set_err(FPT_E_INVALID, "cannot write tune cache %s", path);
+    return FPT_OK;
+}
+
+// Cache key suffix of the current device: its architecture and CU count.
+int32_t device_tag(std::string* tag) {
+    int dev = 0;
+    hipDeviceProp_t prop;
+    HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+    HIP_TRY(hipGetDeviceProperties(&prop, dev), "hipGetDeviceProperties");
+    std::string arch = prop.gcnArchName;
+    const size_t colon = arch.find(':');
+    if (colon != std::string::npos) arch.resize(colon);
+    *tag = arch + "x" + std::to_string(prop.multiProcessorCount) + "cu";
+    return FPT_OK;
+}
+
+int32_t measure_tune(fpt_scene* sc, const fpt_run* run, fpt_batch* bt, fpt_tune* out, float* best_ms);
+
+}  // namespace
+
+extern "C" {
+
+int32_t fpt_autotune(fpt_scene* sc, const fpt_run* run, fpt_batch* bt, const char* cache_path,
+                     const char* workload, uint32_t flags, fpt_tune* out, float* best_ms) {
+    // without a scene or batch only a cache lookup is possible
+    const bool lookup = (flags & FPT_TUNE_CACHED_ONLY) && cache_path;
+    if (!out || (!sc && !bt && !lookup) || (sc && !run)) return set_err(FPT_E_INVALID, "NULL argument");
+    if (cache_path && !workload) return set_err(FPT_E_INVALID, "a cache needs a workload name");
+    if (flags & ~(FPT_TUNE_FORCE | FPT_TUNE_CACHED_ONLY)) return set_err(FPT_E_INVALID, "unknown tune flags");
+    std::map<std::string, CachedTune> cache;
+    std::string key;
+    if (cache_path) {
+        int32_t rc = read_cache(cache_path, &cache);
+        if (rc != FPT_OK) return rc;
+        std::string tag;
+        if ((rc = device_tag(&tag)) != FPT_OK) return rc;
+        key = std::string(workload) + "@" + tag;
+        auto it = cache.find(key);
+        if (it != cache.end() && !(flags & FPT_TUNE_FORCE)) {
+            *out = it->second.t;
+            if (best_ms) *best_ms = (float)it->second.ms;
+            return FPT_OK;
+        }
+    }
+    if (flags & FPT_TUNE_CACHED_ONLY) {
+        std::memset(out, 0, sizeof *out);  // the library defaults
+        if (best_ms) *best_ms = 0.f;
+        return FPT_OK;
+    }
+    float ms = 0.f;
+    int32_t rc = measure_tune(sc, run, bt, out, &ms);
+    if (rc != FPT_OK) return rc;
+    if (best_ms) *best_ms = ms;
+    if (!cache_path) return FPT_OK;
+    cache[key] = CachedTune{*out, (double)ms};
+    return write_cache(cache_path, cache);
+}
+
+}  // extern "C"
+
+namespace {
+
+int32_t measure_tune(fpt_scene* sc, const fpt_run* run, fpt_batch* bt, fpt_tune* out, float* best_ms) {
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0), "event");
     HIP_TRY(hipEventCreate(&e1), "event");
@@ -1351,8 +1572,8 @@ int32_t fpt_autotune(fpt_scene* sc, const fpt_run* run, fpt_batch* bt, fpt_tune*
     (void)hipEventDestroy(e1);
     if (rc != FPT_OK) return rc;
     *out = best_t;
-    if (best_ms) *best_ms = best;
+    *best_ms = best;
     return FPT_OK;
 }
 
-}  // extern "C"
+}  // namespace

@@ -36,6 +36,11 @@ class Scene:
 
     def __init__(self, desc: dict):
         self.desc = desc
+        # the differentiable parameters the scene's tables currently hold:
+        # [conc per (medium, dye slot)] + [QY per dye] + [sigma_s per medium]
+        self.theta = np.array([c for m in desc["media"] for _, c in m["dyes"]] +
+                              [d["qy"] for d in desc["dyes"]] +
+                              [m["sigma_s"] for m in desc["media"]], dtype=np.float64)
         self._d = _abi.scene_desc(desc)
         h = C.c_void_p()
         check(lib().fpt_scene_create(C.byref(self._d), C.byref(h)))
@@ -70,12 +75,21 @@ class Scene:
         return n
 
     def set_params(self, conc=None, qy=None, sigma_s=None):
+        """fpt_scene_set_params on the current stream: renders enqueued after
+        this call see the new parameters."""
         def arr(x):
             return None if x is None else np.ascontiguousarray(x, dtype=np.float64)
         c, q, s = arr(conc), arr(qy), arr(sigma_s)
         check(lib().fpt_scene_set_params(
             self._h, None if c is None else c.ctypes.data, None if q is None else q.ctypes.data,
-            None if s is None else s.ctypes.data))
+            None if s is None else s.ctypes.data, _stream()))
+        nc = sum(len(m["dyes"]) for m in self.desc["media"])
+        nd = len(self.desc["dyes"])
+        th = self.theta.copy()
+        for part, lo, n in ((c, 0, nc), (q, nc, nd), (s, nc + nd, len(self.desc["media"]))):
+            if part is not None:
+                th[lo:lo + n] = part[:n]
+        self.theta = th
 
     def set_tune(self, block_threads=0, blocks_per_cu=0, refill_lanes=0, chunk_paths=0,
                  block_min_vertices=0, block_segments=0, wide_rounds=0):

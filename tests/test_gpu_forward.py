@@ -14,7 +14,7 @@ import pytest
 import closed_forms as cf
 import oracle
 import workloads
-from replay import compare_records
+from replay import compare_records, oracle_replay
 from stats import batch_z, binom_z, check_z, escape_z, multinomial_z
 
 pytestmark = pytest.mark.gpu
@@ -75,13 +75,13 @@ def test_tables_match_oracle(name):
 
 # ------------------------------------------------------------------ plain slab
 def test_slab_replay_all_paths():
-    """Plain slab, all 2^16 paths: every non-marginal path reproduces the
-    oracle's vertex count, scatters, emissions, exit, wavelength and exit
-    state (fp32 vs fp64, relative 1e-5)."""
+    """Plain slab, all 2^16 paths, full length: every non-marginal path
+    reproduces the oracle's vertex count, scatters, emissions, exit,
+    wavelength and exit state (fp32 vs fp64, relative 1e-5 scaled by the
+    path's condition number)."""
     scene, run = workloads.slab_config()
     g = _records(scene, run)
-    o = oracle.render(scene, run, records=True)["records"]
-    rep = compare_records(g, o, scale=1.0)
+    rep = compare_records(g, oracle_replay(scene, run))
     print(rep)
 
 
@@ -110,8 +110,7 @@ def test_slab_full_size_sampled(ior):
     assert abs(f.sum() * n - (td["exit_esc_r"] + td["exit_esc_t"])) <= 1e-3 * n
     for begin in (0, n // 2 - 2048, n - 4096):
         sub = dict(run, path_begin=begin, path_count=4096)
-        o = oracle.render(scene, sub, records=True)["records"]
-        compare_records(rec[begin:begin + 4096], o, scale=1.0)
+        compare_records(rec[begin:begin + 4096], oracle_replay(scene, sub))
 
 
 def test_slab_statistical_parity():
@@ -236,8 +235,7 @@ def test_sphere_body_replay_and_parity():
     scene = workloads.sphere_scene()
     n = 1 << 14
     run = workloads.make_run(n, seed=5)
-    compare_records(_records(scene, run), oracle.render(scene, run, records=True)["records"],
-                    scale=0.5, sigma_t_max=20.0)
+    compare_records(_records(scene, run), oracle_replay(scene, run, scale=0.5), scale=0.5)
     ng = 1 << 20
     g, _ = _render(scene, workloads.make_run(ng, seed=6))
     o = oracle.render(scene, workloads.make_run(n * 4, seed=7))
@@ -250,9 +248,7 @@ def test_cornell_replay():
     the sum of each path's splat values."""
     scene = workloads.cornell_scene(32, 32)
     run = workloads.make_run(1 << 15, seed=4)
-    rep = compare_records(_records(scene, run),
-                          oracle.render(scene, run, records=True)["records"], scale=1.0,
-                          sigma_t_max=200.0)
+    rep = compare_records(_records(scene, run), oracle_replay(scene, run))
     print(rep)
 
 
@@ -269,8 +265,9 @@ def test_cornell_statistical_parity():
 
 def test_cornell_full_size_sampled():
     """Full 128x128, 2^20-path Cornell render in the benchmark's launch
-    configuration: sampled path ranges replay against the oracle, and the film
-    total equals the sum of every path's deposited values."""
+    configuration: the film total equals the sum of every path's deposited
+    values, and three sampled ranges of 4096 paths replay against the oracle
+    over their first 256 vertices and at full length."""
     import torch
     fpt = _fpt()
     from paper_1706_03024_amd import autotune
@@ -281,29 +278,65 @@ def test_cornell_full_size_sampled():
     rec, _ = sc.records(run)
     torch.cuda.synchronize()
     total = float(film.double().sum())
-    sc.close()
     assert abs(total - float(rec["splat_sum"].astype(np.float64).sum())) <= 1e-4 * total
     N = run["path_count"]
     for begin in (0, N // 3, N - 4096):
         sub = dict(run, path_begin=begin, path_count=4096)
-        o = oracle.render(scene, sub, records=True)["records"]
-        compare_records(rec[begin:begin + 4096], o, scale=1.0, sigma_t_max=200.0)
+        g256, _ = sc.records(sub, max_vertices=256)
+        print("256 vertices", compare_records(g256, oracle_replay(scene, sub, max_vertices=256)))
+        print("full length", compare_records(rec[begin:begin + 4096], oracle_replay(scene, sub)))
+    sc.close()
 
 
 def test_large_scene_sampled_replay():
     """Large 5-sphere scene (301 bins, sigma_s up to 1000/mm), in the
-    benchmark's launch shape: 4096 sampled paths, first 256 vertices, replay
-    against the oracle."""
+    benchmark's launch shape: three sampled ranges of 4096 paths, first 256
+    vertices, replay against the oracle."""
     from paper_1706_03024_amd import autotune
     scene, run = workloads.large_config()
-    sub = dict(run, path_begin=123456789, path_count=4096)
     sc = _fpt().Scene(scene)
     autotune.autotune("large-512-1024spp", scene=sc, run=run, measure=False)  # the cached shape, if any
-    g, _ = sc.records(sub, max_vertices=256)
+    for begin in (7, 123456789, run["path_count"] - 4096):
+        sub = dict(run, path_begin=begin, path_count=4096)
+        g, _ = sc.records(sub, max_vertices=256)
+        print(compare_records(g, oracle_replay(scene, sub, max_vertices=256)))
     sc.close()
-    o = oracle.render(scene, sub, records=True, max_vertices=256)["records"]
-    rep = compare_records(g, o, scale=1.0, sigma_t_max=1000.0)
-    print(rep)
+
+
+def test_large_scene_forward_film():
+    """The benchmark's forward instantiation on the large scene (5 bimodal
+    dye spheres, 301 bins, sigma_s up to 1000/mm, scatter cap 1e4) in its
+    tuned launch shape, at 16x16 pixels: 128-vertex deep rounds, deferred
+    connections and merged deposits.  The film, in 32 parity slices, agrees
+    bin by bin with the oracle's film of independent paths (batch-mean z per
+    film cell, per pixel summed over wavelength, and per 10-bin band summed
+    over the image); on the same paths its total equals the sum of the
+    replayed records' deposits."""
+    import torch
+    fpt = _fpt()
+    from paper_1706_03024_amd import autotune
+    B = 32
+    scene = workloads.large_scene(16, 16)
+    _, big_run = workloads.large_config()
+    sc = fpt.Scene(scene)
+    autotune.autotune("large-512-1024spp", scene=sc, run=big_run, measure=False)
+    run = workloads.make_run(1 << 25, seed=31, parity_batches=B)
+    g = sc.render(run).cpu().numpy().astype(np.float64)
+    same = workloads.make_run(1 << 22, seed=33)
+    film = sc.render(same)
+    rec, _ = sc.records(same)
+    torch.cuda.synchronize()
+    total = float(film.double().sum())
+    sc.close()
+    assert abs(total - float(rec["splat_sum"].astype(np.float64).sum())) <= 1e-4 * total
+    o = oracle.render(scene, workloads.make_run(1 << 21, seed=32, parity_batches=B))["film"]
+    z = batch_z(g, o)
+    assert z.size > 1000
+    check_z(z, "large scene film cells: GPU vs oracle", dof=B - 1)
+    check_z(batch_z(g.sum(4), o.sum(4)), "large scene image (summed over wavelength)", dof=B - 1)
+    band = lambda f: f[..., :300].reshape(f.shape[:-1] + (30, 10)).sum(-1).sum((2, 3))
+    zb = batch_z(band(g), band(o))
+    check_z(zb, "large scene spectrum in 10-bin bands (summed over the image)", dof=B - 1)
 
 
 def test_splat_roulette_and_fluorescence_only():
@@ -311,8 +344,7 @@ def test_splat_roulette_and_fluorescence_only():
     only the emitted component.  Both match the oracle on the same streams."""
     scene = workloads.cornell_scene(32, 32)
     run = workloads.make_run(1 << 14, seed=12, splat_rr=0.05, fluorescence_only=True)
-    compare_records(_records(scene, run), oracle.render(scene, run, records=True)["records"],
-                    sigma_t_max=200.0)
+    compare_records(_records(scene, run), oracle_replay(scene, run))
     B = 32
     g, _ = _render(scene, workloads.make_run(1 << 21, seed=13, parity_batches=B, splat_rr=0.05))
     o = oracle.render(scene, workloads.make_run(1 << 18, seed=14, parity_batches=B))["film"]
@@ -378,8 +410,7 @@ def test_tabulated_spectra():
     if all(np.array_equal(gt[k], ga[k]) for k in ("sigma_t", "emis_cdf", "rho")):
         assert np.array_equal(rt.view(np.uint32), ra.view(np.uint32))
     else:
-        o = oracle.render(t, run, records=True, max_vertices=256)["records"]
         st = fpt.Scene(t)
         rt, _ = st.records(run, max_vertices=256)
         st.close()
-        compare_records(rt, o, scale=1.0, sigma_t_max=200.0)
+        compare_records(rt, oracle_replay(t, run, max_vertices=256))

@@ -13,7 +13,7 @@ import pytest
 
 import oracle
 import workloads
-from replay import compare_records
+from replay import compare_records, oracle_replay
 
 pytestmark = pytest.mark.gpu
 
@@ -58,8 +58,7 @@ def test_maximal_box_scene():
     film = sc.render(run, tallies=t)
     rec, _ = sc.records(run)
     torch.cuda.synchronize()
-    o = oracle.render(scene, run, records=True)
-    print(compare_records(rec, o["records"], scale=1.0, sigma_t_max=60.0))
+    print(compare_records(rec, oracle_replay(scene, run)))
     total = float(film.double().sum())
     assert total > 0.0
     assert abs(total - float(rec["splat_sum"].astype(np.float64).sum())) <= 1e-4 * total
@@ -67,8 +66,7 @@ def test_maximal_box_scene():
     assert tal["emissions"] > 0 and tal["crossings"] > 0 and tal["exit_light"] > 0
     crun = workloads.make_run(oracle.camera_paths(scene, 1), seed=92)
     crec = sc.camera_records(crun)
-    oc = oracle.render_camera(scene, crun, records=True)["records"]
-    print(compare_records(crec, oc, scale=1.0, sigma_t_max=60.0))
+    print(compare_records(crec, oracle_replay(scene, crun, camera=True)))
     assert np.sum(crec["splat_sum"] > 0) > 100
     assert sc.n_params == 48
     with pytest.raises(fpt.FptError) as e:
@@ -107,7 +105,7 @@ def test_maximum_bins_slab_and_box():
     run = workloads.make_run(1 << 14, seed=93)
     rec, _ = sc.records(run)
     sc.close()
-    print(compare_records(rec, oracle.render(slab, run, records=True)["records"], scale=1.0))
+    print(compare_records(rec, oracle_replay(slab, run)))
     assert np.sum(rec["n_emit"] > 0) > 0
 
     box = workloads.cornell_scene(16, 16, n_bins=1024)
@@ -115,13 +113,11 @@ def test_maximum_bins_slab_and_box():
     _tables_match(sc, box)
     run = workloads.make_run(1 << 13, seed=94)
     rec, _ = sc.records(run, max_vertices=512)
-    o = oracle.render(box, run, records=True, max_vertices=512)["records"]
-    print(compare_records(rec, o, scale=1.0, sigma_t_max=200.0))
+    print(compare_records(rec, oracle_replay(box, run, max_vertices=512)))
     n = oracle.camera_paths(box, 1)
     sub = workloads.make_run(4096, seed=95, path_begin=n // 2, total_paths=n)
     crec = sc.camera_records(sub, max_vertices=512)
-    oc = oracle.render_camera(box, sub, records=True, max_vertices=512)["records"]
-    print(compare_records(crec, oc, scale=1.0, sigma_t_max=400.0))
+    print(compare_records(crec, oracle_replay(box, sub, max_vertices=512, camera=True)))
     sc.close()
 
 

@@ -308,3 +308,19 @@ def test_tabulated_spectra_reproduce_the_analytic_scene():
     assert np.array_equal(a["records"]["exit_code"], b["records"]["exit_code"])
     assert np.array_equal(a["records"]["n_vertices"], b["records"]["n_vertices"])
     np.testing.assert_allclose(b["film"], a["film"], rtol=1e-9, atol=1e-300)
+
+
+def test_32bit_path_ids():
+    """Path ids are the 32-bit first counter word: a job may hold 2^32 paths
+    (its last ids render, each escape weighing 1/2^32), but one call may not
+    walk all 2^32 of them."""
+    s, r = workloads.slab_config()
+    tail = dict(r, path_begin=(1 << 32) - 100, path_count=100, total_paths=1 << 32)
+    o = oracle.render(s, tail)
+    t = oracle.tallies_dict(o["tallies"])
+    assert t["paths"] == 100
+    assert abs(o["film"].sum() * 2.0 ** 32 - (t["exit_esc_r"] + t["exit_esc_t"])) < 1e-6
+    with pytest.raises(oracle.OracleError):
+        oracle.render(s, dict(r, path_begin=0, path_count=1 << 32, total_paths=1 << 32))
+    with pytest.raises(oracle.OracleError):
+        oracle.render(s, dict(r, path_count=16, total_paths=(1 << 32) + 1))
