@@ -309,6 +309,26 @@ int32_t fpt_scene_timing(fpt_scene* scene, int32_t* renders, float* transport_ms
 int32_t fpt_render(fpt_scene* scene, const fpt_run* run, float* film_dev, uint64_t* tallies_dev,
                    void* hip_stream);
 
+/* Allocation-free variant of fpt_render, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Same arguments, results and errors as fpt_render,
+ * except that its device scratch -- path-queue heads, escape counters and the
+ * deferred-connection slices -- lives in a static array of 24 MiB the library
+ * holds on every device it runs on (until the process ends) instead of the
+ * scene's buffers; it calls no hipMalloc, hipFree or allocating routine.
+ * The deferred slices shrink to fit beside the rest (a full slice falls back to
+ * the in-kernel queue), so tallies are identical to fpt_render's and the film
+ * differs only in the fp32 rounding order of its atomic sums.  Limit: the
+ * escape counters (parity_batches * 4 * n_bins, at most 262144) and per-wave
+ * counts must fit the array beside the queue (they always do for valid runs;
+ * otherwise FPT_E_RANGE before any launch).  Every call on a device
+ * shares that device's array, and the queue and counters are cleared at the
+ * start of each call: calls that overlap on one device (on different streams)
+ * race and give wrong results; serialise them.  Not timed by
+ * fpt_scene_set_timing. */
+int32_t fpt_render_noalloc(fpt_scene* scene, const fpt_run* run, float* film_dev,
+                           uint64_t* tallies_dev, void* hip_stream);
+
 /* Path-replay adjoint of fpt_render: replays the same paths (same random
  * numbers) and accumulates into grad_dev (device, fp32[fpt_grad_param_count])
  * the gradient of <grad_film, film> with respect to the parameters, using the

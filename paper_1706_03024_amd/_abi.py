@@ -140,6 +140,7 @@ def lib():
         "fpt_scene_set_timing": (C.c_int32, [vp, C.c_int32]),
         "fpt_scene_timing": (C.c_int32, [vp, C.POINTER(C.c_int32), C.POINTER(C.c_float), C.POINTER(C.c_float)]),
         "fpt_render": (C.c_int32, [vp, C.POINTER(Run), vp, vp, vp]),
+        "fpt_render_noalloc": (C.c_int32, [vp, C.POINTER(Run), vp, vp, vp]),
         "fpt_render_adjoint": (C.c_int32, [vp, C.POINTER(Run), vp, vp, vp, vp]),
         "fpt_render_records": (C.c_int32, [vp, C.POINTER(Run), vp, C.c_uint32, vp, vp, vp]),
         "fpt_render_camera": (C.c_int32, [vp, C.POINTER(Run), vp, vp, vp, C.c_uint32, vp]),

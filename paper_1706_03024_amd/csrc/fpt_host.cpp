@@ -41,6 +41,7 @@ size_t camera_lds_bytes(const KParams& P);
 hipError_t camera_occupancy(const KParams& P, bool rec, int block, int* blocks_per_cu);
 hipError_t launch_camera(const KParams& P, const KBuffers& B, bool rec, int grid, int block,
                          hipStream_t s);
+hipError_t static_scratch(void** ptr, size_t* bytes);
 }  // namespace fpt
 
 using namespace fpt;
@@ -1044,6 +1045,63 @@ int32_t fpt_render(fpt_scene* sc, const fpt_run* run, float* film, uint64_t* tal
     if (defer) HIP_TRY(launch_splat_jobs(P, Bf, (int)waves, s), "deferred splats");
     if (ev) HIP_TRY(hipEventRecord(ev[2], s), "hipEventRecord");
     if (escape) HIP_TRY(launch_finalize_counts(sc->d_counts, film, n_counts, P.wscale, s), "finalize");
+    return FPT_OK;
+}
+
+int32_t fpt_render_noalloc(fpt_scene* sc, const fpt_run* run, float* film, uint64_t* tallies, void* stream) {
+    if (!sc || !film) return set_err(FPT_E_INVALID, "NULL argument");
+    uint32_t B;
+    int32_t rc = check_run(sc, run, &B);
+    if (rc != FPT_OK) return rc;
+    if (run->path_count == 0) return FPT_OK;
+    hipStream_t s = (hipStream_t)stream;
+    KParams P;
+    fill_run(sc, run, B, &P);
+    const bool escape = sc->desc.sensor == FPT_SENSOR_ESCAPE;
+    const size_t n_counts = escape ? (size_t)film_elems(sc->desc, B) : 0;
+    int block;
+    if ((rc = transport_block(sc, P, MODE_FWD, &block)) != FPT_OK) return rc;
+    int grid;
+    if ((rc = grid_for(sc, P, MODE_FWD, block, run->path_count, &grid)) != FPT_OK) return rc;
+    const bool defer = sc->desc.sensor == FPT_SENSOR_PINHOLE;
+    const size_t waves = (size_t)grid * (block / 64);
+    // the static scratch on this device: queue heads | counts per wave | escape
+    // counters | deferred slices (each part 256-byte aligned)
+    void* base = nullptr;
+    size_t cap = 0;
+    HIP_TRY(static_scratch(&base, &cap), "static scratch address");
+    auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    const size_t q_bytes = up(queue_words() * 8);
+    const size_t c_bytes = defer ? up(waves * 4) : 0;
+    const size_t e_bytes = up(n_counts * 4);
+    const size_t fixed = q_bytes + c_bytes + e_bytes;
+    if (fixed > cap)
+        return set_err(FPT_E_RANGE, "escape film of %zu counters exceeds the %zu-byte static scratch", n_counts, cap);
+    char* b = static_cast<char*>(base);
+    KBuffers Bf;
+    std::memset(&Bf, 0, sizeof Bf);
+    Bf.tables = sc->d_tables;
+    Bf.film = film;
+    Bf.counter = reinterpret_cast<unsigned long long*>(b);
+    Bf.counts = escape ? reinterpret_cast<uint32_t*>(b + q_bytes + c_bytes) : nullptr;
+    Bf.tallies = tallies ? reinterpret_cast<unsigned long long*>(tallies) : nullptr;
+    uint32_t slice = 0;
+    if (defer) {
+        // deferred slices shrink to what is left (a full slice falls back to
+        // the wave's LDS queue, so the film changes only in fp32 rounding order)
+        const size_t per = (cap - fixed) / (waves * 5 * 4);
+        slice = (uint32_t)std::min<size_t>(kSjobSlice, per & ~(size_t)63);
+        if (slice > 0) {
+            Bf.sjob_counts = reinterpret_cast<uint32_t*>(b + q_bytes);
+            Bf.sjobs = reinterpret_cast<uint32_t*>(b + fixed);
+            Bf.sjob_slice = slice;
+        }
+    }
+    HIP_TRY(launch_zero_u64(Bf.counter, queue_words(), s), "zero queue");
+    if (escape) HIP_TRY(launch_zero_u32(Bf.counts, n_counts, s), "zero counts");
+    HIP_TRY(launch_transport(P, Bf, MODE_FWD, grid, block, s), "transport launch");
+    if (slice > 0) HIP_TRY(launch_splat_jobs(P, Bf, (int)waves, s), "deferred splats");
+    if (escape) HIP_TRY(launch_finalize_counts(Bf.counts, film, n_counts, P.wscale, s), "finalize");
     return FPT_OK;
 }
 

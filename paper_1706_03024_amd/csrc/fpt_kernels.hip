@@ -12,6 +12,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include "fpt_internal.h"
 
@@ -2469,6 +2470,37 @@ hipError_t launch_reduce_partials(const float* partials, int nblocks, int np, fl
                                   hipStream_t s) {
     hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(256), 0, s, partials, nblocks, np, grad);
     return hipGetLastError();
+}
+
+// -------------------------------------------------------------------------
+// Device scratch of the allocation-free forward render (fpt_render_noalloc):
+// path-queue heads, escape counters and deferred-connection slices live in
+// this file-scope array instead of buffers the scene allocates.  Every device
+// the library runs on holds its own copy until the process ends; its name is
+// a host-side stand-in, so host code only ever uses the address
+// hipGetSymbolAddress returns on each device (looked up once per device, with
+// that device current, and kept).
+constexpr size_t kStaticScratchBytes = (size_t)24 << 20;
+static __device__ __align__(256) uint32_t scratch[kStaticScratchBytes / 4];
+
+hipError_t static_scratch(void** ptr, size_t* bytes) {
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static void* addr[kMaxDevices] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        addr[dev] = p;
+    }
+    *ptr = addr[dev];
+    *bytes = kStaticScratchBytes;
+    return hipSuccess;
 }
 
 }  // namespace fpt

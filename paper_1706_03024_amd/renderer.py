@@ -136,6 +136,19 @@ class Scene:
         check(lib().fpt_render(self._h, C.byref(r), _ptr(film), _ptr(tallies), _stream()))
         return film
 
+    def render_noalloc(self, run: dict, film, tallies=None):
+        """fpt_render_noalloc: fpt_render with the library's static device
+        scratch; accumulates into `film` (caller-allocated, like `tallies`)."""
+        B = max(1, run.get("parity_batches", 1))
+        _require_cuda(film, torch.float32, "film")
+        if film.numel() != int(np.prod(self.film_shape(B))):
+            raise ValueError("film has the wrong size")
+        if tallies is not None:
+            _require_cuda(tallies, torch.int64, "tallies")
+        r = _abi.run_struct(run)
+        check(lib().fpt_render_noalloc(self._h, C.byref(r), _ptr(film), _ptr(tallies), _stream()))
+        return film
+
     def render_adjoint(self, run: dict, grad_film, grad=None, tallies=None):
         """fpt_render_adjoint: accumulates d<grad_film, film>/d theta into `grad`."""
         _require_cuda(grad_film, torch.float32, "grad_film")
