@@ -1,18 +1,21 @@
 """Benchmark: path vertices/s of the fluorescent path tracer on one MI355X.
 
-Headline workload: the Cornell-style scene (three dye spheres in a diffuse
-box, 128x128 pinhole, 64 spp = 2^20 light paths, 101 bins).  One step = one
-full forward render of that job (fpt_render: every per-vertex stage of the
-walk plus the film splat), inputs resident on the device.  Vertices are
-counted exactly by the device tallies.
+Headline workload: the large highly scattering scene (five bimodal dye
+spheres, sigma_s up to 1000/mm, in a diffuse box; 512x512 pinhole, 1024 spp
+= 2^28 light paths, 301 bins, scatter cap 1e4), the largest single-GPU
+configuration.  One step = one full forward render of that job (fpt_render:
+every per-vertex stage of the walk plus the film splat), inputs resident on
+the device.  Vertices are counted exactly by the device tallies.
 
 The JSON line also carries the roofline of the render's two launches (the
-transport kernel and the deferred-connection kernel): algorithmic ALU lane
-operations per render, from the exact event tallies and a per-event
-operation table, divided by the two launches' mean durations measured with
-HIP events on the render stream, against the MI355X vector issue rate; the
-CPU oracle timed on the host; and the other forms (large scene, plain slab,
-forward+adjoint, batched) as extra fields.
+transport kernel and the deferred-connection kernel): algorithmic FP32 FLOPs
+per render, from the exact event tallies and a per-event FLOP table, divided
+by the two launches' durations measured with HIP events on the render stream
+(mean and median over the timed renders), against the MI355X FP32 vector
+peak; beside it, labelled separately, the same renders' algorithmic ALU lane
+operations against the vector issue rate; the CPU oracle timed on the host;
+and the other forms (Cornell scene, plain slab, forward+adjoint, batched,
+excitation scan, camera-side estimator) as extra fields.
 """
 from __future__ import annotations
 
@@ -39,6 +42,33 @@ STEP = PHILOX + 6      # free flight: log, scale, position update
 START = 2 * PHILOX + 25  # light vertex: line choice, point and direction on the quad
 EMISSION = PHILOX + 17   # quantum-yield test, emission CDF inversion
 CAM_START = PHILOX + 90  # camera-side path: pixel of the path index, pixel sample, eye ray, box entry
+
+
+# Algorithmic FP32 work per event (an FMA counts 2, a transcendental, compare
+# or conversion 1): the per-vertex arithmetic the walk cannot avoid, whatever
+# the implementation (no random-number generation, addressing or control).
+FL_SOURCE = 19            # line choice, point on the quad, cosine-weighted direction
+FL_COLLIDE_SPHERE = 45    # flight (log, scale), sphere exit distance, advance, event, new direction
+FL_COLLIDE_PLANE = 30     # the same with a plane distance (slab, half-space, unbounded)
+FL_EMIT = 23              # quantum-yield test, emission CDF search, emitted direction
+FL_NONRAD = 1             # quantum-yield test
+FL_SURFACE = 17           # reaching an interface, wall, the light or the open face
+FL_REFLECT = 19           # wall or Fresnel reflection: hit plus a new direction
+FL_CONN = 38              # camera connection: distance, projection, cosines, exp
+FL_CONN_SPHERE = 20       # + one chord per sphere
+
+
+def flops_model(t, n_spheres, geometry):
+    """Algorithmic FP32 FLOPs of one render from its event tallies."""
+    collide = FL_COLLIDE_PLANE if geometry in ("slab", "halfspace", "infinite") else FL_COLLIDE_SPHERE
+    return (FL_SOURCE * t["paths"]
+            + collide * (t["scatters"] + t["dye_abs"] + t["exit_bg"])
+            + FL_EMIT * t["emissions"] + FL_NONRAD * t["exit_nonrad"]
+            + FL_SURFACE * (t["crossings"] + t["exit_wall"] + t["exit_light"] + t["exit_esc_r"]
+                            + t["exit_esc_t"])
+            + FL_REFLECT * t["wall_reflect"]
+            + (FL_CONN + FL_CONN_SPHERE * n_spheres) * (t["splat_hit"] + t["splat_miss"]
+                                                        + t["splat_rr_kill"]))
 
 
 def ops_model(t, n_spheres, geometry, refractive=False):
@@ -72,10 +102,11 @@ def camera_ops(t, n_spheres, n_lines):
             + conn * (t["splat_hit"] + t["splat_miss"]))
 
 
-def time_renders(sc, run, steps, warmup, film, camera=False):
+def time_renders(sc, run, steps, warmup, film, camera=False, each=False):
     """Wall time per render over `steps` renders, and the mean durations of
     its transport and deferred-connection launches from the HIP events the
-    library records around them on the render stream in the same renders."""
+    library records around them on the render stream in the same renders
+    (with each=True also the per-render launch durations)."""
     import torch
     render = sc.render_camera if camera else sc.render
     for _ in range(warmup):
@@ -87,6 +118,11 @@ def time_renders(sc, run, steps, warmup, film, camera=False):
         render(run, film=film)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    if each:
+        t, d = sc.timing_each()
+        sc.set_timing(False)
+        assert len(t) == steps
+        return wall / steps * 1e3, float(t.mean()), float(d.mean()), t + d
     n, t_ms, d_ms = sc.timing()
     sc.set_timing(False)
     assert n == steps
@@ -109,13 +145,15 @@ def forward_form(scene, run, steps, warmup, tune_name=None):
     tune = autotune.autotune(tune_name, scene=sc, run=run) if tune_name else None
     film = sc.new_film()
     tal = count_vertices(sc, run)
-    ms, t_ms, d_ms = time_renders(sc, run, steps, warmup, film)
+    ms, t_ms, d_ms, each = time_renders(sc, run, steps, warmup, film, each=True)
     geo = scene["geometry"]["kind"]
     nsph = len(scene["geometry"].get("spheres", [])) if geo == "box" else 0
     ops = ops_model(tal, nsph, geo, refractive=scene["media"][scene["geometry"].get("medium", 0)].get("ior", 1.0) != 1.0)
+    flops = flops_model(tal, nsph, geo)
     sc.close()
     return {"vertices": tal["vertices"], "ms_per_step": ms, "transport_ms": t_ms, "deferred_ms": d_ms,
-            "kernel_ms": t_ms + d_ms, "vertices_per_s": tal["vertices"] / (ms / 1e3), "ops": ops,
+            "kernel_ms": t_ms + d_ms, "kernel_ms_median": float(sorted(each)[len(each) // 2]),
+            "vertices_per_s": tal["vertices"] / (ms / 1e3), "ops": ops, "flops": flops,
             "tallies": tal, "tune": tune}
 
 
@@ -314,38 +352,46 @@ def sweep_form(steps, warmup):
 
 def cpu_baseline(scene, run, target_s=12.0):
     """The oracle as it stands (single thread, fp64) on a bounded sample of the
-    workload: the first paths of the same job, sized to roughly target_s; a
-    job that takes less is rendered whole, repeatedly, until target_s."""
+    workload: the first paths of the same job, in chunks accumulated into one
+    film, until about target_s of rendering (a job that takes less is rendered
+    whole, repeatedly)."""
+    import numpy as np
     import oracle
-    n = 1 << 14
-    t0 = time.perf_counter()
-    o = oracle.render(scene, dict(run, path_count=n))
-    dt = time.perf_counter() - t0
-    n2 = int(min(run["path_count"], max(n, n * target_s / max(dt, 1e-3))))
-    reps, verts, dt = 0, 0, 0.0
-    while dt < 0.8 * target_s or reps == 0:
+    film = np.zeros(oracle.film_shape(scene, max(1, run.get("parity_batches", 1))))
+    chunk = min(run["path_count"], 1 << 14)
+    done = verts = 0
+    dt = 0.0
+    while dt < target_s:
+        begin = done % run["path_count"]
+        n = min(chunk, run["path_count"] - begin)
         t0 = time.perf_counter()
-        o = oracle.render(scene, dict(run, path_count=n2))
+        o = oracle.render(scene, dict(run, path_begin=run["path_begin"] + begin, path_count=n),
+                          film_out=film)
         dt += time.perf_counter() - t0
         verts += int(o["tallies"][1])
-        reps += 1
+        done += n
     return {"value": verts / dt, "unit": "path vertices/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {n2} of {run['total_paths']} light paths of the same job, {reps} time(s) "
-                      f"({verts} vertices, {dt:.1f} s, fp64, 1 thread)"}
+            "sample": f"first {min(done, run['path_count'])} of {run['total_paths']} light paths of "
+                      f"the same job ({done} paths rendered, {verts} vertices, {dt:.1f} s, fp64, "
+                      f"1 thread)"}
 
 
 def _oracle_worker(task):
     """One host process of the all-cores oracle figure: renders consecutive
-    chunks of its own path range (from its start again once done) until its
-    time budget is spent; returns vertices, paths and its busy time."""
+    chunks of its own path range into one film (from its start again once
+    done) until its time budget is spent; returns vertices, paths and its
+    busy time."""
     scene, run, begin, count, budget = task
+    import numpy as np
     import oracle
+    film = np.zeros(oracle.film_shape(scene, max(1, run.get("parity_batches", 1))))
+    chunk = min(count, 1 << 14)
     t0 = time.perf_counter()
     verts = done = 0
     while time.perf_counter() - t0 < budget:
         k = done % count
-        n = count - k   # whole ranges: each call also allocates the film
-        o = oracle.render(scene, dict(run, path_begin=begin + k, path_count=n))
+        n = min(chunk, count - k)
+        o = oracle.render(scene, dict(run, path_begin=begin + k, path_count=n), film_out=film)
         verts += int(o["tallies"][1])
         done += n
     return verts, done, time.perf_counter() - t0
@@ -367,7 +413,8 @@ def cpu_all_cores(scene, run, budget_s=8.0):
     rate = sum(r[0] / r[2] for r in res)
     return {"value": rate, "unit": "path vertices/s", "cores": P, "kind": "oracle",
             "sample": f"{P} concurrent processes, each on its own 1/{P} of the same job's light paths "
-                      f"(repeated until ~{budget_s:.0f} s): {paths} paths, {verts} vertices, fp64"}
+                      f"(in chunks of up to 2^14, until ~{budget_s:.0f} s): {paths} paths, "
+                      f"{verts} vertices, fp64"}
 
 
 COPY_BYTES = 256 << 20
@@ -485,11 +532,28 @@ def profile_run(name, steps):
     print(f"profiled {steps} {name} renders", flush=True)
 
 
+HEADLINE_TUNE = "large-512-1024spp"
+
+
+def form_summary(f, workload):
+    """The per-form fields of a forward render: throughput, the algorithmic
+    FP32 rate against the FP32 peak, the ALU issue fraction (lane-operation
+    model) and, while the recorded counters match the kernel source, HBM
+    bytes per second and the issued FP32 fraction."""
+    out = {k: f[k] for k in ("vertices", "ms_per_step", "vertices_per_s", "kernel_ms",
+                             "kernel_ms_median")}
+    out["fp32_algorithmic_frac"] = f["flops"] / (f["kernel_ms"] / 1e3) / 1e12 / FP32_PEAK_TFLOPS
+    out["alu_frac"] = alu_frac(f)
+    hbm_rate(out, workload, f["kernel_ms"])
+    fp32_rate(out, workload, f["kernel_ms"])
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--only-headline", action="store_true",
@@ -508,19 +572,21 @@ def main():
     all_cores = None
     if not (args.profile or args.only_headline or args.no_cpu_baseline):
         # host processes start before anything touches the GPU
-        all_cores = cpu_all_cores(*workloads.cornell_config())
+        all_cores = cpu_all_cores(*workloads.large_config())
     import torch
     torch.cuda.set_device(int(os.environ.get("LOCAL_RANK", 0)))
     if args.profile:
         profile_run(args.profile, args.steps)
         return
-    scene, run = workloads.cornell_config()
-    head = forward_form(scene, run, args.steps, args.warmup, tune_name="cornell-128-64spp")
+    scene, run = workloads.large_config()
+    head = forward_form(scene, run, args.steps, args.warmup, tune_name=HEADLINE_TUNE)
     if args.only_headline:
-        print(json.dumps({"headline": head}, default=float), flush=True)
+        print(json.dumps({"headline": {k: v for k, v in head.items() if k != "tallies"}},
+                         default=float), flush=True)
         return
     value = head["vertices_per_s"]
-    achieved = head["ops"] / (head["kernel_ms"] / 1e3) / 1e12
+    flop_rate = head["flops"] / (head["kernel_ms"] / 1e3) / 1e12
+    ops_rate = head["ops"] / (head["kernel_ms"] / 1e3) / 1e12
     line = {
         "metric": "path vertices/s on 1 MI355X (fwd, batched, fwd+adjoint) at <=3 s.e. vs oracle",
         "value": value,
@@ -534,62 +600,64 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "cornell box, 3 Gaussian dye spheres, 128x128 pinhole, 64 spp "
-                               "(2^20 light paths), 101 bins, fwd",
+        "config": {"workload": "large highly scattering scene: box, 5 bimodal Gaussian dye spheres "
+                               "(sigma_s 200-1000/mm), 512x512 pinhole, 1024 spp (2^28 light "
+                               "paths), 301 bins, scatter cap 1e4, fwd",
                    "paths": run["path_count"], "vertices_per_step": head["vertices"],
                    "launch": head["tune"]},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TOPS,
-                     "unit": "Tops/s", "frac": achieved / ALU_PEAK_TOPS,
-                     "traffic": measured_traffic("cornell"),
+        "roofline": {"bound": "alu", "achieved": flop_rate, "peak": FP32_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": flop_rate / FP32_PEAK_TFLOPS,
+                     "traffic": measured_traffic("large"),
+                     "work": "algorithmic FP32 FLOPs per render from the event tallies x the "
+                             "per-event FLOP table (FMA = 2)",
                      "kernel": "fpt::k_transport<BOX, FWD> + fpt::k_splat_jobs",
-                     "kernel_ms": head["kernel_ms"], "transport_ms": head["transport_ms"],
-                     "deferred_ms": head["deferred_ms"], "ops_per_launch": head["ops"]},
+                     "kernel_ms": head["kernel_ms"], "kernel_ms_median": head["kernel_ms_median"],
+                     "transport_ms": head["transport_ms"], "deferred_ms": head["deferred_ms"],
+                     "flops_per_launch": head["flops"]},
+        "alu_issue": {"achieved": ops_rate, "peak": ALU_PEAK_TOPS, "unit": "T lane-ops/s",
+                      "frac": ops_rate / ALU_PEAK_TOPS, "ops_per_launch": head["ops"],
+                      "work": "algorithmic 32-bit lane operations per render (Philox, flight, "
+                              "geometry, connections) from the event tallies x the per-event "
+                              "operation table, against 256 CUs x 64 lanes x 2.4 GHz"},
     }
-    fp32_rate(line["roofline"], "cornell", head["kernel_ms"])
+    fp32_rate(line["roofline"], "large", head["kernel_ms"])
     extra = {}
     if not args.no_extra:
-        s3, r3 = workloads.large_config()
-        big = forward_form(s3, r3, max(2, args.steps // 25), 1, tune_name="large-512-1024spp")
-        extra["fwd_large"] = {k: big[k] for k in ("vertices", "ms_per_step", "vertices_per_s")}
+        s2, r2 = workloads.cornell_config()
+        co = forward_form(s2, r2, max(20, args.steps * 5), 5, tune_name="cornell-128-64spp")
+        extra["fwd_cornell"] = form_summary(co, "cornell")
         if not args.no_cpu_baseline:
-            extra["fwd_large"]["cpu_oracle"] = oracle_sample(s3, r3)
-        extra["fwd_large"]["alu_frac"] = alu_frac(big)
-        hbm_rate(extra["fwd_large"], "large", big["kernel_ms"])
-        fp32_rate(extra["fwd_large"], "large", big["kernel_ms"])
+            extra["fwd_cornell"]["cpu_oracle"] = oracle_sample(s2, r2)
         s1, r1 = workloads.slab_config()
         r1 = dict(r1, path_count=1 << 22, total_paths=1 << 22)
-        sl = forward_form(s1, r1, max(5, args.steps // 5), 2, tune_name="slab-2^22")
-        extra["fwd_slab_2^22"] = {k: sl[k] for k in ("vertices", "ms_per_step", "vertices_per_s")}
+        sl = forward_form(s1, r1, max(10, args.steps * 2), 2, tune_name="slab-2^22")
+        extra["fwd_slab_2^22"] = form_summary(sl, "slab")
         if not args.no_cpu_baseline:
             extra["fwd_slab_2^22"]["cpu_oracle"] = oracle_sample(s1, r1)
-        extra["fwd_slab_2^22"]["alu_frac"] = alu_frac(sl)
-        hbm_rate(extra["fwd_slab_2^22"], "slab", sl["kernel_ms"])
-        fp32_rate(extra["fwd_slab_2^22"], "slab", sl["kernel_ms"])
         # the same slab behind a water boundary (n = 1.33): Fresnel reflection
         # and total internal reflection at both faces
         s1w = workloads.deepcopy(s1)
         s1w["media"][0]["ior"] = 1.33
-        sw = forward_form(s1w, r1, max(5, args.steps // 5), 2, tune_name="slab-2^22")
-        extra["fwd_slab_water_2^22"] = {k: sw[k] for k in ("vertices", "ms_per_step", "vertices_per_s")}
-        extra["fwd_slab_water_2^22"]["alu_frac"] = alu_frac(sw)
+        sw = forward_form(s1w, r1, max(10, args.steps * 2), 2, tune_name="slab-2^22")
+        extra["fwd_slab_water_2^22"] = form_summary(sw, "slab_water")
         extra["fwd_slab_water_2^22"]["boundary_reflections"] = sw["tallies"]["wall_reflect"]
         try:
-            extra["fwd_adjoint"] = adjoint_form(max(3, args.steps // 10), 1)
+            extra["fwd_adjoint"] = adjoint_form(max(3, args.steps), 1)
             fp32_rate(extra["fwd_adjoint"], "adjoint", extra["fwd_adjoint"]["ms_per_step"])
             if not args.no_cpu_baseline:
                 sa, ra = workloads.adjoint_config()[:2]
                 extra["fwd_adjoint"]["cpu_oracle"] = oracle_sample(sa, ra, grad=True)
         except Exception as e:  # reported, not hidden
             extra["fwd_adjoint"] = {"error": str(e)}
-        b = batched_form(max(3, args.steps // 10), 1)
+        b = batched_form(max(3, args.steps), 1)
         if b is not None:
             extra["batched"] = b
             if not args.no_cpu_baseline:
                 b["cpu_oracle"] = batch_oracle_sample(*workloads.batch_config())
             hbm_rate(b, "batched", b["ms_per_step"])
             fp32_rate(b, "batched", b["ms_per_step"])
-        extra["excitation_scan"] = sweep_form(max(3, args.steps // 5), 1)
-        extra["camera_side"] = camera_form(max(3, args.steps // 5), 1, cpu=not args.no_cpu_baseline)
+        extra["excitation_scan"] = sweep_form(max(3, args.steps * 2), 1)
+        extra["camera_side"] = camera_form(max(3, args.steps * 2), 1, cpu=not args.no_cpu_baseline)
         hbm_rate(extra["camera_side"], "camera", extra["camera_side"]["kernel_ms"])
         fp32_rate(extra["camera_side"], "camera", extra["camera_side"]["kernel_ms"])
     line["forms"] = extra

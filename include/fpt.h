@@ -289,6 +289,12 @@ int32_t fpt_scene_set_tune(fpt_scene* scene, const fpt_tune* tune);
 #define FPT_MAX_TIMED_RENDERS 4096
 int32_t fpt_scene_set_timing(fpt_scene* scene, int32_t enable);
 int32_t fpt_scene_timing(fpt_scene* scene, int32_t* renders, float* transport_ms, float* deferred_ms);
+/* The same record render by render: waits for the recorded renders, writes
+ * their count to *renders and the durations in ms of the first
+ * min(count, cap) of them to transport_ms[] and deferred_ms[] (host arrays of
+ * cap floats, may be NULL when cap is 0), and clears the record. */
+int32_t fpt_scene_timing_each(fpt_scene* scene, int32_t cap, int32_t* renders, float* transport_ms,
+                              float* deferred_ms);
 
 /* Forward render: the analog walk of sec. 4.1 from the light, every path an
  * unbiased sample of the fluorescent RTE (eqs. 1-2 with the inelastic kernel

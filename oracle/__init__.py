@@ -279,15 +279,23 @@ def _ptr(a):
 
 
 def render(scene, run, film=True, grad_film=None, records=False, record_grad=False,
-           max_vertices=0):
+           max_vertices=0, film_out=None):
     """Run the oracle walk.  Returns a dict with 'film' (fp64, film_shape),
-    'tallies' (uint64[20]), optionally 'grad', 'records', 'record_grad'."""
+    'tallies' (uint64[20]), optionally 'grad', 'records', 'record_grad'.
+    film_out: a C-contiguous fp64 array of the film's shape to accumulate into
+    (returned as 'film') instead of a new zeroed film."""
     L = lib()
     sc = make_scene(scene)
     ru = make_run(run)
     B = max(1, run["parity_batches"])
     out = {}
-    f = np.zeros(film_shape(scene, B), np.float64) if film else None
+    if film_out is not None:
+        if (film_out.dtype != np.float64 or not film_out.flags.c_contiguous
+                or film_out.shape != film_shape(scene, B)):
+            raise OracleError("film_out must be a C-contiguous float64 array of the film's shape")
+        f = film_out
+    else:
+        f = np.zeros(film_shape(scene, B), np.float64) if film else None
     t = np.zeros(N_TALLIES, np.uint64)
     g = None
     gf = None

@@ -139,6 +139,7 @@ def lib():
         "fpt_scene_set_tune": (C.c_int32, [vp, C.POINTER(Tune)]),
         "fpt_scene_set_timing": (C.c_int32, [vp, C.c_int32]),
         "fpt_scene_timing": (C.c_int32, [vp, C.POINTER(C.c_int32), C.POINTER(C.c_float), C.POINTER(C.c_float)]),
+        "fpt_scene_timing_each": (C.c_int32, [vp, C.c_int32, C.POINTER(C.c_int32), vp, vp]),
         "fpt_render": (C.c_int32, [vp, C.POINTER(Run), vp, vp, vp]),
         "fpt_render_noalloc": (C.c_int32, [vp, C.POINTER(Run), vp, vp, vp]),
         "fpt_render_adjoint": (C.c_int32, [vp, C.POINTER(Run), vp, vp, vp, vp]),

@@ -955,22 +955,37 @@ int32_t fpt_scene_set_timing(fpt_scene* sc, int32_t enable) {
     return FPT_OK;
 }
 
-int32_t fpt_scene_timing(fpt_scene* sc, int32_t* renders, float* transport_ms, float* deferred_ms) {
-    if (!sc || !renders || !transport_ms || !deferred_ms) return set_err(FPT_E_INVALID, "NULL argument");
-    double t = 0.0, d = 0.0;
+int32_t fpt_scene_timing_each(fpt_scene* sc, int32_t cap, int32_t* renders, float* transport_ms,
+                              float* deferred_ms) {
+    if (!sc || !renders || (cap > 0 && (!transport_ms || !deferred_ms)) || cap < 0)
+        return set_err(FPT_E_INVALID, "NULL argument");
+    const int n = std::min(sc->timed, cap);
     for (int k = 0; k < sc->timed; ++k) {
         hipEvent_t* ev = &sc->events[(size_t)k * 3];
         HIP_TRY(hipEventSynchronize(ev[2]), "hipEventSynchronize");
-        float a = 0.f, b = 0.f;
-        HIP_TRY(hipEventElapsedTime(&a, ev[0], ev[1]), "hipEventElapsedTime");
-        HIP_TRY(hipEventElapsedTime(&b, ev[1], ev[2]), "hipEventElapsedTime");
-        t += a;
-        d += b;
+        if (k >= n) continue;
+        HIP_TRY(hipEventElapsedTime(&transport_ms[k], ev[0], ev[1]), "hipEventElapsedTime");
+        HIP_TRY(hipEventElapsedTime(&deferred_ms[k], ev[1], ev[2]), "hipEventElapsedTime");
     }
     *renders = sc->timed;
-    *transport_ms = sc->timed ? (float)(t / sc->timed) : 0.f;
-    *deferred_ms = sc->timed ? (float)(d / sc->timed) : 0.f;
     sc->timed = 0;
+    return FPT_OK;
+}
+
+int32_t fpt_scene_timing(fpt_scene* sc, int32_t* renders, float* transport_ms, float* deferred_ms) {
+    if (!sc || !renders || !transport_ms || !deferred_ms) return set_err(FPT_E_INVALID, "NULL argument");
+    std::vector<float> t((size_t)std::max(1, sc->timed)), d((size_t)std::max(1, sc->timed));
+    int32_t n = 0;
+    int32_t rc = fpt_scene_timing_each(sc, sc->timed, &n, t.data(), d.data());
+    if (rc != FPT_OK) return rc;
+    double st = 0.0, sd = 0.0;
+    for (int k = 0; k < n; ++k) {
+        st += t[k];
+        sd += d[k];
+    }
+    *renders = n;
+    *transport_ms = n ? (float)(st / n) : 0.f;
+    *deferred_ms = n ? (float)(sd / n) : 0.f;
     return FPT_OK;
 }
 

@@ -107,6 +107,16 @@ class Scene:
         check(lib().fpt_scene_timing(self._h, C.byref(n), C.byref(t), C.byref(d)))
         return n.value, t.value, d.value
 
+    def timing_each(self, cap=4096):
+        """fpt_scene_timing_each: (transport ms, deferred ms) arrays, one entry
+        per timed render."""
+        t = np.zeros(cap, np.float32)
+        d = np.zeros(cap, np.float32)
+        n = C.c_int32()
+        check(lib().fpt_scene_timing_each(self._h, cap, C.byref(n), t.ctypes.data, d.ctypes.data))
+        k = min(n.value, cap)
+        return t[:k].astype(np.float64), d[:k].astype(np.float64)
+
     def tables(self):
         d = self.desc
         N = d["grid"]["n_bins"]
