@@ -42,6 +42,7 @@ STEP = PHILOX + 6      # free flight: log, scale, position update
 START = 2 * PHILOX + 25  # light vertex: line choice, point and direction on the quad
 EMISSION = PHILOX + 17   # quantum-yield test, emission CDF inversion
 CAM_START = PHILOX + 90  # camera-side path: pixel of the path index, pixel sample, eye ray, box entry
+OPAQUE = 32              # connection opaque in its own sphere: eye direction, sphere exit, test
 
 
 # Algorithmic FP32 work per event (an FMA counts 2, a transcendental, compare
@@ -56,6 +57,9 @@ FL_SURFACE = 17           # reaching an interface, wall, the light or the open f
 FL_REFLECT = 19           # wall or Fresnel reflection: hit plus a new direction
 FL_CONN = 38              # camera connection: distance, projection, cosines, exp
 FL_CONN_SPHERE = 20       # + one chord per sphere
+FL_CONN_OPAQUE = 30       # a connection opaque inside the vertex's own sphere: direction
+                          # to the eye and that sphere's exit distance (no image tests,
+                          # other chords or exp: the kernel resolves it with these)
 
 
 def flops_model(t, n_spheres, geometry):
@@ -68,7 +72,8 @@ def flops_model(t, n_spheres, geometry):
                             + t["exit_esc_t"])
             + FL_REFLECT * t["wall_reflect"]
             + (FL_CONN + FL_CONN_SPHERE * n_spheres) * (t["splat_hit"] + t["splat_miss"]
-                                                        + t["splat_rr_kill"]))
+                                                        + t["splat_rr_kill"] - t.get("splat_opaque", 0))
+            + FL_CONN_OPAQUE * t.get("splat_opaque", 0))
 
 
 def ops_model(t, n_spheres, geometry, refractive=False):
@@ -79,12 +84,14 @@ def ops_model(t, n_spheres, geometry, refractive=False):
     if open_geo and refractive:
         surface += 30   # boundary normal, Fresnel reflectance, mirror
     conn = 118 + 21 * n_spheres                          # camera connection and transmittance
+    opaque = t.get("splat_opaque", 0)                    # resolved inside the own sphere
     return (START * t["paths"]
             + (STEP + medium) * (t["scatters"] + t["dye_abs"] + t["exit_bg"])
             + (STEP + surface) * (t["crossings"] + t["wall_reflect"] + t["exit_wall"] + t["exit_light"]
                                   + t["exit_esc_r"] + t["exit_esc_t"])
             + EMISSION * (t["emissions"] + t["exit_nonrad"])
-            + conn * (t["splat_hit"] + t["splat_miss"] + t["splat_rr_kill"]))
+            + conn * (t["splat_hit"] + t["splat_miss"] + t["splat_rr_kill"] - opaque)
+            + OPAQUE * opaque)
 
 
 def camera_ops(t, n_spheres, n_lines):

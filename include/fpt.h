@@ -49,7 +49,7 @@
 extern "C" {
 #endif
 
-#define FPT_ABI_VERSION 4u
+#define FPT_ABI_VERSION 5u
 
 typedef enum {
     FPT_OK = 0,
@@ -68,7 +68,7 @@ typedef enum {
 #define FPT_MAX_LINES 8
 #define FPT_MAX_BINS 1024
 #define FPT_MAX_GRAD_PARAMS 16
-#define FPT_N_TALLIES 20
+#define FPT_N_TALLIES 21
 
 enum { FPT_SPECTRUM_NONE = 0, FPT_SPECTRUM_GAUSS_MIX = 1, FPT_SPECTRUM_PIECEWISE_LINEAR = 2,
        FPT_SPECTRUM_TABULATED = 3 };
@@ -90,7 +90,13 @@ enum { FPT_EXIT_ESC_R = 0, FPT_EXIT_ESC_T = 1, FPT_EXIT_BG = 2, FPT_EXIT_NONRAD 
 enum { FPT_T_PATHS = 0, FPT_T_VERTICES = 1, FPT_T_SCATTERS = 2, FPT_T_DYE_ABS = 3,
        FPT_T_EMISSIONS = 4, FPT_T_WALL_REFLECT = 5, FPT_T_CROSSINGS = 6,
        FPT_T_SPLAT_HIT = 7, FPT_T_SPLAT_MISS = 8, FPT_T_SPLAT_RR_KILL = 9,
-       FPT_T_EXIT0 = 10 /* + exit code */ };
+       FPT_T_EXIT0 = 10 /* + exit code */,
+       /* forward renders: connections from a medium vertex whose optical depth
+          inside its own sphere alone makes the transmittance exactly 0 in fp32,
+          resolved without evaluation where every point of that sphere passes the
+          connection's geometric tests (they are also counted in SPLAT_HIT, or in
+          SPLAT_RR_KILL when splat_rr > 0, as an evaluation would count them) */
+       FPT_T_SPLAT_OPAQUE = 20 };
 
 /* A spectrum on nm: a Gaussian mixture sum_i value_i exp(-(l-center_i)^2/(2 width_i^2)),
  * a piecewise-linear curve through (center_i, value_i), constant beyond the ends, or

@@ -22,7 +22,7 @@ MAX_SPHERES = 8
 MAX_LINES = 8
 MAX_BINS = 1024
 MAX_GRAD_PARAMS = 16
-N_TALLIES = 20
+N_TALLIES = 21
 
 OK, E_INVALID, E_RANGE, E_NOMEM, E_DEVICE, E_UNSUPPORTED = 0, -1, -2, -3, -4, -5
 SPECTRUM_GAUSS_MIX, SPECTRUM_PIECEWISE_LINEAR, SPECTRUM_TABULATED = 1, 2, 3
@@ -36,7 +36,7 @@ EXIT_NAMES = ["esc_r", "esc_t", "bg", "nonrad", "kcap", "scap", "wall", "light",
               "trunc"]
 TALLY_NAMES = ["paths", "vertices", "scatters", "dye_abs", "emissions", "wall_reflect",
                "crossings", "splat_hit", "splat_miss", "splat_rr_kill"] + \
-              ["exit_" + n for n in EXIT_NAMES]
+              ["exit_" + n for n in EXIT_NAMES] + ["splat_opaque"]
 
 
 class FptError(RuntimeError):
@@ -112,7 +112,7 @@ class PathRecord(C.Structure):
 
 
 RECORD_WORDS = C.sizeof(PathRecord) // 4
-ABI_VERSION = 4
+ABI_VERSION = 5
 TUNE_FORCE, TUNE_CACHED_ONLY = 1, 2
 
 _lib = None

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -299,6 +300,88 @@ uint32_t fbits(float f) {
 }
 
 // Builds the fp32 table image and the scene part of the kernel parameters.
+// Spheres whose every point passes a pinhole connection's geometric tests,
+// with a margin far above fp32 rounding, and whose medium can reach an optical
+// depth of kTauZero inside them (bit s of the result): the kernels may count a
+// connection from such a sphere that is opaque within the sphere itself as a
+// zero-valued hit without evaluating it.  A ball of centre c and radius r
+// passes when it lies inside each of these half-spaces through the eye with
+// clearance r (1 + 1e-3) + 1e-4 mm:
+//   - in front of the camera and inside the image: the planes through the eye
+//     of the image's four edges (fov);
+//   - through the open face: the planes through the eye and the face's four
+//     edges (the segment to the eye then crosses the face's plane inside it);
+// and when the ball and the eye lie strictly on the same side of the light
+// quad's plane (the segment cannot cross the quad).
+uint32_t clear_spheres(const fpt_scene_desc& d, const std::vector<float>& st) {
+    auto dot = [](const double* a, const double* b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; };
+    auto unit = [](double* v) {
+        const double n = std::sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+        for (int i = 0; i < 3; ++i) v[i] /= n;
+    };
+    double f[3] = {d.look[0] - d.eye[0], d.look[1] - d.eye[1], d.look[2] - d.eye[2]}, r[3], u[3];
+    unit(f);
+    cross3(f, d.up, r);
+    unit(r);
+    cross3(r, f, u);
+    const double ty = std::tan(0.5 * d.fov_y_deg * M_PI / 180.0), tx = ty * d.width / d.height;
+    // inward normals of the half-spaces through the eye
+    std::vector<std::array<double, 3>> planes;
+    for (int sg = -1; sg <= 1; sg += 2) {
+        std::array<double, 3> a, b;
+        for (int i = 0; i < 3; ++i) {
+            a[i] = tx * f[i] + sg * r[i];
+            b[i] = ty * f[i] + sg * u[i];
+        }
+        planes.push_back(a);
+        planes.push_back(b);
+    }
+    const int ax = d.open_face >> 1;
+    const double plane = (d.open_face & 1) ? d.box_hi[ax] : d.box_lo[ax];
+    double mid[3];
+    for (int i = 0; i < 3; ++i) mid[i] = 0.5 * (d.box_lo[i] + d.box_hi[i]);
+    mid[ax] = plane;
+    for (int k = 1; k <= 2; ++k) {
+        const int a1 = (ax + k) % 3, a2 = (ax + 3 - k) % 3;  // edge across a1, running along a2
+        for (int side = 0; side < 2; ++side) {
+            double p0[3] = {0.0, 0.0, 0.0}, e2[3] = {0.0, 0.0, 0.0}, v[3], n[3];
+            p0[ax] = plane;
+            p0[a1] = side ? d.box_hi[a1] : d.box_lo[a1];
+            e2[a2] = 1.0;
+            for (int i = 0; i < 3; ++i) v[i] = p0[i] - d.eye[i];
+            cross3(e2, v, n);
+            double m[3] = {mid[0] - d.eye[0], mid[1] - d.eye[1], mid[2] - d.eye[2]};
+            if (dot(n, m) < 0.0)
+                for (double& c : n) c = -c;
+            planes.push_back({n[0], n[1], n[2]});
+        }
+    }
+    double ln[3] = {0.0, 0.0, 0.0};
+    cross3(d.light_u, d.light_v, ln);
+    unit(ln);
+    uint32_t bits = 0u;
+    for (int s = 0; s < d.n_spheres; ++s) {
+        const fpt_sphere& sp = d.spheres[s];
+        const double rad = sp.radius, clear = rad * (1.0 + 1e-3) + 1e-4;
+        float stmax = 0.f;
+        for (int k = 0; k < d.n_bins; ++k) stmax = std::max(stmax, st[(size_t)sp.medium * d.n_bins + k]);
+        if (!((double)stmax * 2.0 * rad >= (double)kTauZero)) continue;
+        double c[3] = {sp.center[0] - d.eye[0], sp.center[1] - d.eye[1], sp.center[2] - d.eye[2]};
+        bool ok = dot(c, f) >= clear;
+        for (const auto& pl : planes) {
+            double n[3] = {pl[0], pl[1], pl[2]};
+            unit(n);
+            ok = ok && dot(c, n) >= clear;
+        }
+        double qc[3] = {sp.center[0] - d.light_pos[0], sp.center[1] - d.light_pos[1], sp.center[2] - d.light_pos[2]};
+        double qe[3] = {d.eye[0] - d.light_pos[0], d.eye[1] - d.light_pos[1], d.eye[2] - d.light_pos[2]};
+        const double sc_ = dot(ln, qc), se = dot(ln, qe);
+        ok = ok && sc_ * se > 0.0 && std::fabs(sc_) >= clear && std::fabs(se) >= 1e-4;
+        if (ok) bits |= 1u << s;
+    }
+    return bits;
+}
+
 int32_t build_tables(fpt_scene* sc) {
     const fpt_scene_desc& d = sc->desc;
     const int N = d.n_bins;
@@ -548,6 +631,7 @@ int32_t build_tables(fpt_scene* sc) {
         P.splat_norm = (float)((double)d.width * d.height / (4.0 * tx * ty));
     }
     P.np = np;
+    P.sph_clear = cam ? clear_spheres(d, sc->h_st) : 0u;
     return FPT_OK;
 }
 

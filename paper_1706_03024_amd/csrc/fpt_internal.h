@@ -85,7 +85,15 @@ struct KParams {
     int off_csig;   // float [n_spheres][n_lines]: sigma_t of sphere s's medium at line l
     float tanx, tany;
     float ior;  // refractive index of the body medium (1: index-matched boundary)
+    // bit s: every point of sphere s passes a camera connection's geometric
+    // tests (in the image, through the open face, clear of the light quad) with
+    // margin, and its medium can reach an optical depth of kTauZero inside it
+    uint32_t sph_clear;
 };
+
+// Optical depth past which a transmittance is exactly 0 in fp32: exp(-103.3)
+// is already below the smallest subnormal.
+constexpr float kTauZero = 110.f;
 
 struct KBuffers {
     const uint32_t* tables;        // table image in device memory

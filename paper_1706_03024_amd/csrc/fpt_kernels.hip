@@ -23,7 +23,6 @@ namespace fpt {
 constexpr float kInf = __builtin_inff();
 constexpr uint32_t kMaxPathVertices = 1u << 28;
 constexpr int kBlockPasses = 4;   // block passes per iteration for paths that never stop
-constexpr float kTauZero = 110.f;  // exp(-110) = 1.7e-48 rounds to 0 in fp32
 constexpr int kLdsSpheres = 32;
 constexpr int kQueueShards = 64;   // path-queue heads (see k_transport)
 constexpr int kShardStride = 16;   // u64 words between heads: separate 128-byte lines                                // word offset of the sphere table
@@ -303,6 +302,23 @@ DEV KParamsArg kernel_params() {
     return p;
 }
 
+// A medium vertex whose connection to the eye would cross an optical depth of
+// at least kTauZero inside its own sphere alone has a transmittance of exactly
+// 0 in fp32: the splat deposits nothing, whatever the other spheres on the way
+// add.  Where the host has shown that every point of that sphere passes the
+// connection's geometric tests (P.sph_clear), its outcome is also known -- a
+// hit of value 0, or a roulette kill when splat_rr > 0 -- so it is counted
+// without being queued and evaluated (about a third of the large scene's
+// connections, from deep inside its densest spheres).
+DEV bool opaque_to_eye(const float* x, int region, float st, const float* sc, float sr2) {
+    const auto& K = *kernel_params();
+    if (region < 0 || !((K.sph_clear >> (uint32_t)region) & 1u)) return false;
+    const float d0 = K.eye[0] - x[0], d1 = K.eye[1] - x[1], d2 = K.eye[2] - x[2];
+    const float ri = __builtin_amdgcn_rsqf(d0 * d0 + d1 * d1 + d2 * d2);
+    const float wc[3] = {d0 * ri, d1 * ri, d2 * ri};
+    return st * sphere_exit(x, wc, sc, sr2) >= kTauZero;
+}
+
 // -------------------------------------------------------------------------
 // Pinhole splat at a realised vertex (eqs. 3-6).  Returns the deposited value
 // (0 if rejected) and the film index; chord lengths go to `chord` for the
@@ -365,11 +381,22 @@ DEV SplatOut splat_eval(const uint32_t* S, const KSphere* SP, const float* x, in
         ok = ok && !blocked;
     }
     // transmittance along the connection, through every sphere (eq. 6); past an
-    // optical depth of 110 it is exactly 0 in fp32
+    // optical depth of kTauZero it is exactly 0 in fp32.  A sphere that no lane's
+    // connection line meets adds nothing and is skipped by the whole wave.
     float tau = 0.f;
 #pragma unroll
-    for (int s = 0; s < FPT_MAX_SPHERES; ++s)
-        if (s < P.n_spheres) tau += wf(S, SP[s].st_row + 2 * lam) * chord_len(SP[s], x, wc, dist);
+    for (int s = 0; s < FPT_MAX_SPHERES; ++s) {
+        if (s >= P.n_spheres) continue;
+        const float o0 = x[0] - SP[s].c[0], o1 = x[1] - SP[s].c[1], o2 = x[2] - SP[s].c[2];
+        const float b = o0 * wc[0] + o1 * wc[1] + o2 * wc[2];
+        const float p0 = o0 - b * wc[0], p1 = o1 - b * wc[1], p2 = o2 - b * wc[2];
+        const float disc = SP[s].r2 - (p0 * p0 + p1 * p1 + p2 * p2);
+        if (!__builtin_amdgcn_ballot_w64(disc > 0.f)) continue;
+        const float sq = fsqrt(fmaxf(disc, 0.f));
+        const float lo = fmaxf(-b - sq, 0.f), hi = fminf(-b + sq, dist);
+        const float len = disc > 0.f ? fmaxf(hi - lo, 0.f) : 0.f;
+        tau += wf(S, SP[s].st_row + 2 * lam) * len;
+    }
     const float tr = tau < kTauZero ? __expf(-tau) : 0.f;
     const float cosc = zc * rdist;
     float v = P.wscale * f * tr * P.splat_norm * __builtin_amdgcn_rcpf(cosc * cosc * cosc * dist2);
@@ -393,6 +420,22 @@ struct Counters {
 };
 
 DEV void lds_count(uint32_t* tally, int slot) { atomicAdd(&tally[slot], 1u); }
+
+// Tallies of the lanes' connections known to deposit exactly 0
+// (opaque_to_eye): the outcome splat_eval would give them, a hit or with
+// splat_rr > 0 a roulette kill, and the count of such connections.  Called by
+// the whole wave.
+DEV void count_opaque(uint32_t* tally, Counters& cnt, bool opaque) {
+    const uint64_t m = __ballot(opaque);
+    if (!m) return;
+    const bool rr = kernel_params()->splat_rr > 0.f;
+    if (opaque && !rr) cnt.splat_hit++;
+    if (lane_id() == (uint32_t)(__ffsll((unsigned long long)m) - 1)) {
+        const uint32_t n = (uint32_t)__popcll(m);
+        atomicAdd(&tally[FPT_T_SPLAT_OPAQUE], n);
+        if (rr) atomicAdd(&tally[FPT_T_SPLAT_RR_KILL], n);
+    }
+}
 
 DEV void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -784,10 +827,14 @@ DEV void block_walk(const KParams& P, const KBuffers& B, const uint32_t* T, cons
         inv_ss = wf(T, mb + MW_INV_SS);
     }
     if constexpr (GEOM == FPT_GEOM_BOX && MODE == MODE_FWD) {
-        if (pinhole)
-            splat_defer(B, q, mine && !(P.fluo_only && Q.comp == 0), Lk.x,
-                        sq_word_a(rr_bits(r), PEND_MEDIUM, 0, Q.comp), (uint32_t)Q.lam | (Q.batch << 16),
-                        exhausted);
+        if (pinhole) {
+            bool want = mine && !(P.fluo_only && Q.comp == 0);
+            const bool opq = want && opaque_to_eye(Lk.x, Q.region, Q.st, Q.sc, Q.sr2);
+            count_opaque(tally, cnt, opq);
+            want = want && !opq;
+            splat_defer(B, q, want, Lk.x, sq_word_a(rr_bits(r), PEND_MEDIUM, 0, Q.comp),
+                        (uint32_t)Q.lam | (Q.batch << 16), exhausted);
+        }
     } else if constexpr (GEOM == FPT_GEOM_BOX) {
         if (pinhole && mine && !(P.fluo_only && Q.comp == 0)) {
             const float zero3[3] = {0.f, 0.f, 0.f};
@@ -957,6 +1004,7 @@ DEV void deep_round(const KParams& P, const KBuffers& B, const uint32_t* T, cons
     Q.inv = rl(L.inv, j);
     Q.ss = rl(L.ss, j);
     Q.lam = rli(L.lam, j);
+    Q.region = rli(L.region, j);
     Q.comp = rli(L.comp, j);
     Q.pid = rlu(L.pid, j);
     Q.v = rlu(L.v, j);
@@ -979,11 +1027,16 @@ DEV void deep_round(const KParams& P, const KBuffers& B, const uint32_t* T, cons
         if (pinhole) {
             const bool dep = !(P.fluo_only && Q.comp == 0);
             const uint32_t wb = (uint32_t)Q.lam | (Q.batch << 16);
-            splat_defer(B, q, m1 && dep, x1, sq_word_a(__float_as_uint(x1[3]), PEND_MEDIUM, 0, Q.comp), wb,
-                        exhausted);
+            const bool o1 = m1 && dep && opaque_to_eye(x1, Q.region, Q.st, Q.sc, Q.sr2);
+            count_opaque(tally, cnt, o1);
+            const bool w1 = m1 && dep && !o1;
+            splat_defer(B, q, w1, x1, sq_word_a(__float_as_uint(x1[3]), PEND_MEDIUM, 0, Q.comp), wb, exhausted);
             sq_drain(P, B.film, T, SP, tally, q, cnt, lane, false);
             if (k2 > 0) {
-                splat_defer(B, q, m2 && dep, x2, sq_word_a(__float_as_uint(x2[3]), PEND_MEDIUM, 0, Q.comp), wb,
+                const bool o2 = m2 && dep && opaque_to_eye(x2, Q.region, Q.st, Q.sc, Q.sr2);
+                count_opaque(tally, cnt, o2);
+                const bool w2 = m2 && dep && !o2;
+                splat_defer(B, q, w2, x2, sq_word_a(__float_as_uint(x2[3]), PEND_MEDIUM, 0, Q.comp), wb,
                             exhausted);
             }
         }
@@ -1414,10 +1467,14 @@ DEV void advance(const KParams& P, const KBuffers& B, const WaveCtx& C, WalkStat
 
     // ---- convergent splat section
     if constexpr (DEFER) {
-        if (pinhole)
-            splat_defer(B, W.q, pend != PEND_NONE && alive && exit_code < 0 && !(P.fluo_only && L.comp == 0),
-                        L.x, sq_word_a(rrb, pend, W.face, L.comp), (uint32_t)L.lam | (L.batch << 16),
-                        exhausted);
+        if (pinhole) {
+            bool want = pend != PEND_NONE && alive && exit_code < 0 && !(P.fluo_only && L.comp == 0);
+            const bool opq = want && pend == PEND_MEDIUM && opaque_to_eye(L.x, L.region, L.st, L.sc, L.sr2);
+            count_opaque(tally, cnt, opq);
+            want = want && !opq;
+            splat_defer(B, W.q, want, L.x, sq_word_a(rrb, pend, W.face, L.comp),
+                        (uint32_t)L.lam | (L.batch << 16), exhausted);
+        }
     } else if constexpr (GEOM == FPT_GEOM_BOX) {
         if (pinhole && pend != PEND_NONE && alive && exit_code < 0) {
             if (!(P.fluo_only && L.comp == 0)) {

@@ -29,7 +29,7 @@ def test_library_exports_every_declared_symbol():
     assert len(syms) >= 17
     for s in syms:
         assert hasattr(L, s), s
-    assert L.fpt_abi_version() == _abi.ABI_VERSION == 4
+    assert L.fpt_abi_version() == _abi.ABI_VERSION == 5
     assert L.fpt_status_str(-3) == b"out of memory"
 
 

@@ -311,7 +311,7 @@ def test_large_scene_forward_film():
     bin by bin with the oracle's film of independent paths (batch-mean z per
     film cell, per pixel summed over wavelength, and per 10-bin band summed
     over the image); on the same paths its total equals the sum of the
-    replayed records' deposits."""
+    replayed records' deposits and its integer tallies the oracle's."""
     import torch
     fpt = _fpt()
     from paper_1706_03024_amd import autotune
@@ -329,6 +329,23 @@ def test_large_scene_forward_film():
     total = float(film.double().sum())
     sc.close()
     assert abs(total - float(rec["splat_sum"].astype(np.float64).sum())) <= 1e-4 * total
+    # same paths on both sides: the integer tallies agree up to marginal paths,
+    # among them the connections the kernel counts without evaluating (zero
+    # transmittance inside the vertex's own sphere: hits, or roulette kills)
+    fpt_sc = fpt.Scene(scene)
+    for rr in (0.0, 0.05):
+        small = workloads.make_run(1 << 16, seed=34, splat_rr=rr)
+        tg = fpt.new_tallies()
+        fpt_sc.render(small, tallies=tg)
+        torch.cuda.synchronize()
+        tg = fpt.tallies_dict(tg)
+        to = oracle.tallies_dict(oracle.render(scene, small)["tallies"])
+        for k in ("vertices", "splat_hit", "splat_miss", "splat_rr_kill", "emissions"):
+            assert abs(tg[k] - to[k]) <= max(8, 1e-4 * to[k]), (rr, k, tg[k], to[k])
+        assert to["splat_hit"] > 0 and (rr == 0.0 or to["splat_rr_kill"] > 0)
+        # a third of the connections start deep inside the densest spheres
+        assert tg["splat_opaque"] > 0.2 * (tg["splat_hit"] + tg["splat_rr_kill"])
+    fpt_sc.close()
     o = oracle.render(scene, workloads.make_run(1 << 21, seed=32, parity_batches=B))["film"]
     z = batch_z(g, o)
     assert z.size > 1000
