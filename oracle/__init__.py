@@ -74,7 +74,7 @@ class Scene(C.Structure):
         ("line_power", C.c_double * MAX_LINES),
         ("sensor", C.c_int32), ("eye", C.c_double * 3), ("look", C.c_double * 3),
         ("up", C.c_double * 3), ("fov_y_deg", C.c_double), ("width", C.c_int32),
-        ("height", C.c_int32),
+        ("height", C.c_int32), ("wall_gloss", C.c_double * 6),
     ]
 
 
@@ -125,6 +125,11 @@ def lib():
         L.orc_tables.argtypes = [C.POINTER(Scene)] + [C.c_void_p] * 8
         L.orc_philox4x32_10.restype = None
         L.orc_philox4x32_10.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
+        L.orc_phong_eval.restype = C.c_double
+        L.orc_phong_eval.argtypes = [C.c_double, C.c_void_p, C.c_void_p, C.c_void_p]
+        L.orc_phong_sample.restype = C.c_double
+        L.orc_phong_sample.argtypes = [C.c_double, C.c_void_p, C.c_void_p, C.c_double, C.c_double,
+                                       C.c_void_p]
         _lib = L
     return _lib
 
@@ -201,6 +206,7 @@ def make_scene(d):
         sc.open_face = geo["open_face"]
         for f, w in enumerate(geo["walls"]):
             _spectrum(sc.walls[f], w, keep)
+        sc.wall_gloss[:] = geo.get("wall_gloss", [0.0] * 6)
         sc.n_spheres = len(geo["spheres"])
         for i, sp in enumerate(geo["spheres"]):
             sc.spheres[i].center[:] = sp["center"]
@@ -376,6 +382,21 @@ def replay_condition(scene, run, max_vertices=0, grad_film=None, camera=False,
             k = np.where(d == 0, 0.0, d / (eta * np.maximum(a, 1e-300)))
             out["kappa_grad"] = np.maximum(out["kappa_grad"], k)
     return out
+
+
+def phong_eval(n, wi, wo, nrm):
+    """The glossy wall lobe over rho, (n+2)/(2 pi) cos^n(alpha) (test hook)."""
+    a = [np.ascontiguousarray(v, np.float64) for v in (wi, wo, nrm)]
+    return lib().orc_phong_eval(float(n), *[x.ctypes.data for x in a])
+
+
+def phong_sample(n, wi, nrm, ua, ub):
+    """A direction drawn from the glossy lobe and its throughput factor (test hook)."""
+    a = [np.ascontiguousarray(v, np.float64) for v in (wi, nrm)]
+    wo = np.zeros(3)
+    f = lib().orc_phong_sample(float(n), a[0].ctypes.data, a[1].ctypes.data, float(ua), float(ub),
+                               wo.ctypes.data)
+    return wo, f
 
 
 def camera_paths(scene, spp):

@@ -170,8 +170,12 @@ static int validate(const orc_scene* sc) {
     if (!(tot > 0.0)) return fail("total light power is 0");
     if (sc->geom == ORC_GEOM_BOX) {
         if (sc->light != ORC_LIGHT_QUAD) return fail("box scenes need a quad light");
-        for (int f = 0; f < 6; ++f)
+        for (int f = 0; f < 6; ++f) {
             if (f != sc->open_face && check_spectrum(&sc->walls[f], 0, sc->n_bins)) return -1;
+            if (!(sc->wall_gloss[f] >= 0.0 && sc->wall_gloss[f] <= 1e4)) return fail("wall gloss outside [0, 1e4]");
+            if (sc->wall_gloss[f] > 0.0 && sc->sensor != ORC_SENSOR_PINHOLE)
+                return fail("glossy walls need a pinhole sensor");
+        }
         if (sc->n_spheres < 0 || sc->n_spheres > ORC_MAX_SPHERES) return fail("n_spheres");
         for (int s = 0; s < sc->n_spheres; ++s) {
             const orc_sphere* sp = &sc->spheres[s];
@@ -336,6 +340,50 @@ static void cos_dir(const double* n, const double* t1, double ua, double ub, dou
     for (int i = 0; i < 3; ++i) w[i] = lx * t1[i] + ly * t2[i] + lz * n[i];
 }
 
+/* Glossy walls: the normalised modified-Phong lobe (a cosine power about the
+ * mirror direction, normalised by (n+2)/(2 pi) so that at normal incidence all
+ * of the reflected energy rho leaves the wall; reciprocal in wi and wo). */
+static void mirror_dir(const double* wi, const double* nrm, double* r) {
+    double d = 2.0 * dot3(wi, nrm);
+    for (int i = 0; i < 3; ++i) r[i] = wi[i] - d * nrm[i];
+}
+
+double orc_phong_eval(double n, const double* wi, const double* wo, const double* nrm) {
+    if (!(dot3(wi, nrm) < 0.0) || !(dot3(wo, nrm) > 0.0)) return 0.0;
+    double r[3];
+    mirror_dir(wi, nrm, r);
+    double c = dot3(r, wo);
+    if (!(c > 0.0)) return 0.0;
+    return (n + 2.0) / (2.0 * M_PI) * pow(c, n);
+}
+
+/* Orthonormal basis (t1, t2) completing unit r (Duff et al., "Building an
+ * Orthonormal Basis, Revisited", JCGT 2017). */
+static void basis_about(const double* r, double* t1, double* t2) {
+    double sg = r[2] >= 0.0 ? 1.0 : -1.0;
+    double a = -1.0 / (sg + r[2]);
+    double b = r[0] * r[1] * a;
+    t1[0] = 1.0 + sg * r[0] * r[0] * a;
+    t1[1] = sg * b;
+    t1[2] = -sg * r[0];
+    t2[0] = b;
+    t2[1] = sg + r[1] * r[1] * a;
+    t2[2] = -r[1];
+}
+
+double orc_phong_sample(double n, const double* wi, const double* nrm, double ua, double ub,
+                        double* wo) {
+    double r[3], t1[3], t2[3];
+    mirror_dir(wi, nrm, r);
+    basis_about(r, t1, t2);
+    double ca = pow(ua, 1.0 / (n + 1.0));
+    double sa = sqrt(fmax(0.0, 1.0 - ca * ca));
+    double ph = 2.0 * M_PI * ub;
+    for (int i = 0; i < 3; ++i) wo[i] = sa * cos(ph) * t1[i] + sa * sin(ph) * t2[i] + ca * r[i];
+    double co = dot3(wo, nrm);
+    return co > 0.0 ? (n + 2.0) / (n + 1.0) * co : 0.0;
+}
+
 /* Inward normal and tangent of box face f (0 x=lo, 1 x=hi, 2 y=lo, ...). */
 static void face_frame(int f, double* n, double* t1) {
     int a = f / 2;
@@ -487,6 +535,7 @@ typedef struct {
     uint32_t batch;
     uint32_t pid;
     double S[ORC_MAX_PARAMS]; /* running score: d/dtheta log p(path prefix) */
+    double weight;            /* throughput weight (glossy reflections; 1 otherwise) */
     double splat_sum;
     double margin;
 } path_t;
@@ -541,7 +590,8 @@ static void tally_escape(ctx_t* c, path_t* p, int side) {
  *   (power/paths) * f * T_r * W_e / r^2,  W_e = N_pix / (A_img cos^3 theta)
  * so that a uniform radiance L reads L in every pixel.
  * f = 1/(4 pi) in a medium, cos/pi on a Lambertian surface. */
-static void splat(ctx_t* c, path_t* p, const double* nrm, int is_light_vertex, uint32_t rr_bits) {
+static void splat(ctx_t* c, path_t* p, const double* nrm, int is_light_vertex, uint32_t rr_bits,
+                  const double* gloss_wi, double gloss_n) {
     const orc_scene* sc = c->sc;
     if (sc->sensor != ORC_SENSOR_PINHOLE) return;
     if (c->run->fluorescence_only && p->comp == 0) return;
@@ -554,7 +604,9 @@ static void splat(ctx_t* c, path_t* p, const double* nrm, int is_light_vertex, u
         double cs = dot3(nrm, wc);
         upd_margin(&p->margin, fabs(cs));
         if (!(cs > 0.0)) { T[ORC_T_SPLAT_MISS]++; return; }
-        f = cs / M_PI;
+        /* BRDF over rho (the path survived the reflection with probability
+         * rho) times the cosine toward the eye */
+        f = gloss_wi ? orc_phong_eval(gloss_n, gloss_wi, wc, nrm) * cs : cs / M_PI;
     } else {
         f = 1.0 / (4.0 * M_PI);
     }
@@ -626,7 +678,7 @@ static void splat(ctx_t* c, path_t* p, const double* nrm, int is_light_vertex, u
     double tr = exp(-tau);
     double cosc = zc / dist;
     double npix = (double)sc->width * (double)sc->height;
-    double v = c->wscale * f * tr * npix / (c->area_img * cosc * cosc * cosc * dist * dist);
+    double v = c->wscale * f * tr * npix / (c->area_img * cosc * cosc * cosc * dist * dist) * p->weight;
     double rr = c->run->splat_rr;
     if (rr > 0.0 && tr < rr) {
         double u = (double)rr_bits * (1.0 / 16777216.0);
@@ -737,6 +789,7 @@ static void run_path(ctx_t* c, uint32_t pid, orc_record* rec, uint32_t max_verti
     path_t p;
     memset(&p, 0, sizeof p);
     p.pid = pid;
+    p.weight = 1.0;
     p.batch = pid % (run->parity_batches ? run->parity_batches : 1);
     p.margin = INFINITY;
     double L = scene_scale(sc);
@@ -795,7 +848,7 @@ static void run_path(ctx_t* c, uint32_t pid, orc_record* rec, uint32_t max_verti
     p.medium = region_medium(sc, p.region);
     T[ORC_T_PATHS]++;
     T[ORC_T_VERTICES]++;
-    if (sc->light == ORC_LIGHT_QUAD) splat(c, &p, c->qn, 1, rr_bits_of(r));
+    if (sc->light == ORC_LIGHT_QUAD) splat(c, &p, c->qn, 1, rr_bits_of(r), NULL, 0.0);
     if (exit_code == -2) {
         /* reflected off the body on entry: escapes from the light vertex */
         int side = p.w[2] < 0.0 ? 0 : 1;
@@ -839,7 +892,7 @@ static void run_path(ctx_t* c, uint32_t pid, orc_record* rec, uint32_t max_verti
                 if (p.n_scatter > run->max_scatter) { exit_code = ORC_EXIT_SCAP; break; }
                 iso_dir(u2, u3, p.w);
                 perturb3(c, &p, 1, p.w);
-                splat(c, &p, NULL, 0, rr_bits_of(r));
+                splat(c, &p, NULL, 0, rr_bits_of(r), NULL, 0.0);
                 continue;
             }
             thr += md->sigma_a_bg;
@@ -880,7 +933,7 @@ static void run_path(ctx_t* c, uint32_t pid, orc_record* rec, uint32_t max_verti
             p.n_emit++;
             p.comp = 1;
             T[ORC_T_EMISSIONS]++;
-            splat(c, &p, NULL, 0, rr_bits_of(r));
+            splat(c, &p, NULL, 0, rr_bits_of(r), NULL, 0.0);
             continue;
         }
         /* reached a surface */
@@ -930,9 +983,25 @@ static void run_path(ctx_t* c, uint32_t pid, orc_record* rec, uint32_t max_verti
             if (!run->excitation_scatter && p.n_emit == 0) { exit_code = ORC_EXIT_EXCSCAT; break; }
             double n[3], t1[3];
             face_frame(h.index, n, t1);
+            double gn = sc->wall_gloss[h.index];
+            if (gn > 0.0) {
+                /* glossy wall: the realised vertex splats with the lobe about the
+                 * mirror of the incoming direction, then the path continues in a
+                 * direction drawn from the lobe with its throughput factor, or
+                 * ends when that direction falls below the wall */
+                double wi[3] = {p.w[0], p.w[1], p.w[2]}, wo[3];
+                splat(c, &p, n, 0, rr_bits_of(r), wi, gn);
+                double fw = orc_phong_sample(gn, wi, n, u2, u3, wo);
+                upd_margin(&p.margin, fabs(dot3(wo, n)));
+                if (!(fw > 0.0)) { exit_code = ORC_EXIT_WALL; break; }
+                memcpy(p.w, wo, sizeof p.w);
+                perturb3(c, &p, 1, p.w);
+                p.weight *= fw;
+                continue;
+            }
             cos_dir(n, t1, u2, u3, p.w);
             perturb3(c, &p, 1, p.w);
-            splat(c, &p, n, 0, rr_bits_of(r));
+            splat(c, &p, n, 0, rr_bits_of(r), NULL, 0.0);
             continue;
         }
         /* index-matched interface: change medium, no deflection */
@@ -1266,6 +1335,8 @@ int32_t orc_render_camera(const orc_scene* sc, const orc_run* run, double* film,
     if (!sc || !run) return fail("null argument");
     if (sc->geom != ORC_GEOM_BOX || sc->sensor != ORC_SENSOR_PINHOLE || sc->light != ORC_LIGHT_QUAD)
         return fail("the camera-side estimator needs a box scene with a pinhole and a quad light");
+    for (int f = 0; f < 6; ++f)
+        if (sc->wall_gloss[f] > 0.0) return fail("the camera-side estimator has Lambertian walls only");
     uint64_t per_sample = (uint64_t)sc->width * (uint64_t)sc->height * (uint64_t)sc->n_bins;
     if (per_sample == 0 || run->total_paths == 0 || run->total_paths % per_sample != 0)
         return fail("total_paths must be spp * width * height * n_bins");

@@ -113,6 +113,11 @@ typedef struct {
     int32_t sensor;
     double eye[3], look[3], up[3], fov_y_deg;
     int32_t width, height;
+    /* Glossy walls (sec. 5: the glossy Cornell box): wall f reflects with the
+     * normalised modified-Phong BRDF rho_f(lambda) (n+2)/(2 pi) cos^n(alpha),
+     * alpha the angle between the outgoing direction and the mirror direction,
+     * when wall_gloss[f] = n > 0 (pinhole scenes only); 0 = Lambertian. */
+    double wall_gloss[6];
 } orc_scene;
 
 typedef struct {
@@ -146,6 +151,18 @@ typedef struct {
     double splat_sum; /* sum of the values this path deposited */
     double margin;    /* smallest relative decision margin along the path */
 } orc_record;
+
+/* The glossy wall lobe (test hooks).  Directions: wi the incoming travel
+ * direction, wo the outgoing one, nrm the wall's inward unit normal.
+ * orc_phong_eval returns the BRDF over rho: (n+2)/(2 pi) cos^n(alpha), alpha
+ * between wo and the mirror direction of wi (0 when wo or wi is on the wrong
+ * side of the wall).  orc_phong_sample draws wo about the mirror direction
+ * with density (n+1)/(2 pi) cos^n(alpha) from uniforms (ua, ub) and returns
+ * the throughput factor BRDF cos(theta_o) / (rho pdf) = (n+2)/(n+1) cos(theta_o),
+ * or 0 when wo falls below the wall (the path ends there). */
+double orc_phong_eval(double n, const double* wi, const double* wo, const double* nrm);
+double orc_phong_sample(double n, const double* wi, const double* nrm, double ua, double ub,
+                        double* wo);
 
 /* Philox4x32-10 (Salmon et al., SC'11): out = bijection(ctr) under key. */
 void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);

@@ -306,3 +306,59 @@ def dielectric_sphere_point(n, sigma, a, s):
         mc = math.sqrt(1.0 - (a / n / s) ** 2)
         pts = [-mc, mc]
     return integrate.quad(f, -1.0, 1.0, points=pts or None, limit=200)[0]
+
+
+def phong_lobe(n, wi, wo, normal, about_normal=False):
+    """Normalised modified-Phong lobe over rho: (n+2)/(2 pi) cos^n(alpha), alpha
+    between the outgoing direction wo and the mirror direction of the incoming
+    travel direction wi about the wall normal (arrays of directions on the
+    last axis; 0 where wo leaves through the back of the wall)."""
+    wi, wo, normal = (np.asarray(a, float) for a in (wi, wo, normal))
+    r = normal if about_normal else wi - 2.0 * (wi @ normal)[..., None] * normal
+    c = np.maximum((r * wo).sum(-1), 0.0)
+    return np.where((wo @ normal) > 0, (n + 2.0) / (2.0 * math.pi) * c ** n, 0.0)
+
+
+def hemisphere_integral(fn, normal, n_theta=256, n_phi=256):
+    """int over the hemisphere about `normal` of fn(w) cos(theta) dw, by
+    Gauss-Legendre in cos(theta) and the trapezoid rule in phi (fn takes an
+    array of directions)."""
+    normal = np.asarray(normal, float)
+    t1 = np.cross(normal, [1.0, 0.0, 0.0] if abs(normal[0]) < 0.9 else [0.0, 1.0, 0.0])
+    t1 /= np.linalg.norm(t1)
+    t2 = np.cross(normal, t1)
+    g, wg = np.polynomial.legendre.leggauss(n_theta)
+    mu = 0.5 * (g + 1.0)
+    wmu = 0.5 * wg
+    ph = (np.arange(n_phi) + 0.5) * 2.0 * math.pi / n_phi
+    MU, PH = np.meshgrid(mu, ph, indexing="ij")
+    S = np.sqrt(1.0 - MU * MU)
+    w = (S * np.cos(PH))[..., None] * t1 + (S * np.sin(PH))[..., None] * t2 + MU[..., None] * normal
+    vals = fn(w) * MU
+    return float((vals * wmu[:, None]).sum() * 2.0 * math.pi / n_phi)
+
+
+def glossy_wall_radiance(x, normal, w_eye, corner, u, v, radiance, rho, n_exp, n=64,
+                         about_normal=False):
+    """Radiance leaving a glossy wall point x toward w_eye (unit, from x) when
+    the wall is lit only by a Lambertian parallelogram of radiance L:
+    int_quad rho lobe(wi, w_eye) L cos_x cos_l / r^2 dA, wi the direction from
+    the light point to x, by Gauss-Legendre quadrature over the quad."""
+    x = np.asarray(x, float)
+    g, w = np.polynomial.legendre.leggauss(n)
+    g = 0.5 * (g + 1)
+    w = 0.5 * w
+    nl = np.cross(u, v)
+    area = np.linalg.norm(nl)
+    nl = nl / area
+    A, B = np.meshgrid(g, g, indexing="ij")
+    W = np.outer(w, w)
+    y = corner[None, None, :] + A[..., None] * u + B[..., None] * v
+    dv = x - y
+    r2 = (dv * dv).sum(-1)
+    wi = dv / np.sqrt(r2)[..., None]
+    cl = wi @ nl
+    cx = -(wi @ np.asarray(normal, float))
+    f = rho * phong_lobe(n_exp, wi, np.broadcast_to(w_eye, wi.shape), normal, about_normal)
+    val = np.where((cl > 0) & (cx > 0), f * radiance * cl * cx / r2, 0.0)
+    return float((val * W).sum() * area)

@@ -144,6 +144,15 @@ def cornell_scene(width=128, height=128, conc_scale=(1.0, 1.0, 1.0), n_bins=101)
     }
 
 
+def glossy_cornell_scene(width=128, height=128, back=30.0, floor=8.0, n_bins=101):
+    """The Cornell scene with glossy walls (the paper's glossy Cornell box,
+    sec. 5): back wall and floor reflect with normalised modified-Phong lobes
+    of exponent `back` and `floor` about the mirror direction."""
+    s = cornell_scene(width, height, n_bins=n_bins)
+    s["geometry"]["wall_gloss"] = [0.0, 0.0, float(floor), 0.0, float(back), 0.0]
+    return s
+
+
 def cornell_config():
     """128x128 pinhole, 64 spp (2^20 light paths), 101 bins."""
     return cornell_scene(), make_run(128 * 128 * 64, seed=0)
