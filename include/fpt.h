@@ -183,6 +183,17 @@ typedef struct {
     int32_t width, height;
     double eye[3], look[3], up[3];
     double fov_y_deg;
+    /* Glossy walls (sec. 5, the glossy Cornell box): wall f with wall_gloss[f] =
+     * n > 0 reflects with the normalised modified-Phong BRDF
+     * walls[f](lambda) (n+2)/(2 pi) cos^n(alpha), alpha the angle between the
+     * outgoing direction and the mirror direction of the incoming one; the path
+     * survives with probability walls[f](lambda), draws its new direction from
+     * the lobe (cos alpha = u^(1/(n+1)) about the mirror direction) and carries
+     * the throughput weight (n+2)/(n+1) cos(theta_out), ending where that
+     * direction falls below the wall.  n in [0, 1e4]; 0 = Lambertian.  Box scenes
+     * with a pinhole sensor only (weighted paths do not fit integer escape
+     * tallies); the camera-side estimator refuses glossy scenes. */
+    double wall_gloss[6];
 } fpt_scene_desc;
 
 /* One render call: paths [path_begin, path_begin + path_count) of a job of

@@ -85,7 +85,7 @@ class SceneDesc(C.Structure):
         ("line_nm", C.c_double * MAX_LINES), ("line_power", C.c_double * MAX_LINES),
         ("sensor", C.c_int32), ("width", C.c_int32), ("height", C.c_int32),
         ("eye", C.c_double * 3), ("look", C.c_double * 3), ("up", C.c_double * 3),
-        ("fov_y_deg", C.c_double),
+        ("fov_y_deg", C.c_double), ("wall_gloss", C.c_double * 6),
     ]
 
 
@@ -234,6 +234,7 @@ def scene_desc(d):
         s.open_face = geo["open_face"]
         for f, w in enumerate(geo["walls"]):
             _spectrum(s.walls[f], w, keep)
+        s.wall_gloss[:] = geo.get("wall_gloss", [0.0] * 6)
         s.n_spheres = len(geo["spheres"])
         for i, sp in enumerate(geo["spheres"]):
             s.spheres[i].center[:] = sp["center"]

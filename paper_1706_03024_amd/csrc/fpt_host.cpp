@@ -228,6 +228,15 @@ int32_t validate(const fpt_scene_desc* d) {
     default:
         return set_err(FPT_E_INVALID, "geometry kind %d", d->geometry);
     }
+    bool glossy = false;
+    for (int f = 0; f < 6; ++f) {
+        if (!(d->wall_gloss[f] >= 0.0 && d->wall_gloss[f] <= 1e4))
+            return set_err(FPT_E_RANGE, "wall %d: Phong exponent outside [0, 1e4]", f);
+        glossy = glossy || d->wall_gloss[f] > 0.0;
+    }
+    if (glossy && (d->geometry != FPT_GEOM_BOX || d->sensor != FPT_SENSOR_PINHOLE))
+        return set_err(FPT_E_UNSUPPORTED, "glossy walls need a box scene with a pinhole "
+                                          "(path weights do not fit integer escape tallies)");
     if (d->geometry != FPT_GEOM_BOX) {
         if (d->body_medium < 0 || d->body_medium >= d->n_media) return set_err(FPT_E_INVALID, "body_medium");
         if (d->sensor != FPT_SENSOR_ESCAPE) return set_err(FPT_E_UNSUPPORTED, "pinhole sensor needs a box scene");
@@ -444,6 +453,7 @@ int32_t build_tables(fpt_scene* sc) {
     P.off_cum = off; off += d.n_media * cum_stride * N;
     P.off_cdf = off; off += d.n_dyes * N;
     P.off_rho = off; off += 6 * N;
+    P.off_gloss = off; off += d.geometry == FPT_GEOM_BOX ? 8 : 0;  // 6 exponents, even alignment
     P.off_kap = off; off += d.n_media * kap_stride * N;
     const bool cam = d.geometry == FPT_GEOM_BOX && d.sensor == FPT_SENSOR_PINHOLE;
     P.off_src = off; off += cam ? d.n_media * N * d.n_lines : 0;
@@ -498,6 +508,9 @@ int32_t build_tables(fpt_scene* sc) {
     }
     if (d.geometry == FPT_GEOM_BOX) {
         for (int f = 0; f < 6; ++f) {
+            const bool g = f != d.open_face && d.wall_gloss[f] > 0.0;
+            img[P.off_gloss + f] = fbits(g ? (float)d.wall_gloss[f] : 0.f);
+            P.glossy = P.glossy || g;
             for (int k = 0; k < N; ++k) {
                 const double r = (f == d.open_face) ? 0.0 : spectrum_on_grid(d.walls[f], lam[k], k);
                 if (!(r >= 0.0 && r <= 1.0)) return set_err(FPT_E_RANGE, "wall %d reflectance outside [0,1]", f);
@@ -739,7 +752,7 @@ int32_t reserve_scratch(fpt_scene* sc) {
     if (sc->desc.geometry == FPT_GEOM_BOX && sc->desc.sensor == FPT_SENSOR_PINHOLE) {
         if ((rc = max_launch(sc, P, MODE_FWD, &blocks, &waves)) != FPT_OK) return rc;
         if (waves) {
-            HIP_TRY(hipMalloc(&sc->d_sjobs, waves * 5 * kSjobSlice * 4), "hipMalloc(deferred splats)");
+            HIP_TRY(hipMalloc(&sc->d_sjobs, waves * kEntryWords * kSjobSlice * 4), "hipMalloc(deferred splats)");
             HIP_TRY(hipMalloc(&sc->d_sjob_counts, waves * 4), "hipMalloc(deferred splat counts)");
             sc->sjob_waves = waves;
         }
@@ -1188,7 +1201,7 @@ int32_t fpt_render_noalloc(fpt_scene* sc, const fpt_run* run, float* film, uint6
     if (defer) {
         // deferred slices shrink to what is left (a full slice falls back to
         // the wave's LDS queue, so the film changes only in fp32 rounding order)
-        const size_t per = (cap - fixed) / (waves * 5 * 4);
+        const size_t per = (cap - fixed) / (waves * kEntryWords * 4);
         slice = (uint32_t)std::min<size_t>(kSjobSlice, per & ~(size_t)63);
         if (slice > 0) {
             Bf.sjob_counts = reinterpret_cast<uint32_t*>(b + q_bytes);
@@ -1278,6 +1291,7 @@ int32_t fpt_render_camera(fpt_scene* sc, const fpt_run* run, float* film, uint64
     const fpt_scene_desc& d = sc->desc;
     if (d.geometry != FPT_GEOM_BOX || d.sensor != FPT_SENSOR_PINHOLE)
         return set_err(FPT_E_UNSUPPORTED, "the camera-side estimator needs a box scene with a pinhole");
+    if (sc->base.glossy) return set_err(FPT_E_UNSUPPORTED, "the camera-side estimator has Lambertian walls only");
     uint32_t B;
     int32_t rc = check_run(sc, run, &B);
     if (rc != FPT_OK) return rc;

@@ -89,11 +89,20 @@ struct KParams {
     // tests (in the image, through the open face, clear of the light quad) with
     // margin, and its medium can reach an optical depth of kTauZero inside it
     uint32_t sph_clear;
+    // glossy walls: word offset of the walls' Phong exponents (6 floats, 0 =
+    // Lambertian) in the table image, and whether any wall is glossy
+    int off_gloss;
+    int glossy;
 };
 
 // Optical depth past which a transmittance is exactly 0 in fp32: exp(-103.3)
 // is already below the smallest subnormal.
 constexpr float kTauZero = 110.f;
+
+// Words per queued camera connection (structure of arrays): x, y, z, two packed
+// words (roulette bits, vertex kind, wall face, component; wavelength bin,
+// parity slice) and the path's throughput weight (glossy walls only).
+constexpr int kEntryWords = 6;
 
 struct KBuffers {
     const uint32_t* tables;        // table image in device memory

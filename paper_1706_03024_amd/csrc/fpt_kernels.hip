@@ -92,6 +92,7 @@ struct Lane {
     int lam, region, medium, comp;
     uint32_t pid, v, nsc, nem, batch;
     float splat_sum;
+    float wgt;  // throughput weight (glossy walls; 1 otherwise)
 };
 
 DEV void load_sigma(const KParams& P, const uint32_t* S, Lane& L) {
@@ -330,7 +331,7 @@ struct SplatOut {
 };
 
 DEV SplatOut splat_eval(const uint32_t* S, const KSphere* SP, const float* x, int lam, int comp,
-                        uint32_t batch, int pend, const float* nrm, uint32_t rrb) {
+                        uint32_t batch, int pend, const float* nrm, uint32_t rrb, float wgt = 1.f) {
     const auto& P = *kernel_params();
     // Every test is evaluated and folded into `ok`, so the lanes of a wave stay
     // together; a rejected connection deposits nothing.
@@ -399,7 +400,7 @@ DEV SplatOut splat_eval(const uint32_t* S, const KSphere* SP, const float* x, in
     }
     const float tr = tau < kTauZero ? __expf(-tau) : 0.f;
     const float cosc = zc * rdist;
-    float v = P.wscale * f * tr * P.splat_norm * __builtin_amdgcn_rcpf(cosc * cosc * cosc * dist2);
+    float v = P.wscale * f * tr * P.splat_norm * __builtin_amdgcn_rcpf(cosc * cosc * cosc * dist2) * wgt;
     SplatOut o;
     o.status = ok ? 0 : 1;
     if (ok && P.splat_rr > 0.f && tr < P.splat_rr) {
@@ -454,7 +455,10 @@ DEV void wave_sync() {
 // words: rr bits (24) | pend (2) << 24 | wall face (3) << 26 | component << 29,
 // and wavelength bin | parity batch << 16.  head and count are wave-uniform.
 constexpr int kSqCap = 128;             // entries per wave, a power of two >= 2 * 64
-constexpr int kSqWords = 5 * kSqCap;    // x, y, z, packed a, packed b (structure of arrays)
+// LDS words of a wave's ring: structure of arrays of 5 words per entry, 6 with
+// glossy walls (the weight word).  The sixth word is not reserved otherwise: at
+// the large scene's table size it would cost a workgroup per CU.
+__host__ __device__ inline int sq_words(const KParams& P) { return (P.glossy ? kEntryWords : kEntryWords - 1) * kSqCap; }
 
 struct SplatQ {
     uint32_t* base;  // this wave's ring: [5][kSqCap] words
@@ -469,8 +473,10 @@ DEV uint32_t sq_word_a(uint32_t rrb, int pend, int face, int comp) {
 }
 
 // Appends one entry per lane with `want`; at most 64, so count stays below
-// kSqCap when it was below 64 before.
-DEV void sq_push(SplatQ& q, bool want, const float* x, uint32_t wa, uint32_t wb) {
+// kSqCap when it was below 64 before.  The weight word is written only where
+// paths carry weights (WGT: scenes with glossy walls).
+template <bool WGT>
+DEV void sq_push(SplatQ& q, bool want, const float* x, uint32_t wa, uint32_t wb, float wgt) {
     const uint64_t m = __ballot(want);
     if (want) {
         const int k = (q.head + q.count + (int)mbcnt(m)) & (kSqCap - 1);
@@ -479,6 +485,7 @@ DEV void sq_push(SplatQ& q, bool want, const float* x, uint32_t wa, uint32_t wb)
         q.base[2 * kSqCap + k] = __float_as_uint(x[2]);
         q.base[3 * kSqCap + k] = wa;
         q.base[4 * kSqCap + k] = wb;
+        if constexpr (WGT) q.base[5 * kSqCap + k] = __float_as_uint(wgt);
     }
     q.count += __popcll(m);
 }
@@ -535,7 +542,7 @@ DEV void film_add_merged(const KParams& P, float* film, uint32_t* agg, const Dep
 
 // One queued connection: decode and evaluate; the deposit is returned.
 DEV Deposit splat_entry(const KParams& P, const uint32_t* T, const KSphere* SP, uint32_t* tally,
-                        Counters& cnt, const float* x, uint32_t wa, uint32_t wb) {
+                        Counters& cnt, const float* x, uint32_t wa, uint32_t wb, float wgt) {
     const int pend = (int)((wa >> 24) & 3u), face = (int)((wa >> 26) & 7u), comp = (int)((wa >> 29) & 1u);
     // surface normal: the light's for its own vertex, a wall's inward normal otherwise
     const int ax = face >> 1;
@@ -544,7 +551,7 @@ DEV Deposit splat_entry(const KParams& P, const uint32_t* T, const KSphere* SP, 
     nrm[0] = pend == PEND_SOURCE ? P.ln[0] : (ax == 0 ? sg : 0.f);
     nrm[1] = pend == PEND_SOURCE ? P.ln[1] : (ax == 1 ? sg : 0.f);
     nrm[2] = pend == PEND_SOURCE ? P.ln[2] : (ax == 2 ? sg : 0.f);
-    const SplatOut so = splat_eval(T, SP, x, (int)(wb & 0xFFFFu), comp, wb >> 16, pend, nrm, wa & 0xFFFFFFu);
+    const SplatOut so = splat_eval(T, SP, x, (int)(wb & 0xFFFFu), comp, wb >> 16, pend, nrm, wa & 0xFFFFFFu, wgt);
     Deposit d;
     d.has = so.status == 0 && so.v != 0.f;  // +0 changes nothing
     d.idx = so.idx;
@@ -566,7 +573,8 @@ DEV void sq_flush(const KParams& P, float* film, const uint32_t* T, const KSpher
         const int k = (q.head + (int)lane) & (kSqCap - 1);
         const float x[3] = {__uint_as_float(q.base[k]), __uint_as_float(q.base[kSqCap + k]),
                             __uint_as_float(q.base[2 * kSqCap + k])};
-        d = splat_entry(P, T, SP, tally, cnt, x, q.base[3 * kSqCap + k], q.base[4 * kSqCap + k]);
+        const float wgt = P.glossy ? __uint_as_float(q.base[5 * kSqCap + k]) : 1.f;
+        d = splat_entry(P, T, SP, tally, cnt, x, q.base[3 * kSqCap + k], q.base[4 * kSqCap + k], wgt);
     }
     film_add_merged(P, film, q.agg, d, lane);
     q.head = (q.head + n) & (kSqCap - 1);
@@ -580,8 +588,9 @@ DEV void sq_flush(const KParams& P, float* film, const uint32_t* T, const KSpher
 // `sjob_slice` entries per wave; no atomics), which a separate launch
 // evaluates with every lane busy, so the last long paths walk at the walk's
 // own speed.  A full slice falls back to the LDS queue.
+template <bool WGT>
 DEV void splat_defer(const KBuffers& B, SplatQ& q, bool want, const float* x, uint32_t wa, uint32_t wb,
-                     bool exhausted) {
+                     float wgt, bool exhausted) {
     const uint64_t m = __ballot(want);
     const int n = __popcll(m);
     if (exhausted && q.slice && q.sj_n + n <= (int)B.sjob_slice) {
@@ -593,11 +602,12 @@ DEV void splat_defer(const KBuffers& B, SplatQ& q, bool want, const float* x, ui
             q.slice[2 * S + k] = __float_as_uint(x[2]);
             q.slice[3 * S + k] = wa;
             q.slice[4 * S + k] = wb;
+            if constexpr (WGT) q.slice[5 * S + k] = __float_as_uint(wgt);
         }
         q.sj_n += n;
         return;
     }
-    sq_push(q, want, x, wa, wb);
+    sq_push<WGT>(q, want, x, wa, wb, wgt);
 }
 
 // Full batches of 64 while there are any; with `all`, the remainder as well.
@@ -670,7 +680,7 @@ DEV float medium_exit(const KParams& P, const float* x, const float* w, const fl
     }
 }
 
-template <int GEOM, int MODE>
+template <int GEOM, int MODE, bool GLOSS>
 DEV void block_walk(const KParams& P, const KBuffers& B, const uint32_t* T, const KSphere* SP,
                     uint32_t* tally, Lane& L, uint64_t& elig, uint32_t lane, bool pinhole,
                     Counters& cnt, float* Sw, float* Gxl, float* G, bool& full, bool& deep, SplatQ& q,
@@ -723,6 +733,7 @@ DEV void block_walk(const KParams& P, const KBuffers& B, const uint32_t* T, cons
         Q.nsc = rlu(L.nsc, js);
         Q.nem = rlu(L.nem, js);
         Q.batch = rlu(L.batch, js);
+        if constexpr (GLOSS) Q.wgt = rl(L.wgt, js);
     } else {
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
@@ -745,6 +756,7 @@ DEV void block_walk(const KParams& P, const KBuffers& B, const uint32_t* T, cons
         Q.nsc = (uint32_t)__shfl((int)L.nsc, js);
         Q.nem = (uint32_t)__shfl((int)L.nem, js);
         Q.batch = (uint32_t)__shfl((int)L.batch, js);
+        if constexpr (GLOSS) Q.wgt = __shfl(L.wgt, js);
     }
     Q.splat_sum = 0.f;
 
@@ -832,14 +844,14 @@ DEV void block_walk(const KParams& P, const KBuffers& B, const uint32_t* T, cons
             const bool opq = want && opaque_to_eye(Lk.x, Q.region, Q.st, Q.sc, Q.sr2);
             count_opaque(tally, cnt, opq);
             want = want && !opq;
-            splat_defer(B, q, want, Lk.x, sq_word_a(rr_bits(r), PEND_MEDIUM, 0, Q.comp),
-                        (uint32_t)Q.lam | (Q.batch << 16), exhausted);
+            splat_defer<GLOSS>(B, q, want, Lk.x, sq_word_a(rr_bits(r), PEND_MEDIUM, 0, Q.comp),
+                               (uint32_t)Q.lam | (Q.batch << 16), GLOSS ? Q.wgt : 1.f, exhausted);
         }
     } else if constexpr (GEOM == FPT_GEOM_BOX) {
         if (pinhole && mine && !(P.fluo_only && Q.comp == 0)) {
             const float zero3[3] = {0.f, 0.f, 0.f};
             const SplatOut so = splat_eval(T, SP, Lk.x, Q.lam, Q.comp, Q.batch, PEND_MEDIUM, zero3,
-                                           rr_bits(r));
+                                           rr_bits(r), GLOSS ? Q.wgt : 1.f);
             if (so.status == 0) {
                 cnt.splat_hit++;
                 dep = so.v;
@@ -988,7 +1000,7 @@ DEV void deep_half(const KParams& P, const Lane& Q, uint32_t v0, uint32_t lane, 
     xk[3] = __uint_as_float(rr_bits(r));
 }
 
-template <int GEOM>
+template <int GEOM, bool GLOSS>
 DEV void deep_round(const KParams& P, const KBuffers& B, const uint32_t* T, const KSphere* SP,
                     uint32_t* tally, Lane& L, int j, uint32_t lane, bool pinhole, Counters& cnt, bool& full,
                     SplatQ& q, bool exhausted) {
@@ -1010,6 +1022,7 @@ DEV void deep_round(const KParams& P, const KBuffers& B, const uint32_t* T, cons
     Q.v = rlu(L.v, j);
     Q.nsc = rlu(L.nsc, j);
     Q.batch = rlu(L.batch, j);
+    Q.wgt = GLOSS ? rl(L.wgt, j) : 1.f;
     float wn1[3], x1[4], p1[3], win1[3], wn2[3], x2[4], p2[3], win2[3];
     bool st1, st2;
     deep_half<GEOM>(P, Q, Q.v, lane, Q.w, Q.x, wn1, x1, p1, win1, st1);
@@ -1030,14 +1043,15 @@ DEV void deep_round(const KParams& P, const KBuffers& B, const uint32_t* T, cons
             const bool o1 = m1 && dep && opaque_to_eye(x1, Q.region, Q.st, Q.sc, Q.sr2);
             count_opaque(tally, cnt, o1);
             const bool w1 = m1 && dep && !o1;
-            splat_defer(B, q, w1, x1, sq_word_a(__float_as_uint(x1[3]), PEND_MEDIUM, 0, Q.comp), wb, exhausted);
+            splat_defer<GLOSS>(B, q, w1, x1, sq_word_a(__float_as_uint(x1[3]), PEND_MEDIUM, 0, Q.comp), wb, Q.wgt,
+                               exhausted);
             sq_drain(P, B.film, T, SP, tally, q, cnt, lane, false);
             if (k2 > 0) {
                 const bool o2 = m2 && dep && opaque_to_eye(x2, Q.region, Q.st, Q.sc, Q.sr2);
                 count_opaque(tally, cnt, o2);
                 const bool w2 = m2 && dep && !o2;
-                splat_defer(B, q, w2, x2, sq_word_a(__float_as_uint(x2[3]), PEND_MEDIUM, 0, Q.comp), wb,
-                            exhausted);
+                splat_defer<GLOSS>(B, q, w2, x2, sq_word_a(__float_as_uint(x2[3]), PEND_MEDIUM, 0, Q.comp), wb,
+                                   Q.wgt, exhausted);
             }
         }
     }
@@ -1061,6 +1075,70 @@ DEV void deep_round(const KParams& P, const KBuffers& B, const uint32_t* T, cons
 }
 
 // -------------------------------------------------------------------------
+// Glossy wall reflection: the normalised modified-Phong lobe of exponent n,
+// rho (n+2)/(2 pi) cos^n(alpha), alpha measured from the mirror direction of
+// the incoming direction w about the wall `face` (sec. 5: glossy Cornell box).
+// The path survived the reflection test with probability rho, so its camera
+// connection at this vertex is weighted by the lobe toward the eye over the
+// Lambertian cos/pi the splat evaluates: (n+2)/2 cos^n(alpha_eye) (`lobe`).
+// The new direction is drawn from the lobe: cos alpha = u2^(1/(n+1)), azimuth
+// (sp, cp) = 2 pi u3, in the orthonormal basis of Duff et al. (2017) about the
+// mirror direction.  Returns false when it falls below the wall (the path ends
+// there), else sets w and the throughput factor (n+2)/(n+1) cos(theta_o).
+DEV bool glossy_reflect(float n, int face, float u2, float sp, float cp, const float* x, float* w,
+                        float* nrm, float& lobe, float& factor) {
+    const auto& K = *kernel_params();
+    const int ax = face >> 1;
+    const float sg = (face & 1) ? -1.f : 1.f;
+    nrm[0] = ax == 0 ? sg : 0.f;
+    nrm[1] = ax == 1 ? sg : 0.f;
+    nrm[2] = ax == 2 ? sg : 0.f;
+    // mirror about an axis-aligned wall: negate the normal component
+    const float r[3] = {ax == 0 ? -w[0] : w[0], ax == 1 ? -w[1] : w[1], ax == 2 ? -w[2] : w[2]};
+    const float d0 = K.eye[0] - x[0], d1 = K.eye[1] - x[1], d2 = K.eye[2] - x[2];
+    const float ce = (r[0] * d0 + r[1] * d1 + r[2] * d2) * __builtin_amdgcn_rsqf(d0 * d0 + d1 * d1 + d2 * d2);
+    lobe = ce > 0.f ? (n + 2.f) * 0.5f * __builtin_amdgcn_exp2f(n * __builtin_amdgcn_logf(ce)) : 0.f;
+    // cos alpha = u2^(1/(n+1)) = 2^y; sin^2 alpha = 1 - 2^(2y) = -expm1(2 y ln 2),
+    // by its Taylor series where 2y ln 2 is small (a sharp lobe puts cos alpha
+    // next to 1, where 1 - cos^2 would cancel), else directly
+    const float y = u2 > 0.f ? __builtin_amdgcn_logf(u2) * __builtin_amdgcn_rcpf(n + 1.f) : -kInf;
+    const float ca = __builtin_amdgcn_exp2f(y);
+    const float e = 2.f * 0.693147180559945309f * y;
+    float s2;
+    if (e > -0.5f) {
+        float t = 1.f + e * (1.f / 8.f);
+        t = 1.f + e * (1.f / 7.f) * t;
+        t = 1.f + e * (1.f / 6.f) * t;
+        t = 1.f + e * (1.f / 5.f) * t;
+        t = 1.f + e * (1.f / 4.f) * t;
+        t = 1.f + e * (1.f / 3.f) * t;
+        t = 1.f + e * (1.f / 2.f) * t;
+        s2 = -e * t;
+    } else {
+        s2 = 1.f - ca * ca;
+    }
+    const float sa = fsqrt(fmaxf(0.f, s2));
+    const float sz = r[2] >= 0.f ? 1.f : -1.f;
+    const float a = -__builtin_amdgcn_rcpf(sz + r[2]);
+    const float b = r[0] * r[1] * a;
+    const float t1[3] = {1.f + sz * r[0] * r[0] * a, sz * b, -sz * r[0]};
+    const float t2[3] = {b, sz + r[1] * r[1] * a, -r[1]};
+    const float p = sa * cp, q = sa * sp;
+    const float wo[3] = {p * t1[0] + q * t2[0] + ca * r[0], p * t1[1] + q * t2[1] + ca * r[1],
+                         p * t1[2] + q * t2[2] + ca * r[2]};
+    const float co = sg * (ax == 0 ? wo[0] : (ax == 1 ? wo[1] : wo[2]));
+    if (!(co > 0.f)) {
+        factor = 0.f;
+        return false;
+    }
+    w[0] = wo[0];
+    w[1] = wo[1];
+    w[2] = wo[2];
+    factor = (n + 2.f) * __builtin_amdgcn_rcpf(n + 1.f) * co;
+    return true;
+}
+
+// -------------------------------------------------------------------------
 // Per-wave context and per-lane walk state, shared by the single-scene and the
 // batched persistent kernels.
 struct WaveCtx {
@@ -1081,6 +1159,11 @@ struct WalkState {
     int face;  // wall face of a pending surface splat (deferred splats)
     float nrm[3];
     uint32_t rrb;
+    // glossy walls: the pending splat is a glossy reflection weighted by `sw`
+    // (the path's weight times the lobe toward the eye), and the path ends
+    // after it (its sampled direction fell below the wall)
+    float sw;
+    bool gspl, gdie;
     Counters cnt;
     SplatQ q;
 };
@@ -1105,6 +1188,9 @@ template <int GEOM, int MODE, bool REFR>
 DEV void advance(const KParams& P, const KBuffers& B, const WaveCtx& C, WalkState& W, AdjView& A,
                  float* G, bool exhausted) {
     constexpr bool DEFER = (GEOM == FPT_GEOM_BOX && MODE == MODE_FWD);  // queued splats
+    // in a box the refraction instantiation flag selects glossy walls instead
+    // (per-path throughput weights)
+    constexpr bool kGloss = REFR && GEOM == FPT_GEOM_BOX;
     constexpr bool ADJ = (MODE == MODE_ADJ || MODE == MODE_REC_ADJ);
     constexpr bool REC = (MODE == MODE_REC || MODE == MODE_REC_ADJ);
     (void)ADJ;
@@ -1153,7 +1239,7 @@ DEV void advance(const KParams& P, const KBuffers& B, const WaveCtx& C, WalkStat
                         const int j = __ffsll((unsigned long long)ed) - 1;
                         elig &= ~(1ull << j);
                         bool fj = false;
-                        deep_round<GEOM>(P, B, T, SP, tally, L, j, lane, pinhole, cnt, fj, W.q, exhausted);
+                        deep_round<GEOM, kGloss>(P, B, T, SP, tally, L, j, lane, pinhole, cnt, fj, W.q, exhausted);
                         if ((int)lane == j) {
                             full = fj;
                             deep = fj;
@@ -1162,7 +1248,7 @@ DEV void advance(const KParams& P, const KBuffers& B, const WaveCtx& C, WalkStat
                         continue;
                     }
                 }
-                block_walk<GEOM, MODE>(P, B, T, SP, tally, L, elig, lane, pinhole, cnt,
+                block_walk<GEOM, MODE, kGloss>(P, B, T, SP, tally, L, elig, lane, pinhole, cnt,
                                        ADJ ? A.S - lane : nullptr, ADJ ? A.Gx : nullptr, G, full, deep, W.q,
                                        exhausted, deepm);
                 if constexpr (DEFER) sq_drain(P, B.film, T, SP, tally, W.q, cnt, lane, false);
@@ -1218,6 +1304,7 @@ DEV void advance(const KParams& P, const KBuffers& B, const WaveCtx& C, WalkStat
             const float u0 = u24(r.x), u1 = u24(r.y), u2 = u24(r.z), u3 = u24(r.w);
             float dir_sin = 0.f, dir_cos = 0.f;  // polar sine/cosine of a new direction
             int frame = -1;                      // -1 world axes, else wall face
+            float gloss_n = 0.f;                 // Phong exponent of a glossy wall reflection
             bool need1 = false;                  // the vertex draws call 1 of its counter too
             int dye = 0;                         // the absorbing dye (step lanes)
             if (start) {
@@ -1225,6 +1312,7 @@ DEV void advance(const KParams& P, const KBuffers& B, const WaveCtx& C, WalkStat
                 L.nsc = 0;
                 L.nem = 0;
                 L.comp = 0;
+                if constexpr (kGloss) L.wgt = 1.f;
                 L.batch = L.pid % P.batches;
                 L.splat_sum = 0.f;
                 int line = 0;
@@ -1320,11 +1408,13 @@ DEV void advance(const KParams& P, const KBuffers& B, const WaveCtx& C, WalkStat
                                 exit_code = FPT_EXIT_EXCSCAT;
                             } else {
                                 // Lambertian reflection about the wall's inward normal
+                                // (or the glossy lobe, below)
                                 dir_sin = fsqrt(u2);
                                 dir_cos = fsqrt(1.f - u2);
                                 frame = h.idx;
                                 W.face = h.idx;
                                 pend = PEND_SURFACE;
+                                if constexpr (kGloss) gloss_n = wf(T, P.off_gloss + h.idx);
                             }
                         }
                     } else {
@@ -1443,7 +1533,18 @@ DEV void advance(const KParams& P, const KBuffers& B, const WaveCtx& C, WalkStat
                     float sp, cp;
                     sincos_rev(u3, &sp, &cp);
                     const float a = dir_sin * cp, b = dir_sin * sp;
-                    if (frame < 0) {
+                    if (kGloss && gloss_n > 0.f) {
+                        float lobe = 0.f, fac = 0.f;
+                        const bool on = glossy_reflect(gloss_n, frame, u2, sp, cp, L.x, L.w, nrm, lobe, fac);
+                        W.sw = L.wgt * lobe;
+                        W.gspl = true;
+                        if (on) {
+                            L.wgt *= fac;
+                        } else {
+                            exit_code = FPT_EXIT_WALL;
+                            W.gdie = true;
+                        }
+                    } else if (frame < 0) {
                         L.w[0] = a; L.w[1] = b; L.w[2] = dir_cos;
                     } else {
                         // wall frame: normal n = sg e_ax, tangents e_(ax+1), sg e_(ax+2)
@@ -1468,17 +1569,22 @@ DEV void advance(const KParams& P, const KBuffers& B, const WaveCtx& C, WalkStat
     // ---- convergent splat section
     if constexpr (DEFER) {
         if (pinhole) {
-            bool want = pend != PEND_NONE && alive && exit_code < 0 && !(P.fluo_only && L.comp == 0);
+            bool want = pend != PEND_NONE && alive && (exit_code < 0 || (kGloss && W.gdie)) &&
+                        !(P.fluo_only && L.comp == 0);
             const bool opq = want && pend == PEND_MEDIUM && opaque_to_eye(L.x, L.region, L.st, L.sc, L.sr2);
             count_opaque(tally, cnt, opq);
             want = want && !opq;
-            splat_defer(B, W.q, want, L.x, sq_word_a(rrb, pend, W.face, L.comp),
-                        (uint32_t)L.lam | (L.batch << 16), exhausted);
+            float sw = 1.f;
+            if constexpr (kGloss) sw = W.gspl ? W.sw : L.wgt;
+            splat_defer<kGloss>(B, W.q, want, L.x, sq_word_a(rrb, pend, W.face, L.comp),
+                                (uint32_t)L.lam | (L.batch << 16), sw, exhausted);
         }
     } else if constexpr (GEOM == FPT_GEOM_BOX) {
-        if (pinhole && pend != PEND_NONE && alive && exit_code < 0) {
+        if (pinhole && pend != PEND_NONE && alive && (exit_code < 0 || (kGloss && W.gdie))) {
             if (!(P.fluo_only && L.comp == 0)) {
-                const SplatOut so = splat_eval(T, SP, L.x, L.lam, L.comp, L.batch, pend, nrm, rrb);
+                float sw = 1.f;
+                if constexpr (kGloss) sw = W.gspl ? W.sw : L.wgt;
+                const SplatOut so = splat_eval(T, SP, L.x, L.lam, L.comp, L.batch, pend, nrm, rrb, sw);
                 if (so.status == 0) {
                     cnt.splat_hit++;
                     L.splat_sum += so.v;
@@ -1515,6 +1621,10 @@ DEV void advance(const KParams& P, const KBuffers& B, const WaveCtx& C, WalkStat
         }
     }
     pend = PEND_NONE;
+    if constexpr (kGloss) {
+        W.gspl = false;
+        W.gdie = false;
+    }
 
     // ---- path end
     if (alive && exit_code >= 0) {
@@ -1614,9 +1724,13 @@ __global__ void __launch_bounds__(256) k_transport(const KParams P, const KBuffe
     W.face = 0;
     W.nrm[0] = W.nrm[1] = W.nrm[2] = 0.f;
     W.rrb = 0;
+    W.sw = 1.f;
+    W.gspl = false;
+    W.gdie = false;
+    W.L.wgt = 1.f;
     constexpr bool DEFER = (GEOM == FPT_GEOM_BOX && MODE == MODE_FWD);
-    W.q.base = smem + kLdsTable + tw + P.hist_words + wave * (kSqWords + kAggWords);  // DEFER only
-    W.q.agg = W.q.base + kSqWords;
+    W.q.base = smem + kLdsTable + tw + P.hist_words + wave * (sq_words(P) + kAggWords);  // DEFER only
+    W.q.agg = W.q.base + sq_words(P);
     if constexpr (DEFER) {
         for (int i = (int)lane; i < kAggSlots; i += 64) {
             W.q.agg[i] = kAggEmpty;
@@ -1626,7 +1740,7 @@ __global__ void __launch_bounds__(256) k_transport(const KParams P, const KBuffe
     W.q.head = 0;
     W.q.count = 0;
     const uint32_t gwave = blockIdx.x * (blockDim.x >> 6) + (uint32_t)__builtin_amdgcn_readfirstlane(wave);
-    W.q.slice = (DEFER && B.sjobs) ? B.sjobs + (size_t)gwave * 5 * B.sjob_slice : nullptr;
+    W.q.slice = (DEFER && B.sjobs) ? B.sjobs + (size_t)gwave * kEntryWords * B.sjob_slice : nullptr;
     W.q.sj_n = 0;
     bool exhausted = false;
     // the path queue is split into kQueueShards contiguous ranges with a head
@@ -1796,6 +1910,10 @@ __global__ void __launch_bounds__(256) k_batch(const KBatch Bt) {
     W.face = 0;
     W.nrm[0] = W.nrm[1] = W.nrm[2] = 0.f;
     W.rrb = 0;
+    W.sw = 1.f;
+    W.gspl = false;
+    W.gdie = false;
+    W.L.wgt = 1.f;
     W.q.base = nullptr;
     W.q.agg = nullptr;
     W.q.head = 0;
@@ -1890,7 +2008,7 @@ __global__ void __launch_bounds__(256) k_splat_jobs(const KParams P, const KBuff
     for (int i = threadIdx.x; i < P.n_spheres; i += blockDim.x) SPw[i] = P.spheres[i];
     __syncthreads();
     const uint32_t S = B.sjob_slice;
-    const uint32_t* sl = B.sjobs + (size_t)blockIdx.x * 5 * S;
+    const uint32_t* sl = B.sjobs + (size_t)blockIdx.x * kEntryWords * S;
     const uint32_t lane = lane_id();
     const uint32_t wv = threadIdx.x >> 6;
     uint32_t* agg = smem + kLdsTable + ((P.off_kap + 63) & ~63) + wv * kAggWords;
@@ -1907,7 +2025,8 @@ __global__ void __launch_bounds__(256) k_splat_jobs(const KParams P, const KBuff
         d.v = 0.f;
         if (i < n) {
             const float x[3] = {__uint_as_float(sl[i]), __uint_as_float(sl[S + i]), __uint_as_float(sl[2 * S + i])};
-            d = splat_entry(P, T, SPw, tally, cnt, x, sl[3 * S + i], sl[4 * S + i]);
+            const float wgt = P.glossy ? __uint_as_float(sl[5 * S + i]) : 1.f;
+            d = splat_entry(P, T, SPw, tally, cnt, x, sl[3 * S + i], sl[4 * S + i], wgt);
         }
         film_add_merged(P, B.film, agg, d, lane);
     }
@@ -2414,7 +2533,7 @@ size_t transport_lds_bytes(const KParams& P, int block_threads, int mode) {
     const int staged = (mode == MODE_ADJ || mode == MODE_REC_ADJ) ? P.off_src : P.off_kap;
     size_t words = kLdsTable + ((staged + 63) & ~63) + P.hist_words;
     if (mode == MODE_FWD && P.geometry == FPT_GEOM_BOX)  // deferred splat rings and merging tables
-        words += (size_t)(block_threads / 64) * (kSqWords + kAggWords);
+        words += (size_t)(block_threads / 64) * (sq_words(P) + kAggWords);
     if (mode == MODE_ADJ || mode == MODE_REC_ADJ)
         words += (size_t)(block_threads / 64) * 2 * kMaxNP * 64 + (size_t)(block_threads / 64) * kMaxNP;
     return words * 4;
@@ -2440,8 +2559,11 @@ static hipError_t launch_m(const KParams& P, const KBuffers& B, int grid, int bl
     case FPT_GEOM_INFINITE:
         hipLaunchKernelGGL((k_transport<FPT_GEOM_INFINITE, MODE, false>), dim3(grid), dim3(block), lds, s, P, B);
         return hipGetLastError();
-    default:
-        hipLaunchKernelGGL((k_transport<FPT_GEOM_BOX, MODE, false>), dim3(grid), dim3(block), lds, s, P, B);
+    default:  // the box: the second instantiation carries glossy walls
+        if (P.glossy)
+            hipLaunchKernelGGL((k_transport<FPT_GEOM_BOX, MODE, true>), dim3(grid), dim3(block), lds, s, P, B);
+        else
+            hipLaunchKernelGGL((k_transport<FPT_GEOM_BOX, MODE, false>), dim3(grid), dim3(block), lds, s, P, B);
         return hipGetLastError();
     }
 }
@@ -2461,7 +2583,7 @@ static hipError_t occ_m(const KParams& P, int block, int* n) {
         return r ? occ_t<FPT_GEOM_HALFSPACE, MODE, true>(P, block, n) : occ_t<FPT_GEOM_HALFSPACE, MODE, false>(P, block, n);
     case FPT_GEOM_SPHERE: return r ? occ_t<FPT_GEOM_SPHERE, MODE, true>(P, block, n) : occ_t<FPT_GEOM_SPHERE, MODE, false>(P, block, n);
     case FPT_GEOM_INFINITE: return occ_t<FPT_GEOM_INFINITE, MODE, false>(P, block, n);
-    default: return occ_t<FPT_GEOM_BOX, MODE, false>(P, block, n);
+    default: return P.glossy ? occ_t<FPT_GEOM_BOX, MODE, true>(P, block, n) : occ_t<FPT_GEOM_BOX, MODE, false>(P, block, n);
     }
 }
 

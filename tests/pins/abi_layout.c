@@ -17,6 +17,7 @@ int main(void) {
     printf("off_light %zu\n", offsetof(fpt_scene_desc, light));
     printf("off_sensor %zu\n", offsetof(fpt_scene_desc, sensor));
     printf("off_fov %zu\n", offsetof(fpt_scene_desc, fov_y_deg));
+    printf("off_gloss %zu\n", offsetof(fpt_scene_desc, wall_gloss));
     printf("off_splat_rr %zu\n", offsetof(fpt_run, splat_rr));
     return 0;
 }

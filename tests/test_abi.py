@@ -52,6 +52,7 @@ def test_struct_layouts_match_header():
     assert int(out["off_light"]) == _abi.SceneDesc.light.offset
     assert int(out["off_sensor"]) == _abi.SceneDesc.sensor.offset
     assert int(out["off_fov"]) == _abi.SceneDesc.fov_y_deg.offset
+    assert int(out["off_gloss"]) == _abi.SceneDesc.wall_gloss.offset
     assert int(out["off_splat_rr"]) == _abi.Run.splat_rr.offset
 
 
@@ -108,6 +109,18 @@ def test_invalid_box_descriptors_rejected():
     assert _create_status(s)[0] == _abi.E_UNSUPPORTED
     s = workloads.cornell_scene(8, 8)
     s["media"][1]["ior"] = 1.5   # refracting sphere: no straight camera connection through it
+    assert _create_status(s)[0] == _abi.E_UNSUPPORTED
+
+
+def test_glossy_walls_rejected_where_unsupported():
+    s = workloads.glossy_cornell_scene(8, 8)
+    s["geometry"]["wall_gloss"][2] = -1.0
+    assert _create_status(s)[0] == _abi.E_RANGE
+    s = workloads.glossy_cornell_scene(8, 8)
+    s["geometry"]["wall_gloss"][2] = 2e4
+    assert _create_status(s)[0] == _abi.E_RANGE
+    s = workloads.glossy_cornell_scene(8, 8)
+    s["sensor"] = {"kind": "escape"}
     assert _create_status(s)[0] == _abi.E_UNSUPPORTED
 
 
