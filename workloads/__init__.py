@@ -466,6 +466,20 @@ def dark_box_scene(sphere_medium=None, width=32, height=32, n_bins=101, lines=No
     }
 
 
+def validation_scene(lambda_x=550.0, conc_uM=1.0, sigma_s=20.0, width=32, n_bins=101):
+    """The paper's spectral validation (sec. 6, Figs. 6-7) as a synthetic scene:
+    one sphere of a single Gaussian dye (absorption 550/20 nm, emission 580/25 nm,
+    epsilon 7e4, QY 0.8) in a box with black walls, lit at one excitation line,
+    seen by a pinhole; weak dye (1 uM) so reabsorption barely reshapes the
+    escaping fluorescence."""
+    med = {"sigma_s": sigma_s, "sigma_a_bg": 0.01, "dyes": [[0, conc_uM]]}
+    s = dark_box_scene(sphere_medium=med, width=width, height=width, n_bins=n_bins,
+                       lines=[(lambda_x, 1.0)])
+    s["dyes"] = [{"absorption": gauss((550.0, 20.0, 1.0)), "emission": gauss((580.0, 25.0, 1.0)),
+                  "epsilon": 7e4, "qy": 0.8}]
+    return s
+
+
 def maximal_scene(n_bins=101, width=16):
     """The box at every descriptor maximum the ABI allows: 8 spheres, each of
     its own medium; 8 dyes, 4 in every medium; 8 light lines; a 16-term
