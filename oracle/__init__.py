@@ -15,7 +15,9 @@ import subprocess
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "liboracle.so")
+BUILD_PATH = os.path.join(_HERE, "liboracle.so")
+# a sanitizer build of the same source may stand in for it (tests only)
+LIB_PATH = os.environ.get("FPT_ORACLE_LIBRARY") or BUILD_PATH
 
 MAX_TERMS, MAX_DYES, MAX_MEDIA, MAX_MEDIUM_DYES, MAX_SPHERES, MAX_LINES = 16, 8, 8, 4, 8, 8
 
@@ -30,7 +32,7 @@ N_TALLIES = 20
 def build(verbose=False):
     """Compile liboracle.so with gcc (-O2, no fast-math)."""
     cmd = ["gcc", "-O2", "-std=c11", "-Wall", "-fPIC", "-shared",
-           os.path.join(_HERE, "oracle.c"), "-lm", "-o", LIB_PATH]
+           os.path.join(_HERE, "oracle.c"), "-lm", "-o", BUILD_PATH]
     if verbose:
         print(" ".join(cmd))
     subprocess.run(cmd, check=True)

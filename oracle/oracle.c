@@ -183,6 +183,8 @@ static int validate(const orc_scene* sc) {
             if (!(sp->radius > 0.0)) return fail("sphere radius");
         }
     } else {
+        for (int f = 0; f < 6; ++f)
+            if (sc->wall_gloss[f] != 0.0) return fail("glossy walls need a box scene");
         if (sc->body_medium < 0 || sc->body_medium >= sc->n_media) return fail("body medium");
         if (sc->sensor != ORC_SENSOR_ESCAPE) return fail("pinhole needs a box scene");
         if (sc->light == ORC_LIGHT_QUAD) return fail("quad light needs a box scene");

@@ -12,7 +12,8 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libfpt.so")
+# a sanitizer build of the same sources may stand in for it (tests only)
+LIB_PATH = os.environ.get("FPT_LIBRARY") or os.path.join(_HERE, "libfpt.so")
 
 MAX_TERMS = 16
 MAX_DYES = 8

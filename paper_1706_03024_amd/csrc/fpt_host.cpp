@@ -68,6 +68,37 @@ int32_t hip_err(hipError_t e, const char* what) {
     return set_err(FPT_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
 }
 
+// Allocation-failure injection for robustness tests: with FPT_FAULT_INJECT=N
+// in the environment, the N-th allocation (device, pinned host, or the scene /
+// batch object itself) made by one fpt_scene_create or fpt_batch_create call
+// fails as out of memory; the call must then return FPT_E_NOMEM having freed
+// everything it had allocated.  Armed at the start of those calls only.
+thread_local int g_alloc_n = 0, g_alloc_fail = 0;
+
+void alloc_fault_arm(bool on) {
+    const char* e = on ? std::getenv("FPT_FAULT_INJECT") : nullptr;
+    g_alloc_fail = e ? std::atoi(e) : 0;
+    g_alloc_n = 0;
+}
+
+bool alloc_fault_hit() { return g_alloc_fail > 0 && ++g_alloc_n == g_alloc_fail; }
+
+hipError_t dev_malloc(void** p, size_t bytes) {
+    if (alloc_fault_hit()) return hipErrorOutOfMemory;
+    return hipMalloc(p, bytes);
+}
+
+hipError_t pinned_malloc(void** p, size_t bytes) {
+    if (alloc_fault_hit()) return hipErrorOutOfMemory;
+    return hipHostMalloc(p, bytes, hipHostMallocDefault);
+}
+
+template <class T>
+T* new_object() {
+    if (alloc_fault_hit()) return nullptr;
+    return new (std::nothrow) T();
+}
+
 #define HIP_TRY(expr, what)                       \
     do {                                          \
         hipError_t e_ = (expr);                   \
@@ -650,7 +681,7 @@ int32_t build_tables(fpt_scene* sc) {
 
 int32_t upload_tables(fpt_scene* sc) {
     const size_t bytes = sc->image.size() * 4;
-    if (!sc->d_tables) HIP_TRY(hipMalloc(&sc->d_tables, std::max<size_t>(bytes, 4)), "hipMalloc(tables)");
+    if (!sc->d_tables) HIP_TRY(dev_malloc((void**)&sc->d_tables, std::max<size_t>(bytes, 4)), "hipMalloc(tables)");
     HIP_TRY(hipMemcpy(sc->d_tables, sc->image.data(), bytes, hipMemcpyHostToDevice), "upload tables");
     return FPT_OK;
 }
@@ -732,10 +763,10 @@ int32_t max_launch(const fpt_scene* sc, const KParams& P0, int mode, size_t* blo
 
 // Device scratch of a scene, sized once for every launch it can make.
 int32_t reserve_scratch(fpt_scene* sc) {
-    HIP_TRY(hipMalloc(&sc->d_counter, queue_words() * 8), "hipMalloc(path queue)");
+    HIP_TRY(dev_malloc((void**)&sc->d_counter, queue_words() * 8), "hipMalloc(path queue)");
     if (sc->desc.sensor == FPT_SENSOR_ESCAPE) {
         sc->counts_words = (size_t)film_elems(sc->desc, 64);
-        HIP_TRY(hipMalloc(&sc->d_counts, sc->counts_words * 4), "hipMalloc(counts)");
+        HIP_TRY(dev_malloc((void**)&sc->d_counts, sc->counts_words * 4), "hipMalloc(counts)");
     }
     fpt_run r;
     std::memset(&r, 0, sizeof r);
@@ -746,18 +777,19 @@ int32_t reserve_scratch(fpt_scene* sc) {
     int32_t rc = max_launch(sc, P, MODE_ADJ, &blocks, &waves);
     if (rc != FPT_OK) return rc;
     if (blocks) {
-        HIP_TRY(hipMalloc(&sc->d_partials, blocks * kMaxNP * 4), "hipMalloc(partials)");
+        HIP_TRY(dev_malloc((void**)&sc->d_partials, blocks * kMaxNP * 4), "hipMalloc(partials)");
         sc->partials_blocks = blocks;
     }
     if (sc->desc.geometry == FPT_GEOM_BOX && sc->desc.sensor == FPT_SENSOR_PINHOLE) {
         if ((rc = max_launch(sc, P, MODE_FWD, &blocks, &waves)) != FPT_OK) return rc;
         if (waves) {
-            HIP_TRY(hipMalloc(&sc->d_sjobs, waves * kEntryWords * kSjobSlice * 4), "hipMalloc(deferred splats)");
-            HIP_TRY(hipMalloc(&sc->d_sjob_counts, waves * 4), "hipMalloc(deferred splat counts)");
+            HIP_TRY(dev_malloc((void**)&sc->d_sjobs, waves * kEntryWords * kSjobSlice * 4),
+                    "hipMalloc(deferred splats)");
+            HIP_TRY(dev_malloc((void**)&sc->d_sjob_counts, waves * 4), "hipMalloc(deferred splat counts)");
             sc->sjob_waves = waves;
         }
     }
-    HIP_TRY(hipHostMalloc((void**)&sc->h_stage, std::max<size_t>(4, sc->image.size() * 4), hipHostMallocDefault),
+    HIP_TRY(pinned_malloc((void**)&sc->h_stage, std::max<size_t>(4, sc->image.size() * 4)),
             "hipHostMalloc(table staging)");
     HIP_TRY(hipEventCreateWithFlags(&sc->staged, hipEventDisableTiming), "hipEventCreate");
     return FPT_OK;
@@ -867,7 +899,8 @@ int32_t batch_build_items(fpt_batch* bt) {
         if (bt->d_items) (void)hipFree(bt->d_items);
         bt->d_items = nullptr;
         bt->items_cap = 0;
-        HIP_TRY(hipMalloc(&bt->d_items, std::max<size_t>(1, items.size()) * sizeof(KWorkItem)), "hipMalloc(items)");
+        HIP_TRY(dev_malloc((void**)&bt->d_items, std::max<size_t>(1, items.size()) * sizeof(KWorkItem)),
+                "hipMalloc(items)");
         bt->items_cap = items.size();
     }
     if (!items.empty())
@@ -941,12 +974,22 @@ const char* fpt_status_str(int32_t s) {
 
 const char* fpt_last_error(void) { return g_err.c_str(); }
 
-int32_t fpt_scene_create(const fpt_scene_desc* desc, fpt_scene** out) {
-    if (!desc || !out) return set_err(FPT_E_INVALID, "NULL argument");
-    *out = nullptr;
+}  // extern "C"
+
+namespace {
+
+// fpt_scene_create without its exception and fault-injection wrapper: `held`
+// owns the scene until it is handed out, so every failure path (a status, or
+// a host allocation failure thrown by the table build) frees all of it.
+struct SceneHold {
+    fpt_scene* p = nullptr;
+    ~SceneHold() { if (p) fpt_scene_destroy(p); }
+};
+
+int32_t scene_create(const fpt_scene_desc* desc, fpt_scene** out, SceneHold& held) {
     int32_t rc = validate(desc);
     if (rc != FPT_OK) return rc;
-    fpt_scene* sc = new (std::nothrow) fpt_scene();
+    fpt_scene* sc = held.p = new_object<fpt_scene>();
     if (!sc) return set_err(FPT_E_NOMEM, "host allocation");
     sc->desc = *desc;
     // tabulated spectra are borrowed for the call: keep copies and point at them
@@ -961,22 +1004,32 @@ int32_t fpt_scene_create(const fpt_scene_desc* desc, fpt_scene** out) {
     }
     for (int f = 0; f < 6; ++f) own(sc->desc.walls[f]);
     std::memset(&sc->tune, 0, sizeof sc->tune);
-    if ((rc = build_tables(sc)) != FPT_OK) {
-        delete sc;
-        return rc;
-    }
-    hipError_t e = hipGetDevice(&sc->device);
-    if (e == hipSuccess) e = hipDeviceGetAttribute(&sc->n_cu, hipDeviceAttributeMultiprocessorCount, sc->device);
-    if (e != hipSuccess) {
-        delete sc;
-        return hip_err(e, "device query");
-    }
-    if ((rc = upload_tables(sc)) != FPT_OK || (rc = reserve_scratch(sc)) != FPT_OK) {
-        fpt_scene_destroy(sc);
-        return rc;
-    }
+    if ((rc = build_tables(sc)) != FPT_OK) return rc;
+    HIP_TRY(hipGetDevice(&sc->device), "device query");
+    HIP_TRY(hipDeviceGetAttribute(&sc->n_cu, hipDeviceAttributeMultiprocessorCount, sc->device), "device query");
+    if ((rc = upload_tables(sc)) != FPT_OK || (rc = reserve_scratch(sc)) != FPT_OK) return rc;
     *out = sc;
+    held.p = nullptr;
     return FPT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t fpt_scene_create(const fpt_scene_desc* desc, fpt_scene** out) {
+    if (!desc || !out) return set_err(FPT_E_INVALID, "NULL argument");
+    *out = nullptr;
+    alloc_fault_arm(true);
+    int32_t rc;
+    try {
+        SceneHold held;
+        rc = scene_create(desc, out, held);
+    } catch (const std::bad_alloc&) {
+        rc = set_err(FPT_E_NOMEM, "host allocation");
+    }
+    alloc_fault_arm(false);
+    return rc;
 }
 
 void fpt_scene_destroy(fpt_scene* sc) {
@@ -1333,13 +1386,41 @@ int32_t fpt_render_camera(fpt_scene* sc, const fpt_run* run, float* film, uint64
     return FPT_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+int32_t batch_create(const fpt_scene_desc* descs, const fpt_run* runs, int32_t n, const fpt_tune* tune,
+                     fpt_batch** out);
+
+}  // namespace
+
+extern "C" {
+
 int32_t fpt_batch_create(const fpt_scene_desc* descs, const fpt_run* runs, int32_t n,
                          const fpt_tune* tune, fpt_batch** out) {
     if (!descs || !runs || !out) return set_err(FPT_E_INVALID, "NULL argument");
     *out = nullptr;
     if (n < 1 || n > (1 << 20)) return set_err(FPT_E_RANGE, "instance count %d", n);
-    fpt_batch* bt = new (std::nothrow) fpt_batch();
-    if (!bt) return set_err(FPT_E_NOMEM, "host allocation");
+    alloc_fault_arm(true);
+    int32_t rc;
+    try {
+        rc = batch_create(descs, runs, n, tune, out);
+    } catch (const std::bad_alloc&) {
+        rc = set_err(FPT_E_NOMEM, "host allocation");
+    }
+    alloc_fault_arm(false);
+    return rc;
+}
+
+}  // extern "C"
+
+namespace {
+
+// fpt_batch_create after its argument checks; `bt` is freed on every failure
+// path, a host allocation failure thrown by the setup included.
+int32_t batch_setup(fpt_batch* bt, const fpt_scene_desc* descs, const fpt_run* runs, int32_t n,
+                    const fpt_tune* tune, fpt_batch** out) {
     std::memset(&bt->tune, 0, sizeof bt->tune);
     if (tune) bt->tune = *tune;
     bt->n = n;
@@ -1399,12 +1480,12 @@ int32_t fpt_batch_create(const fpt_scene_desc* descs, const fpt_run* runs, int32
     bt->max_table_words = max_tw;
     hipError_t e = hipGetDevice(&bt->device);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&bt->n_cu, hipDeviceAttributeMultiprocessorCount, bt->device);
-    if (e == hipSuccess) e = hipMalloc(&bt->d_params, sizeof(KParams) * n);
-    if (e == hipSuccess) e = hipMalloc(&bt->d_tables, std::max<size_t>(4, tables.size() * 4));
-    if (e == hipSuccess) e = hipMalloc(&bt->d_toff, 4 * (size_t)n);
-    if (e == hipSuccess) e = hipMalloc(&bt->d_wscale, 4 * (size_t)n);
-    if (e == hipSuccess) e = hipMalloc(&bt->d_counts, 4 * (size_t)n * bt->hist_words);
-    if (e == hipSuccess) e = hipMalloc(&bt->d_counter, 64);
+    if (e == hipSuccess) e = dev_malloc((void**)&bt->d_params, sizeof(KParams) * n);
+    if (e == hipSuccess) e = dev_malloc((void**)&bt->d_tables, std::max<size_t>(4, tables.size() * 4));
+    if (e == hipSuccess) e = dev_malloc((void**)&bt->d_toff, 4 * (size_t)n);
+    if (e == hipSuccess) e = dev_malloc((void**)&bt->d_wscale, 4 * (size_t)n);
+    if (e == hipSuccess) e = dev_malloc((void**)&bt->d_counts, 4 * (size_t)n * bt->hist_words);
+    if (e == hipSuccess) e = dev_malloc((void**)&bt->d_counter, 64);
     if (e == hipSuccess) e = hipMemcpy(bt->d_params, params.data(), sizeof(KParams) * n, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(bt->d_tables, tables.data(), tables.size() * 4, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(bt->d_toff, toff.data(), 4 * (size_t)n, hipMemcpyHostToDevice);
@@ -1421,6 +1502,22 @@ int32_t fpt_batch_create(const fpt_scene_desc* descs, const fpt_run* runs, int32
     *out = bt;
     return FPT_OK;
 }
+
+int32_t batch_create(const fpt_scene_desc* descs, const fpt_run* runs, int32_t n, const fpt_tune* tune,
+                     fpt_batch** out) {
+    fpt_batch* bt = new_object<fpt_batch>();
+    if (!bt) return set_err(FPT_E_NOMEM, "host allocation");
+    try {
+        return batch_setup(bt, descs, runs, n, tune, out);  // frees bt on its failure paths
+    } catch (...) {
+        fpt_batch_destroy(bt);
+        throw;
+    }
+}
+
+}  // namespace
+
+extern "C" {
 
 int32_t fpt_batch_render(fpt_batch* bt, float* films, uint64_t* tallies, void* stream) {
     if (!bt || !films) return set_err(FPT_E_INVALID, "NULL argument");
