@@ -39,8 +39,13 @@ enum { PEND_NONE = 0, PEND_MEDIUM = 1, PEND_SURFACE = 2, PEND_SOURCE = 3 };
 // Philox4x32-10 (Salmon et al., SC'11): ten rounds of two 32x32->64 products;
 // the high halves are xor-ed with the other counter words and the round key,
 // which advances by the two Weyl increments.  The key is uniform per launch
-// (kept in scalar registers); the products map to v_mad_u64_u32.
+// (kept in scalar registers); the products map to v_mad_u64_u32.  The empty
+// asm makes the key opaque at every call, so the ten round keys are formed
+// by scalar adds where they are used: hoisted out of the persistent loop
+// they occupied 20 scalar registers, which spilled to VGPR lanes and came
+// back through one v_readlane (a vector instruction) per round.
 DEV uint4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0, uint32_t k1) {
+    asm volatile("" : "+s"(k0), "+s"(k1));
 #pragma unroll
     for (int i = 0; i < 10; ++i) {
         const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
@@ -59,6 +64,11 @@ DEV uint4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0
 
 // 24 high bits -> [0,1), exact in fp32.
 DEV float u24(uint32_t x) { return (float)(x >> 8) * 5.9604644775390625e-08f; }
+// -ln(1 - u) for u = u24(.) in [0, 1): the hardware base-2 logarithm times
+// ln 2.  1 - u >= 2^-24 is a normal number, so the range reduction and the
+// compensated ln 2 product of the library logarithm (about ten more
+// instructions, under 1 ulp of difference) are not needed.
+DEV float neg_log1m(float u) { return -0.693147182f * __builtin_amdgcn_logf(1.f - u); }
 DEV uint32_t rr_bits(const uint4 r) {
     return ((r.x & 0xFFu) << 16) | ((r.y & 0xFFu) << 8) | (r.z & 0xFFu);
 }
@@ -763,7 +773,7 @@ DEV void block_walk(const KParams& P, const KBuffers& B, const uint32_t* T, cons
     const uint32_t vk = Q.v + 1u + pos;
     const uint4 r = philox(Q.pid, vk, 0u, 0u, P.key0, P.key1);
     const float u0 = u24(r.x), u1 = u24(r.y), u2 = u24(r.z), u3 = u24(r.w);
-    const float tk = -__logf(1.f - u0) * Q.inv;
+    const float tk = neg_log1m(u0) * Q.inv;
     const bool scat = u1 * Q.st < Q.ss;
     float sp, cp;
     sincos_rev(u3, &sp, &cp);
@@ -959,7 +969,7 @@ DEV void deep_half(const KParams& P, const Lane& Q, uint32_t v0, uint32_t lane, 
     const uint32_t vk = v0 + 1u + lane;
     const uint4 r = philox(Q.pid, vk, 0u, 0u, P.key0, P.key1);
     const float u0 = u24(r.x), u1 = u24(r.y), u2 = u24(r.z), u3 = u24(r.w);
-    const float tk = -__logf(1.f - u0) * Q.inv;
+    const float tk = neg_log1m(u0) * Q.inv;
     const bool scat = u1 * Q.st < Q.ss;
     float sp, cp;
     sincos_rev(u3, &sp, &cp);
@@ -1284,347 +1294,359 @@ DEV void advance(const KParams& P, const KBuffers& B, const WaveCtx& C, WalkStat
             }
         }
     };
-    if (alive && !full) {
-        const bool start = fresh;
-        bool step = false;
-        if (!start) {
-            L.v++;
-            if (REC && P.max_vertices && L.v >= P.max_vertices) {
-                exit_code = FPT_EXIT_TRUNC;
-            } else if (L.v >= kMaxPathVertices) {
-                exit_code = FPT_EXIT_SCAP;  // hard bound: every wave's loop terminates
+    // ---- vertex 0 of every path assigned in this iteration: the light (eq. 12;
+    // counter (pid, 0): call 0 picks the excitation line and, on a quad, the
+    // point, call 1 the direction).  Its camera connection is made at once and
+    // the path takes its first flight in the same iteration, below, so a new
+    // path costs no iteration of its own.
+    if (alive && fresh) {
+        cnt.vertices++;
+        const uint4 r = philox(L.pid, 0u, 0u, 0u, P.key0, P.key1);
+        const float u0 = u24(r.x), u1 = u24(r.y), u2 = u24(r.z);
+        L.nsc = 0;
+        L.nem = 0;
+        L.comp = 0;
+        if constexpr (kGloss) L.wgt = 1.f;
+        L.batch = L.pid % P.batches;
+        L.splat_sum = 0.f;
+        int line = 0;
+        for (; line < P.n_lines - 1; ++line)
+            if (u0 < P.line_cum[line]) break;
+        L.lam = P.line_bin[line];
+        if constexpr (ADJ) {
+#pragma unroll
+            for (int i = 0; i < kMaxNP; ++i) A.S[i * 64] = 0.f;
+        }
+        bool reflected = false;  // off a refractive body on entry
+        if (P.light == FPT_LIGHT_BEAM) {
+            L.x[0] = P.lpos[0]; L.x[1] = P.lpos[1]; L.x[2] = P.lpos[2];
+            L.w[0] = P.ldir[0]; L.w[1] = P.ldir[1]; L.w[2] = P.ldir[2];
+            L.region = 0;
+            if constexpr (kBody) {
+                if (P.ior != 1.f) {
+                    // entering a refractive body: Fresnel reflection (the path
+                    // leaves at once) or refraction by Snell's law; u1 decides
+                    float nb[3], ct;
+                    const float ws[3] = {-L.w[0], -L.w[1], -L.w[2]};
+                    body_normal<GEOM>(P, L.x, ws, nb);
+                    const float ci = -dot3(L.w, nb);
+                    if (u1 < fresnel(ci, 1.f, P.ior, ct)) {
+                        mirror(L.w, nb);
+                        lds_count(tally, FPT_T_WALL_REFLECT);
+                        reflected = true;
+                    } else {
+                        const float eta = __builtin_amdgcn_rcpf(P.ior), k = eta * ci - ct;
+                        float t3[3];
+#pragma unroll
+                        for (int i = 0; i < 3; ++i) t3[i] = eta * L.w[i] + k * nb[i];
+                        const float s = __builtin_amdgcn_rsqf(dot3(t3, t3));
+                        L.w[0] = t3[0] * s; L.w[1] = t3[1] * s; L.w[2] = t3[2] * s;
+                    }
+                }
+            }
+        } else {
+            const uint4 r1 = philox(L.pid, 0u, 1u, 0u, P.key0, P.key1);
+            const float ua = u24(r1.x), ub = u24(r1.y);
+            float sp, cp;
+            sincos_rev(ub, &sp, &cp);
+            if (P.light == FPT_LIGHT_POINT) {
+                L.x[0] = P.lpos[0]; L.x[1] = P.lpos[1]; L.x[2] = P.lpos[2];
+                const float ct = 1.f - 2.f * ua;
+                const float st = 2.f * fsqrt(ua * (1.f - ua));
+                L.w[0] = st * cp; L.w[1] = st * sp; L.w[2] = ct;
+                L.region = 0;
             } else {
-                step = true;
+                const float a = u1, b = u2;
+                const float sr = fsqrt(ua), cz = fsqrt(1.f - ua);
+                const float lx = sr * cp, ly = sr * sp;
+#pragma unroll
+                for (int i = 0; i < 3; ++i) {
+                    L.x[i] = P.lpos[i] + a * P.lu[i] + b * P.lv[i];
+                    L.w[i] = lx * P.lt1[i] + ly * P.lt2[i] + cz * P.ln[i];
+                }
+                L.region = -1;
             }
         }
-        if (start || step) {
+        L.medium = (GEOM == FPT_GEOM_BOX) ? -1 : P.body_medium;
+        L.sc[0] = L.sc[1] = L.sc[2] = 0.f;
+        L.sr2 = 0.f;
+        load_medium(P, T, L);
+        if (reflected) escape();
+        if (pinhole && P.light == FPT_LIGHT_QUAD) {
+            pend = PEND_SOURCE;
+            nrm[0] = P.ln[0]; nrm[1] = P.ln[1]; nrm[2] = P.ln[2];
+            rrb = rr_bits(r);
+        }
+    }
+    // ---- convergent splat section: the pending camera connection of every
+    // lane (the light vertex's, then the step's).  `medium`: the vertex may be
+    // a medium vertex (not for light vertices).
+    auto connect = [&](const bool medium) {
+        if constexpr (DEFER) {
+            if (pinhole) {
+                bool want = pend != PEND_NONE && alive && (exit_code < 0 || (kGloss && W.gdie)) &&
+                            !(P.fluo_only && L.comp == 0);
+                const bool opq = want && medium && pend == PEND_MEDIUM &&
+                                 opaque_to_eye(L.x, L.region, L.st, L.sc, L.sr2);
+                count_opaque(tally, cnt, opq);
+                want = want && !opq;
+                float sw = 1.f;
+                if constexpr (kGloss) sw = W.gspl ? W.sw : L.wgt;
+                splat_defer<kGloss>(B, W.q, want, L.x, sq_word_a(rrb, pend, W.face, L.comp),
+                                    (uint32_t)L.lam | (L.batch << 16), sw, exhausted);
+            }
+        } else if constexpr (GEOM == FPT_GEOM_BOX) {
+            if (pinhole && pend != PEND_NONE && alive && (exit_code < 0 || (kGloss && W.gdie))) {
+                if (!(P.fluo_only && L.comp == 0)) {
+                    float sw = 1.f;
+                    if constexpr (kGloss) sw = W.gspl ? W.sw : L.wgt;
+                    const SplatOut so = splat_eval(T, SP, L.x, L.lam, L.comp, L.batch, pend, nrm, rrb, sw);
+                    if (so.status == 0) {
+                        cnt.splat_hit++;
+                        L.splat_sum += so.v;
+                        if constexpr (MODE == MODE_FWD)
+                        if (so.v != 0.f) unsafeAtomicAdd(&B.film[so.idx], so.v);  // +0 changes nothing
+                        if constexpr (ADJ) {
+                            const float g = B.gfilm[so.idx];
+                            const float gv = g * so.v;
+#pragma unroll
+                            for (int i = 0; i < kMaxNP; ++i)
+                                if (i < P.np) G[i] += gv * A.S[i * 64];
+                            // d v / d theta = -v sum_s chord_s d sigma_t(m_s) / d theta
+                            const float e0 = P.eye[0] - L.x[0], e1 = P.eye[1] - L.x[1], e2 = P.eye[2] - L.x[2];
+                            const float dist = fsqrt(e0 * e0 + e1 * e1 + e2 * e2);
+                            const float id = __builtin_amdgcn_rcpf(dist);
+                            const float wc[3] = {e0 * id, e1 * id, e2 * id};
+                            for (int s = 0; s < P.n_spheres; ++s) {
+                                const float len = chord_len(SP[s], L.x, wc, dist);
+                                if (!(len > 0.f)) continue;
+                                const int m = SP[s].medium;
+                                const int mb = P.off_med + m * kMedWords;
+                                const float c = -gv * len;
+                                adj_add(A.Gx, wi(T, mb + MW_PSS), c);
+                                const int nd = wi(T, mb + MW_NDYES);
+                                for (int j = 0; j < nd; ++j)
+                                    adj_add(A.Gx, wi(T, mb + MW_PC + j),
+                                            c * wf(T, P.off_kap + (m * P.kap_stride + j) * P.N + L.lam));
+                            }
+                        }
+                    } else {
+                        lds_count(tally, so.status == 2 ? FPT_T_SPLAT_RR_KILL : FPT_T_SPLAT_MISS);
+                    }
+                }
+            }
+        }
+        pend = PEND_NONE;
+        if constexpr (kGloss) {
+            W.gspl = false;
+            W.gdie = false;
+        }
+    };
+    if (__ballot(pend != PEND_NONE)) {
+        connect(false);
+        // the ring holds fewer than 64 entries before each append
+        if constexpr (DEFER) {
+            if (pinhole) sq_drain(P, B.film, T, SP, tally, W.q, cnt, lane, false);
+        }
+    }
+    // ---- one step for every live lane: the next vertex, from the counter
+    // (pid, vertex) -- call 0 for the flight, the event and a new direction,
+    // call 1 for a dye's quantum-yield test and emitted wavelength
+    if (alive && !full && exit_code < 0) {
+        L.v++;
+        bool step = false;
+        if (REC && P.max_vertices && L.v >= P.max_vertices) {
+            exit_code = FPT_EXIT_TRUNC;
+        } else if (L.v >= kMaxPathVertices) {
+            exit_code = FPT_EXIT_SCAP;  // hard bound: every wave's loop terminates
+        } else {
+            step = true;
+        }
+        if (step) {
             cnt.vertices++;
-            const uint32_t vc = start ? 0u : L.v;
-            const uint4 r = philox(L.pid, vc, 0u, 0u, P.key0, P.key1);
+            const uint4 r = philox(L.pid, L.v, 0u, 0u, P.key0, P.key1);
             const float u0 = u24(r.x), u1 = u24(r.y), u2 = u24(r.z), u3 = u24(r.w);
             float dir_sin = 0.f, dir_cos = 0.f;  // polar sine/cosine of a new direction
             int frame = -1;                      // -1 world axes, else wall face
             float gloss_n = 0.f;                 // Phong exponent of a glossy wall reflection
             bool need1 = false;                  // the vertex draws call 1 of its counter too
-            int dye = 0;                         // the absorbing dye (step lanes)
-            if (start) {
-                // vertex 0: the light (eq. 12: light point, excitation wavelength)
-                L.nsc = 0;
-                L.nem = 0;
-                L.comp = 0;
-                if constexpr (kGloss) L.wgt = 1.f;
-                L.batch = L.pid % P.batches;
-                L.splat_sum = 0.f;
-                int line = 0;
-                for (; line < P.n_lines - 1; ++line)
-                    if (u0 < P.line_cum[line]) break;
-                L.lam = P.line_bin[line];
-                need1 = P.light != FPT_LIGHT_BEAM;
-                if constexpr (ADJ) {
-#pragma unroll
-                    for (int i = 0; i < kMaxNP; ++i) A.S[i * 64] = 0.f;
-                }
-            } else {
-                // eq. 6: free flight with density sigma_t exp(-sigma_t t)
-                const float tf = (L.inv == kInf) ? kInf : -__logf(1.f - u0) * L.inv;
-                const Hit h = next_surface<GEOM>(P, SP, L, GEOM == FPT_GEOM_BOX && L.v == 1u);
-                const bool collide = tf < h.d;
-                const float len = collide ? tf : h.d;
-                if (len < kInf) {
-                    L.x[0] += len * L.w[0];
-                    L.x[1] += len * L.w[1];
-                    L.x[2] += len * L.w[2];
-                    score_length<MODE>(P, T, L, A, len);
-                }
-                if (!collide) snap_to_plane<GEOM>(P, L, h);
-                if (collide) {
-                    const float s = u1 * L.st;
-                    if (s < L.ss) {
-                        // elastic scattering, isotropic phase function (eq. 2)
-                        ev = EV_SCATTER;
-                        if constexpr (ADJ)
-                            adj_add(A.S, wi(T, P.off_med + L.medium * kMedWords + MW_PSS),
-                                    wf(T, P.off_med + L.medium * kMedWords + MW_INV_SS));
-                        L.nsc++;
-                        cnt.scatters++;
-                        if (!P.exc_scatter && L.nem == 0u) exit_code = FPT_EXIT_EXCSCAT;
-                        else if (L.nsc > P.max_scatter) exit_code = FPT_EXIT_SCAP;
-                        else {
-                            dir_cos = 1.f - 2.f * u2;
-                            dir_sin = 2.f * fsqrt(u2 * (1.f - u2));
-                            pend = PEND_MEDIUM;
-                        }
-                    } else if (s < L.thr_bg || L.ndy == 0) {
-                        ev = EV_BG;
-                        exit_code = FPT_EXIT_BG;
-                    } else {
-                        // a fluorescent particle: which dye slot (sec. 4.1)
-                        ev = EV_DYE;
-                        int j = 0;
-                        const int cb = P.off_cum + L.medium * P.cum_stride * P.N + L.lam;
-                        for (; j < L.ndy - 1; ++j)
-                            if (s < wf(T, cb + j * P.N)) break;
-                        const int mb = P.off_med + L.medium * kMedWords;
-                        if constexpr (ADJ) adj_add(A.S, wi(T, mb + MW_PC + j), wf(T, mb + MW_INV_C + j));
-                        lds_count(tally, FPT_T_DYE_ABS);
-                        if (L.nem >= P.max_emissions) {
-                            exit_code = FPT_EXIT_KCAP;
-                        } else {
-                            dye = wi(T, mb + MW_DYE + j);
-                            need1 = true;  // quantum-yield test and emitted wavelength
-                        }
-                    }
-                } else {
-                    ev = h.ev;
-                    bool refl = false;
-                    if constexpr (kBody) {
-                        if (ev == EV_ESC && h.d < kInf && P.ior != 1.f) {
-                            // the body's dielectric boundary: specular reflection with
-                            // the Fresnel probability (total internal reflection beyond
-                            // the critical angle), else the path crosses out; u1 decides
-                            float nb[3], ct;
-                            body_normal<GEOM>(P, L.x, L.w, nb);
-                            if (u1 < fresnel(dot3(L.w, nb), P.ior, 1.f, ct)) {
-                                mirror(L.w, nb);
-                                lds_count(tally, FPT_T_WALL_REFLECT);
-                                refl = true;
-                            }
-                        }
-                    }
-                    if (refl) {
-                        // the path stays in the body with the mirrored direction
-                    } else if (ev == EV_ESC || ev == EV_INF) {
-                        escape();
-                    } else if (ev == EV_LIGHT) {
-                        exit_code = FPT_EXIT_LIGHT;
-                    } else if (ev == EV_WALL) {
-                        const float rho = h.idx >= 0 ? wf(T, P.off_rho + h.idx * P.N + L.lam) : 0.f;
-                        if (!(u1 < rho)) {
-                            exit_code = FPT_EXIT_WALL;
-                        } else {
-                            lds_count(tally, FPT_T_WALL_REFLECT);
-                            if (!P.exc_scatter && L.nem == 0u) {
-                                // direct excitation only: an elastic event before the emission
-                                exit_code = FPT_EXIT_EXCSCAT;
-                            } else {
-                                // Lambertian reflection about the wall's inward normal
-                                // (or the glossy lobe, below)
-                                dir_sin = fsqrt(u2);
-                                dir_cos = fsqrt(1.f - u2);
-                                frame = h.idx;
-                                W.face = h.idx;
-                                pend = PEND_SURFACE;
-                                if constexpr (kGloss) gloss_n = wf(T, P.off_gloss + h.idx);
-                            }
-                        }
-                    } else {
-                        // index-matched interface: change medium, keep direction
-                        lds_count(tally, FPT_T_CROSSINGS);
-                        if constexpr (GEOM == FPT_GEOM_BOX) {
-                            L.region = (ev == EV_ENTER) ? h.idx : -1;
-                            L.medium = -1;
-                            if (L.region >= 0) {
-                                const KSphere& sp = SP[L.region];
-                                L.sc[0] = sp.c[0];
-                                L.sc[1] = sp.c[1];
-                                L.sc[2] = sp.c[2];
-                                L.sr2 = sp.r2;
-                                L.medium = sp.medium;
-                            }
-                            load_medium(P, T, L);
-                        }
-                    }
-                }
+            int dye = 0;                         // the absorbing dye
+            // eq. 6: free flight with density sigma_t exp(-sigma_t t)
+            const float tf = (L.inv == kInf) ? kInf : neg_log1m(u0) * L.inv;
+            const Hit h = next_surface<GEOM>(P, SP, L, GEOM == FPT_GEOM_BOX && L.v == 1u);
+            const bool collide = tf < h.d;
+            const float len = collide ? tf : h.d;
+            if (len < kInf) {
+                L.x[0] += len * L.w[0];
+                L.x[1] += len * L.w[1];
+                L.x[2] += len * L.w[2];
+                score_length<MODE>(P, T, L, A, len);
             }
-            // call 1 of the counter: the light's direction (and position on a
-            // quad), or the quantum-yield test and emitted wavelength of a dye
-            uint4 r1 = make_uint4(0u, 0u, 0u, 0u);
-            if (need1) r1 = philox(L.pid, vc, 1u, 0u, P.key0, P.key1);
-            if (start) {
-                bool reflected = false;  // off a refractive body on entry
-                if (P.light == FPT_LIGHT_BEAM) {
-                    L.x[0] = P.lpos[0]; L.x[1] = P.lpos[1]; L.x[2] = P.lpos[2];
-                    L.w[0] = P.ldir[0]; L.w[1] = P.ldir[1]; L.w[2] = P.ldir[2];
-                    L.region = 0;
-                    if constexpr (kBody) {
-                        if (P.ior != 1.f) {
-                            // entering a refractive body: Fresnel reflection (the path
-                            // leaves at once) or refraction by Snell's law; u1 decides
-                            float nb[3], ct;
-                            const float ws[3] = {-L.w[0], -L.w[1], -L.w[2]};
-                            body_normal<GEOM>(P, L.x, ws, nb);
-                            const float ci = -dot3(L.w, nb);
-                            if (u1 < fresnel(ci, 1.f, P.ior, ct)) {
-                                mirror(L.w, nb);
-                                lds_count(tally, FPT_T_WALL_REFLECT);
-                                reflected = true;
-                            } else {
-                                const float eta = __builtin_amdgcn_rcpf(P.ior), k = eta * ci - ct;
-                                float t3[3];
-#pragma unroll
-                                for (int i = 0; i < 3; ++i) t3[i] = eta * L.w[i] + k * nb[i];
-                                const float s = __builtin_amdgcn_rsqf(dot3(t3, t3));
-                                L.w[0] = t3[0] * s; L.w[1] = t3[1] * s; L.w[2] = t3[2] * s;
-                            }
-                        }
-                    }
-                } else {
-                    const float ua = u24(r1.x), ub = u24(r1.y);
-                    float sp, cp;
-                    sincos_rev(ub, &sp, &cp);
-                    if (P.light == FPT_LIGHT_POINT) {
-                        L.x[0] = P.lpos[0]; L.x[1] = P.lpos[1]; L.x[2] = P.lpos[2];
-                        const float ct = 1.f - 2.f * ua;
-                        const float st = 2.f * fsqrt(ua * (1.f - ua));
-                        L.w[0] = st * cp; L.w[1] = st * sp; L.w[2] = ct;
-                        L.region = 0;
-                    } else {
-                        const float a = u1, b = u2;
-                        const float sr = fsqrt(ua), cz = fsqrt(1.f - ua);
-                        const float lx = sr * cp, ly = sr * sp;
-#pragma unroll
-                        for (int i = 0; i < 3; ++i) {
-                            L.x[i] = P.lpos[i] + a * P.lu[i] + b * P.lv[i];
-                            L.w[i] = lx * P.lt1[i] + ly * P.lt2[i] + cz * P.ln[i];
-                        }
-                        L.region = -1;
-                    }
-                }
-                L.medium = (GEOM == FPT_GEOM_BOX) ? -1 : P.body_medium;
-                L.sc[0] = L.sc[1] = L.sc[2] = 0.f;
-                L.sr2 = 0.f;
-                load_medium(P, T, L);
-                if (reflected) escape();
-                if (pinhole && P.light == FPT_LIGHT_QUAD) {
-                    pend = PEND_SOURCE;
-                    nrm[0] = P.ln[0]; nrm[1] = P.ln[1]; nrm[2] = P.ln[2];
-                    rrb = rr_bits(r);
-                }
-            } else {
-                if (need1) {
-                    const int db = P.off_dye + dye * kDyeWords;
-                    const float uq = u24(r1.x);
-                    if (!(uq < wf(T, db + DW_QY))) {
-                        if constexpr (ADJ) adj_add(A.S, wi(T, db + DW_PQ), -wf(T, db + DW_INV_1MQY));
-                        exit_code = FPT_EXIT_NONRAD;
-                    } else {
-                        if constexpr (ADJ) adj_add(A.S, wi(T, db + DW_PQ), wf(T, db + DW_INV_QY));
-                        // eq. 10: emitted wavelength from the emission CDF,
-                        // independent of the excitation wavelength (sec. 2.1)
-                        const float ul = u24(r1.y);
-                        const uint32_t* cdf = T + P.off_cdf + dye * P.N;
-                        int lo = 0, hi = P.N - 1;
-                        while (lo < hi) {
-                            const int mid = (lo + hi) >> 1;
-                            if (ul < __uint_as_float(cdf[mid])) hi = mid;
-                            else lo = mid + 1;
-                        }
-                        L.lam = lo;
-                        load_sigma(P, T, L);
-                        L.nem++;
-                        L.comp = 1;
-                        lds_count(tally, FPT_T_EMISSIONS);
+            if (!collide) snap_to_plane<GEOM>(P, L, h);
+            if (collide) {
+                const float s = u1 * L.st;
+                if (s < L.ss) {
+                    // elastic scattering, isotropic phase function (eq. 2)
+                    ev = EV_SCATTER;
+                    if constexpr (ADJ)
+                        adj_add(A.S, wi(T, P.off_med + L.medium * kMedWords + MW_PSS),
+                                wf(T, P.off_med + L.medium * kMedWords + MW_INV_SS));
+                    L.nsc++;
+                    cnt.scatters++;
+                    if (!P.exc_scatter && L.nem == 0u) exit_code = FPT_EXIT_EXCSCAT;
+                    else if (L.nsc > P.max_scatter) exit_code = FPT_EXIT_SCAP;
+                    else {
                         dir_cos = 1.f - 2.f * u2;
                         dir_sin = 2.f * fsqrt(u2 * (1.f - u2));
                         pend = PEND_MEDIUM;
                     }
-                }
-                if (pend != PEND_NONE && exit_code < 0) {
-                    float sp, cp;
-                    sincos_rev(u3, &sp, &cp);
-                    const float a = dir_sin * cp, b = dir_sin * sp;
-                    if (kGloss && gloss_n > 0.f) {
-                        float lobe = 0.f, fac = 0.f;
-                        const bool on = glossy_reflect(gloss_n, frame, u2, sp, cp, L.x, L.w, nrm, lobe, fac);
-                        W.sw = L.wgt * lobe;
-                        W.gspl = true;
-                        if (on) {
-                            L.wgt *= fac;
-                        } else {
-                            exit_code = FPT_EXIT_WALL;
-                            W.gdie = true;
-                        }
-                    } else if (frame < 0) {
-                        L.w[0] = a; L.w[1] = b; L.w[2] = dir_cos;
+                } else if (s < L.thr_bg || L.ndy == 0) {
+                    ev = EV_BG;
+                    exit_code = FPT_EXIT_BG;
+                } else {
+                    // a fluorescent particle: which dye slot (sec. 4.1)
+                    ev = EV_DYE;
+                    int j = 0;
+                    const int cb = P.off_cum + L.medium * P.cum_stride * P.N + L.lam;
+                    for (; j < L.ndy - 1; ++j)
+                        if (s < wf(T, cb + j * P.N)) break;
+                    const int mb = P.off_med + L.medium * kMedWords;
+                    if constexpr (ADJ) adj_add(A.S, wi(T, mb + MW_PC + j), wf(T, mb + MW_INV_C + j));
+                    lds_count(tally, FPT_T_DYE_ABS);
+                    if (L.nem >= P.max_emissions) {
+                        exit_code = FPT_EXIT_KCAP;
                     } else {
-                        // wall frame: normal n = sg e_ax, tangents e_(ax+1), sg e_(ax+2)
-                        const int ax = frame >> 1;
-                        const float sg = (frame & 1) ? -1.f : 1.f;
-                        const float c = sg * dir_cos, bb = sg * b;
-                        L.w[0] = ax == 0 ? c : (ax == 1 ? bb : a);
-                        L.w[1] = ax == 0 ? a : (ax == 1 ? c : bb);
-                        L.w[2] = ax == 0 ? bb : (ax == 1 ? a : c);
-                        nrm[0] = ax == 0 ? sg : 0.f;
-                        nrm[1] = ax == 1 ? sg : 0.f;
-                        nrm[2] = ax == 2 ? sg : 0.f;
+                        dye = wi(T, mb + MW_DYE + j);
+                        need1 = true;  // quantum-yield test and emitted wavelength
                     }
-                    rrb = rr_bits(r);
-                } else {
-                    pend = PEND_NONE;
                 }
-            }
-        }
-    }
-
-    // ---- convergent splat section
-    if constexpr (DEFER) {
-        if (pinhole) {
-            bool want = pend != PEND_NONE && alive && (exit_code < 0 || (kGloss && W.gdie)) &&
-                        !(P.fluo_only && L.comp == 0);
-            const bool opq = want && pend == PEND_MEDIUM && opaque_to_eye(L.x, L.region, L.st, L.sc, L.sr2);
-            count_opaque(tally, cnt, opq);
-            want = want && !opq;
-            float sw = 1.f;
-            if constexpr (kGloss) sw = W.gspl ? W.sw : L.wgt;
-            splat_defer<kGloss>(B, W.q, want, L.x, sq_word_a(rrb, pend, W.face, L.comp),
-                                (uint32_t)L.lam | (L.batch << 16), sw, exhausted);
-        }
-    } else if constexpr (GEOM == FPT_GEOM_BOX) {
-        if (pinhole && pend != PEND_NONE && alive && (exit_code < 0 || (kGloss && W.gdie))) {
-            if (!(P.fluo_only && L.comp == 0)) {
-                float sw = 1.f;
-                if constexpr (kGloss) sw = W.gspl ? W.sw : L.wgt;
-                const SplatOut so = splat_eval(T, SP, L.x, L.lam, L.comp, L.batch, pend, nrm, rrb, sw);
-                if (so.status == 0) {
-                    cnt.splat_hit++;
-                    L.splat_sum += so.v;
-                    if constexpr (MODE == MODE_FWD)
-                    if (so.v != 0.f) unsafeAtomicAdd(&B.film[so.idx], so.v);  // +0 changes nothing
-                    if constexpr (ADJ) {
-                        const float g = B.gfilm[so.idx];
-                        const float gv = g * so.v;
-#pragma unroll
-                        for (int i = 0; i < kMaxNP; ++i)
-                            if (i < P.np) G[i] += gv * A.S[i * 64];
-                        // d v / d theta = -v sum_s chord_s d sigma_t(m_s) / d theta
-                        const float e0 = P.eye[0] - L.x[0], e1 = P.eye[1] - L.x[1], e2 = P.eye[2] - L.x[2];
-                        const float dist = fsqrt(e0 * e0 + e1 * e1 + e2 * e2);
-                        const float id = __builtin_amdgcn_rcpf(dist);
-                        const float wc[3] = {e0 * id, e1 * id, e2 * id};
-                        for (int s = 0; s < P.n_spheres; ++s) {
-                            const float len = chord_len(SP[s], L.x, wc, dist);
-                            if (!(len > 0.f)) continue;
-                            const int m = SP[s].medium;
-                            const int mb = P.off_med + m * kMedWords;
-                            const float c = -gv * len;
-                            adj_add(A.Gx, wi(T, mb + MW_PSS), c);
-                            const int nd = wi(T, mb + MW_NDYES);
-                            for (int j = 0; j < nd; ++j)
-                                adj_add(A.Gx, wi(T, mb + MW_PC + j),
-                                        c * wf(T, P.off_kap + (m * P.kap_stride + j) * P.N + L.lam));
+            } else {
+                ev = h.ev;
+                bool refl = false;
+                if constexpr (kBody) {
+                    if (ev == EV_ESC && h.d < kInf && P.ior != 1.f) {
+                        // the body's dielectric boundary: specular reflection with
+                        // the Fresnel probability (total internal reflection beyond
+                        // the critical angle), else the path crosses out; u1 decides
+                        float nb[3], ct;
+                        body_normal<GEOM>(P, L.x, L.w, nb);
+                        if (u1 < fresnel(dot3(L.w, nb), P.ior, 1.f, ct)) {
+                            mirror(L.w, nb);
+                            lds_count(tally, FPT_T_WALL_REFLECT);
+                            refl = true;
+                        }
+                    }
+                }
+                if (refl) {
+                    // the path stays in the body with the mirrored direction
+                } else if (ev == EV_ESC || ev == EV_INF) {
+                    escape();
+                } else if (ev == EV_LIGHT) {
+                    exit_code = FPT_EXIT_LIGHT;
+                } else if (ev == EV_WALL) {
+                    const float rho = h.idx >= 0 ? wf(T, P.off_rho + h.idx * P.N + L.lam) : 0.f;
+                    if (!(u1 < rho)) {
+                        exit_code = FPT_EXIT_WALL;
+                    } else {
+                        lds_count(tally, FPT_T_WALL_REFLECT);
+                        if (!P.exc_scatter && L.nem == 0u) {
+                            // direct excitation only: an elastic event before the emission
+                            exit_code = FPT_EXIT_EXCSCAT;
+                        } else {
+                            // Lambertian reflection about the wall's inward normal
+                            // (or the glossy lobe, below)
+                            dir_sin = fsqrt(u2);
+                            dir_cos = fsqrt(1.f - u2);
+                            frame = h.idx;
+                            W.face = h.idx;
+                            pend = PEND_SURFACE;
+                            if constexpr (kGloss) gloss_n = wf(T, P.off_gloss + h.idx);
                         }
                     }
                 } else {
-                    lds_count(tally, so.status == 2 ? FPT_T_SPLAT_RR_KILL : FPT_T_SPLAT_MISS);
+                    // index-matched interface: change medium, keep direction
+                    lds_count(tally, FPT_T_CROSSINGS);
+                    if constexpr (GEOM == FPT_GEOM_BOX) {
+                        L.region = (ev == EV_ENTER) ? h.idx : -1;
+                        L.medium = -1;
+                        if (L.region >= 0) {
+                            const KSphere& sp = SP[L.region];
+                            L.sc[0] = sp.c[0];
+                            L.sc[1] = sp.c[1];
+                            L.sc[2] = sp.c[2];
+                            L.sr2 = sp.r2;
+                            L.medium = sp.medium;
+                        }
+                        load_medium(P, T, L);
+                    }
                 }
+            }
+            uint4 r1 = make_uint4(0u, 0u, 0u, 0u);
+            if (need1) r1 = philox(L.pid, L.v, 1u, 0u, P.key0, P.key1);
+            if (need1) {
+                const int db = P.off_dye + dye * kDyeWords;
+                const float uq = u24(r1.x);
+                if (!(uq < wf(T, db + DW_QY))) {
+                    if constexpr (ADJ) adj_add(A.S, wi(T, db + DW_PQ), -wf(T, db + DW_INV_1MQY));
+                    exit_code = FPT_EXIT_NONRAD;
+                } else {
+                    if constexpr (ADJ) adj_add(A.S, wi(T, db + DW_PQ), wf(T, db + DW_INV_QY));
+                    // eq. 10: emitted wavelength from the emission CDF,
+                    // independent of the excitation wavelength (sec. 2.1)
+                    const float ul = u24(r1.y);
+                    const uint32_t* cdf = T + P.off_cdf + dye * P.N;
+                    int lo = 0, hi = P.N - 1;
+                    while (lo < hi) {
+                        const int mid = (lo + hi) >> 1;
+                        if (ul < __uint_as_float(cdf[mid])) hi = mid;
+                        else lo = mid + 1;
+                    }
+                    L.lam = lo;
+                    load_sigma(P, T, L);
+                    L.nem++;
+                    L.comp = 1;
+                    lds_count(tally, FPT_T_EMISSIONS);
+                    dir_cos = 1.f - 2.f * u2;
+                    dir_sin = 2.f * fsqrt(u2 * (1.f - u2));
+                    pend = PEND_MEDIUM;
+                }
+            }
+            if (pend != PEND_NONE && exit_code < 0) {
+                float sp, cp;
+                sincos_rev(u3, &sp, &cp);
+                const float a = dir_sin * cp, b = dir_sin * sp;
+                if (kGloss && gloss_n > 0.f) {
+                    float lobe = 0.f, fac = 0.f;
+                    const bool on = glossy_reflect(gloss_n, frame, u2, sp, cp, L.x, L.w, nrm, lobe, fac);
+                    W.sw = L.wgt * lobe;
+                    W.gspl = true;
+                    if (on) {
+                        L.wgt *= fac;
+                    } else {
+                        exit_code = FPT_EXIT_WALL;
+                        W.gdie = true;
+                    }
+                } else if (frame < 0) {
+                    L.w[0] = a; L.w[1] = b; L.w[2] = dir_cos;
+                } else {
+                    // wall frame: normal n = sg e_ax, tangents e_(ax+1), sg e_(ax+2)
+                    const int ax = frame >> 1;
+                    const float sg = (frame & 1) ? -1.f : 1.f;
+                    const float c = sg * dir_cos, bb = sg * b;
+                    L.w[0] = ax == 0 ? c : (ax == 1 ? bb : a);
+                    L.w[1] = ax == 0 ? a : (ax == 1 ? c : bb);
+                    L.w[2] = ax == 0 ? bb : (ax == 1 ? a : c);
+                    nrm[0] = ax == 0 ? sg : 0.f;
+                    nrm[1] = ax == 1 ? sg : 0.f;
+                    nrm[2] = ax == 2 ? sg : 0.f;
+                }
+                rrb = rr_bits(r);
+            } else {
+                pend = PEND_NONE;
             }
         }
     }
-    pend = PEND_NONE;
-    if constexpr (kGloss) {
-        W.gspl = false;
-        W.gdie = false;
-    }
+    connect(true);
 
     // ---- path end
     if (alive && exit_code >= 0) {
@@ -2263,7 +2285,7 @@ DEV int cam_step(const KParams& P, const uint32_t* S, const KSphere* SP, uint32_
     const uint4 r = philox(L.pid, L.v, 0u, 0u, P.key0, P.key1);
     const float u0 = u24(r.x), u1 = u24(r.y), u2 = u24(r.z), u3 = u24(r.w);
     // eq. 6: free flight at the emission wavelength
-    const float tf = (L.inv == kInf) ? kInf : -__logf(1.f - u0) * L.inv;
+    const float tf = (L.inv == kInf) ? kInf : neg_log1m(u0) * L.inv;
     const Hit h = next_surface<FPT_GEOM_BOX>(P, SP, L, false);
     const bool collide = tf < h.d;
     const float len = collide ? tf : h.d;
