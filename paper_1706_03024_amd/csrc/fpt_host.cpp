@@ -341,19 +341,19 @@ uint32_t fbits(float f) {
 
 // Builds the fp32 table image and the scene part of the kernel parameters.
 // Spheres whose every point passes a pinhole connection's geometric tests,
-// with a margin far above fp32 rounding, and whose medium can reach an optical
-// depth of kTauZero inside them (bit s of the result): the kernels may count a
-// connection from such a sphere that is opaque within the sphere itself as a
-// zero-valued hit without evaluating it.  A ball of centre c and radius r
-// passes when it lies inside each of these half-spaces through the eye with
-// clearance r (1 + 1e-3) + 1e-4 mm:
+// with a margin far above fp32 rounding (bit s of the result): a connection
+// from inside such a sphere is in the image, leaves through the open face and
+// misses the light quad, so the kernels need not evaluate those tests for it.
+// A ball of centre c and radius r passes when it lies inside each of these
+// half-spaces through the eye with clearance r (1 + 1e-3) + 1e-4 mm:
 //   - in front of the camera and inside the image: the planes through the eye
 //     of the image's four edges (fov);
 //   - through the open face: the planes through the eye and the face's four
-//     edges (the segment to the eye then crosses the face's plane inside it);
+//     edges (the segment to the eye then crosses the face's plane inside it,
+//     the eye lying outside the box beyond that plane);
 // and when the ball and the eye lie strictly on the same side of the light
 // quad's plane (the segment cannot cross the quad).
-uint32_t clear_spheres(const fpt_scene_desc& d, const std::vector<float>& st) {
+uint32_t clear_spheres(const fpt_scene_desc& d) {
     auto dot = [](const double* a, const double* b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; };
     auto unit = [](double* v) {
         const double n = std::sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
@@ -399,13 +399,13 @@ uint32_t clear_spheres(const fpt_scene_desc& d, const std::vector<float>& st) {
     double ln[3] = {0.0, 0.0, 0.0};
     cross3(d.light_u, d.light_v, ln);
     unit(ln);
+    // the eye outside the box, beyond the open face's plane
+    const double out = (d.open_face & 1) ? d.eye[ax] - plane : plane - d.eye[ax];
+    if (!(out >= 1e-4)) return 0u;
     uint32_t bits = 0u;
     for (int s = 0; s < d.n_spheres; ++s) {
         const fpt_sphere& sp = d.spheres[s];
         const double rad = sp.radius, clear = rad * (1.0 + 1e-3) + 1e-4;
-        float stmax = 0.f;
-        for (int k = 0; k < d.n_bins; ++k) stmax = std::max(stmax, st[(size_t)sp.medium * d.n_bins + k]);
-        if (!((double)stmax * 2.0 * rad >= (double)kTauZero)) continue;
         double c[3] = {sp.center[0] - d.eye[0], sp.center[1] - d.eye[1], sp.center[2] - d.eye[2]};
         bool ok = dot(c, f) >= clear;
         for (const auto& pl : planes) {
@@ -420,6 +420,61 @@ uint32_t clear_spheres(const fpt_scene_desc& d, const std::vector<float>& st) {
         if (ok) bits |= 1u << s;
     }
     return bits;
+}
+
+// Spheres whose medium reaches an optical depth of kTauZero across the
+// sphere at some wavelength (bit s): only there can a connection be opaque
+// within the sphere itself, which the kernels count as a zero-valued hit
+// without evaluating it.
+uint32_t opaque_capable(const fpt_scene_desc& d, const std::vector<float>& st) {
+    uint32_t bits = 0u;
+    for (int s = 0; s < d.n_spheres; ++s) {
+        const fpt_sphere& sp = d.spheres[s];
+        float stmax = 0.f;
+        for (int k = 0; k < d.n_bins; ++k) stmax = std::max(stmax, st[(size_t)sp.medium * d.n_bins + k]);
+        if ((double)stmax * 2.0 * sp.radius >= (double)kTauZero) bits |= 1u << s;
+    }
+    return bits;
+}
+
+// The spheres a segment from a point of sphere s to the eye can cross
+// (bit s' of occl[s]; s itself always).  Seen from the eye, sphere s fills
+// the cone of half-angle asin(r_s / |c_s - e|) about its centre's direction;
+// such a segment lies in that cone and ends nearer to the eye than
+// |c_s - e| + r_s.  Sphere s' is left out when its own cone is separated from
+// sphere s's by at least 1e-3 rad, or when all of it lies at least 1e-3 mm
+// beyond that distance; either way every such segment misses it by far more
+// than fp32 rounding, so the kernels' chord of s' is exactly 0 there.
+void sphere_occluders(const fpt_scene_desc& d, uint32_t* occl) {
+    for (int s = 0; s < FPT_MAX_SPHERES; ++s) occl[s] = 0u;
+    double a[FPT_MAX_SPHERES][3], dist[FPT_MAX_SPHERES], half[FPT_MAX_SPHERES];
+    bool cone[FPT_MAX_SPHERES];
+    for (int s = 0; s < d.n_spheres; ++s) {
+        const fpt_sphere& sp = d.spheres[s];
+        double n2 = 0.0;
+        for (int i = 0; i < 3; ++i) {
+            a[s][i] = sp.center[i] - d.eye[i];
+            n2 += a[s][i] * a[s][i];
+        }
+        dist[s] = std::sqrt(n2);
+        cone[s] = dist[s] > sp.radius * (1.0 + 1e-6);  // the eye outside the sphere
+        half[s] = cone[s] ? std::asin(sp.radius / dist[s]) : M_PI;
+        if (cone[s])
+            for (int i = 0; i < 3; ++i) a[s][i] /= dist[s];
+    }
+    for (int s = 0; s < d.n_spheres; ++s) {
+        occl[s] = 1u << s;
+        for (int t = 0; t < d.n_spheres; ++t) {
+            if (t == s) continue;
+            bool apart = false;
+            if (cone[s] && cone[t]) {
+                const double c = std::max(-1.0, std::min(1.0, a[s][0] * a[t][0] + a[s][1] * a[t][1] + a[s][2] * a[t][2]));
+                apart = std::acos(c) >= half[s] + half[t] + 1e-3;
+            }
+            const bool beyond = dist[t] - d.spheres[t].radius >= dist[s] + d.spheres[s].radius + 1e-3;
+            if (!(apart || beyond)) occl[s] |= 1u << t;
+        }
+    }
 }
 
 int32_t build_tables(fpt_scene* sc) {
@@ -675,7 +730,9 @@ int32_t build_tables(fpt_scene* sc) {
         P.splat_norm = (float)((double)d.width * d.height / (4.0 * tx * ty));
     }
     P.np = np;
-    P.sph_clear = cam ? clear_spheres(d, sc->h_st) : 0u;
+    P.geo_clear = cam ? clear_spheres(d) : 0u;
+    P.sph_clear = P.geo_clear & opaque_capable(d, sc->h_st);
+    sphere_occluders(d, P.sph_occl);
     return FPT_OK;
 }
 

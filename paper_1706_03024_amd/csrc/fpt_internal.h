@@ -93,6 +93,13 @@ struct KParams {
     // Lambertian) in the table image, and whether any wall is glossy
     int off_gloss;
     int glossy;
+    // pinhole connections from medium vertices: bit s of geo_clear when every
+    // point of sphere s passes the connection's geometric tests with margin
+    // (sph_clear adds the optical-depth condition), and sph_occl[s] the
+    // spheres whose chord a connection from inside sphere s can have nonzero
+    // (s itself included; a sphere outside it meets no such segment)
+    uint32_t geo_clear;
+    uint32_t sph_occl[FPT_MAX_SPHERES];
 };
 
 // Optical depth past which a transmittance is exactly 0 in fp32: exp(-103.3)

@@ -50,8 +50,9 @@ DEV uint4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0
     for (int i = 0; i < 10; ++i) {
         const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
         const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
-        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
-        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        // three-input xor in one v_bitop3_b32 (truth table 0x96: odd parity)
+        const uint32_t n0 = __builtin_amdgcn_bitop3_b32((uint32_t)(p1 >> 32), c1, k0, 0x96);
+        const uint32_t n2 = __builtin_amdgcn_bitop3_b32((uint32_t)(p0 >> 32), c3, k1, 0x96);
         c1 = (uint32_t)p1;
         c3 = (uint32_t)p0;
         c0 = n0;
@@ -332,16 +333,22 @@ DEV bool opaque_to_eye(const float* x, int region, float st, const float* sc, fl
 
 // -------------------------------------------------------------------------
 // Pinhole splat at a realised vertex (eqs. 3-6).  Returns the deposited value
-// (0 if rejected) and the film index; chord lengths go to `chord` for the
-// adjoint.  f = 1/(4 pi) in a medium, cos/pi on a Lambertian surface.
+// (0 if rejected) and the film index.  f = 1/(4 pi) in a medium, cos/pi on a
+// Lambertian surface.  CLEAR: a medium vertex inside a sphere of
+// P.geo_clear, whose connection passes the geometric tests, which are then
+// skipped, and whose transmittance is taken over the spheres of `smask`
+// (P.sph_occl of its sphere) only: the others' chords are exactly 0, so the
+// result is bit for bit the general one.
 struct SplatOut {
     float v;
     long long idx;
     int status;  // 0 hit, 1 miss, 2 roulette kill
 };
 
+template <bool CLEAR = false>
 DEV SplatOut splat_eval(const uint32_t* S, const KSphere* SP, const float* x, int lam, int comp,
-                        uint32_t batch, int pend, const float* nrm, uint32_t rrb, float wgt = 1.f) {
+                        uint32_t batch, int pend, const float* nrm, uint32_t rrb, float wgt = 1.f,
+                        uint32_t smask = ~0u) {
     const auto& P = *kernel_params();
     // Every test is evaluated and folded into `ok`, so the lanes of a wave stay
     // together; a rejected connection deposits nothing.
@@ -362,10 +369,11 @@ DEV SplatOut splat_eval(const uint32_t* S, const KSphere* SP, const float* x, in
     const float yi = -(d[0] * P.cu[0] + d[1] * P.cu[1] + d[2] * P.cu[2]) * izc * P.inv_tany;
     const float fx = (xi + 1.f) * 0.5f * (float)P.W;
     const float fy = (1.f - yi) * 0.5f * (float)P.H;
-    ok = ok && fx >= 0.f && fx < (float)P.W && fy >= 0.f && fy < (float)P.H;
+    if (CLEAR) ok = true;
+    ok = ok && (CLEAR || (fx >= 0.f && fx < (float)P.W && fy >= 0.f && fy < (float)P.H));
     // visibility: the segment from x (inside the box) to the eye (outside,
     // beyond the open face's plane) must cross that plane inside the face
-    {
+    if constexpr (!CLEAR) {
         // one-hot axis vectors: the dot products pick coordinates exactly
         const auto& e = P.vis_e;
         const float xa = e[0][0] * x[0] + e[0][1] * x[1] + e[0][2] * x[2];
@@ -379,7 +387,7 @@ DEV SplatOut splat_eval(const uint32_t* S, const KSphere* SP, const float* x, in
         ok = ok && q1 >= P.vis_lo1 && q1 <= P.vis_hi1 && q2 >= P.vis_lo2 && q2 <= P.vis_hi2;
     }
     // and must not pass through the (opaque) light quad, unless x is on it
-    if (pend != PEND_SOURCE) {
+    if (!CLEAR && pend != PEND_SOURCE) {
         const float dn = P.ln[0] * d[0] + P.ln[1] * d[1] + P.ln[2] * d[2];
         const float pc0 = P.lpos[0] - x[0], pc1 = P.lpos[1] - x[1], pc2 = P.lpos[2] - x[2];
         const float t = fdiv(P.ln[0] * pc0 + P.ln[1] * pc1 + P.ln[2] * pc2, dn);
@@ -397,7 +405,7 @@ DEV SplatOut splat_eval(const uint32_t* S, const KSphere* SP, const float* x, in
     float tau = 0.f;
 #pragma unroll
     for (int s = 0; s < FPT_MAX_SPHERES; ++s) {
-        if (s >= P.n_spheres) continue;
+        if (s >= P.n_spheres || !((smask >> s) & 1u)) continue;
         const float o0 = x[0] - SP[s].c[0], o1 = x[1] - SP[s].c[1], o2 = x[2] - SP[s].c[2];
         const float b = o0 * wc[0] + o1 * wc[1] + o2 * wc[2];
         const float p0 = o0 - b * wc[0], p1 = o1 - b * wc[1], p2 = o2 - b * wc[2];
@@ -478,8 +486,9 @@ struct SplatQ {
     int sj_n;         // entries written to it
 };
 
+// `face`: the wall face of a surface vertex, the sphere of a medium vertex.
 DEV uint32_t sq_word_a(uint32_t rrb, int pend, int face, int comp) {
-    return (rrb & 0xFFFFFFu) | ((uint32_t)pend << 24) | ((uint32_t)face << 26) | ((uint32_t)comp << 29);
+    return (rrb & 0xFFFFFFu) | ((uint32_t)pend << 24) | ((uint32_t)(face & 7) << 26) | ((uint32_t)comp << 29);
 }
 
 // Appends one entry per lane with `want`; at most 64, so count stays below
@@ -551,8 +560,9 @@ DEV void film_add_merged(const KParams& P, float* film, uint32_t* agg, const Dep
 }
 
 // One queued connection: decode and evaluate; the deposit is returned.
+template <bool CLEAR>
 DEV Deposit splat_entry(const KParams& P, const uint32_t* T, const KSphere* SP, uint32_t* tally,
-                        Counters& cnt, const float* x, uint32_t wa, uint32_t wb, float wgt) {
+                        Counters& cnt, const float* x, uint32_t wa, uint32_t wb, float wgt, uint32_t smask) {
     const int pend = (int)((wa >> 24) & 3u), face = (int)((wa >> 26) & 7u), comp = (int)((wa >> 29) & 1u);
     // surface normal: the light's for its own vertex, a wall's inward normal otherwise
     const int ax = face >> 1;
@@ -561,7 +571,8 @@ DEV Deposit splat_entry(const KParams& P, const uint32_t* T, const KSphere* SP, 
     nrm[0] = pend == PEND_SOURCE ? P.ln[0] : (ax == 0 ? sg : 0.f);
     nrm[1] = pend == PEND_SOURCE ? P.ln[1] : (ax == 1 ? sg : 0.f);
     nrm[2] = pend == PEND_SOURCE ? P.ln[2] : (ax == 2 ? sg : 0.f);
-    const SplatOut so = splat_eval(T, SP, x, (int)(wb & 0xFFFFu), comp, wb >> 16, pend, nrm, wa & 0xFFFFFFu, wgt);
+    const SplatOut so = splat_eval<CLEAR>(T, SP, x, (int)(wb & 0xFFFFu), comp, wb >> 16, pend, nrm,
+                                          wa & 0xFFFFFFu, wgt, smask);
     Deposit d;
     d.has = so.status == 0 && so.v != 0.f;  // +0 changes nothing
     d.idx = so.idx;
@@ -571,21 +582,41 @@ DEV Deposit splat_entry(const KParams& P, const uint32_t* T, const KSphere* SP, 
     return d;
 }
 
-// Evaluates the oldest n <= 64 entries, lane i taking entry head + i.
-DEV void sq_flush(const KParams& P, float* film, const uint32_t* T, const KSphere* SP, uint32_t* tally,
-                  SplatQ& q, Counters& cnt, uint32_t lane, int n) {
-    wave_sync();
+// The entries of the lanes with `valid`, evaluated together (called by the
+// whole wave).  When every one is a medium vertex of the same sphere of
+// P.geo_clear -- the usual case, the connections of one long path's wave
+// rounds -- they take splat_eval's CLEAR form with that sphere's occluders.
+DEV Deposit splat_entries(const KParams& P, const uint32_t* T, const KSphere* SP, uint32_t* tally,
+                          Counters& cnt, bool valid, const float* x, uint32_t wa, uint32_t wb, float wgt) {
+    const int pend = (int)((wa >> 24) & 3u), reg = (int)((wa >> 26) & 7u);
+    const uint64_t act = __ballot(valid);
     Deposit d;
     d.has = false;
     d.idx = 0;
     d.v = 0.f;
-    if ((int)lane < n) {
-        const int k = (q.head + (int)lane) & (kSqCap - 1);
-        const float x[3] = {__uint_as_float(q.base[k]), __uint_as_float(q.base[kSqCap + k]),
-                            __uint_as_float(q.base[2 * kSqCap + k])};
-        const float wgt = P.glossy ? __uint_as_float(q.base[5 * kSqCap + k]) : 1.f;
-        d = splat_entry(P, T, SP, tally, cnt, x, q.base[3 * kSqCap + k], q.base[4 * kSqCap + k], wgt);
+    if (!act) return d;
+    const int r0 = __builtin_amdgcn_readlane(reg, __ffsll((unsigned long long)act) - 1);
+    const bool same = valid && pend == PEND_MEDIUM && reg == r0 && ((kernel_params()->geo_clear >> r0) & 1u);
+    if (__ballot(same) == act) {
+        const uint32_t smask = kernel_params()->sph_occl[r0];
+        if (valid) d = splat_entry<true>(P, T, SP, tally, cnt, x, wa, wb, wgt, smask);
+    } else if (valid) {
+        d = splat_entry<false>(P, T, SP, tally, cnt, x, wa, wb, wgt, ~0u);
     }
+    return d;
+}
+
+// Evaluates the oldest n <= 64 entries, lane i taking entry head + i.
+DEV void sq_flush(const KParams& P, float* film, const uint32_t* T, const KSphere* SP, uint32_t* tally,
+                  SplatQ& q, Counters& cnt, uint32_t lane, int n) {
+    wave_sync();
+    const bool valid = (int)lane < n;
+    const int k = (q.head + (int)lane) & (kSqCap - 1);
+    const float x[3] = {__uint_as_float(q.base[k]), __uint_as_float(q.base[kSqCap + k]),
+                        __uint_as_float(q.base[2 * kSqCap + k])};
+    const float wgt = P.glossy ? __uint_as_float(q.base[5 * kSqCap + k]) : 1.f;
+    const Deposit d = splat_entries(P, T, SP, tally, cnt, valid, x, q.base[3 * kSqCap + k], q.base[4 * kSqCap + k],
+                                    wgt);
     film_add_merged(P, film, q.agg, d, lane);
     q.head = (q.head + n) & (kSqCap - 1);
     q.count -= n;
@@ -663,14 +694,17 @@ DEV void score_length(const KParams& P, const uint32_t* T, const Lane& L, AdjVie
 DEV float rl(float x, int j) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), j)); }
 // Cross-lane moves on the VALU (DPP) instead of through the LDS crossbar.
 // row_shr:d takes the value of lane i-d within each row of 16 lanes; lanes
-// with no source get -0, the exact identity of fp32 addition.  wave_shr:1
-// takes lane i-1 across the whole wave.
+// with no source read +0 (bound_ctrl), which adds exactly (up to the sign of
+// a zero sum), and with that fill the compiler folds the move into the add
+// (one v_add_f32 with a DPP source instead of a fill, a move and an add).
+// wave_shr:1 takes lane i-1 across the whole wave; lane 0 keeps `first`.
 template <int D>
 DEV float row_shr(float x) {
-    return __int_as_float(__builtin_amdgcn_update_dpp((int)0x80000000, __float_as_int(x), 0x110 + D, 0xf, 0xf, false));
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x110 + D, 0xf, 0xf, true));
 }
-DEV float wave_shr1(float x) {
-    return __int_as_float(__builtin_amdgcn_update_dpp((int)0x80000000, __float_as_int(x), 0x138, 0xf, 0xf, false));
+DEV float wave_shr1(float x, float first) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(first), __float_as_int(x), 0x138, 0xf, 0xf,
+                                                      false));
 }
 DEV int rli(int x, int j) { return __builtin_amdgcn_readlane(x, j); }
 DEV uint32_t rlu(uint32_t x, int j) { return (uint32_t)__builtin_amdgcn_readlane((int)x, j); }
@@ -783,7 +817,7 @@ DEV void block_walk(const KParams& P, const KBuffers& B, const uint32_t* T, cons
     float win[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        const float up = wave_shr1(wn[c]);
+        const float up = wave_shr1(wn[c], Q.w[c]);
         win[c] = pos == 0 ? Q.w[c] : up;
     }
     const float seg3[3] = {tk * win[0], tk * win[1], tk * win[2]};
@@ -854,7 +888,7 @@ DEV void block_walk(const KParams& P, const KBuffers& B, const uint32_t* T, cons
             const bool opq = want && opaque_to_eye(Lk.x, Q.region, Q.st, Q.sc, Q.sr2);
             count_opaque(tally, cnt, opq);
             want = want && !opq;
-            splat_defer<GLOSS>(B, q, want, Lk.x, sq_word_a(rr_bits(r), PEND_MEDIUM, 0, Q.comp),
+            splat_defer<GLOSS>(B, q, want, Lk.x, sq_word_a(rr_bits(r), PEND_MEDIUM, Q.region, Q.comp),
                                (uint32_t)Q.lam | (Q.batch << 16), GLOSS ? Q.wgt : 1.f, exhausted);
         }
     } else if constexpr (GEOM == FPT_GEOM_BOX) {
@@ -978,10 +1012,7 @@ DEV void deep_half(const KParams& P, const Lane& Q, uint32_t v0, uint32_t lane, 
     wn[1] = stt * sp;
     wn[2] = ct;
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        const float up = wave_shr1(wn[c]);
-        win[c] = lane == 0 ? wprev[c] : up;
-    }
+    for (int c = 0; c < 3; ++c) win[c] = wave_shr1(wn[c], wprev[c]);
     const float seg3[3] = {tk * win[0], tk * win[1], tk * win[2]};
     float s0 = seg3[0], s1 = seg3[1], s2 = seg3[2];
 #define FPT_SCAN3(D) s0 += row_shr<D>(s0); s1 += row_shr<D>(s1); s2 += row_shr<D>(s2);
@@ -1053,14 +1084,14 @@ DEV void deep_round(const KParams& P, const KBuffers& B, const uint32_t* T, cons
             const bool o1 = m1 && dep && opaque_to_eye(x1, Q.region, Q.st, Q.sc, Q.sr2);
             count_opaque(tally, cnt, o1);
             const bool w1 = m1 && dep && !o1;
-            splat_defer<GLOSS>(B, q, w1, x1, sq_word_a(__float_as_uint(x1[3]), PEND_MEDIUM, 0, Q.comp), wb, Q.wgt,
+            splat_defer<GLOSS>(B, q, w1, x1, sq_word_a(__float_as_uint(x1[3]), PEND_MEDIUM, Q.region, Q.comp), wb, Q.wgt,
                                exhausted);
             sq_drain(P, B.film, T, SP, tally, q, cnt, lane, false);
             if (k2 > 0) {
                 const bool o2 = m2 && dep && opaque_to_eye(x2, Q.region, Q.st, Q.sc, Q.sr2);
                 count_opaque(tally, cnt, o2);
                 const bool w2 = m2 && dep && !o2;
-                splat_defer<GLOSS>(B, q, w2, x2, sq_word_a(__float_as_uint(x2[3]), PEND_MEDIUM, 0, Q.comp), wb,
+                splat_defer<GLOSS>(B, q, w2, x2, sq_word_a(__float_as_uint(x2[3]), PEND_MEDIUM, Q.region, Q.comp), wb,
                                    Q.wgt, exhausted);
             }
         }
@@ -1392,7 +1423,8 @@ DEV void advance(const KParams& P, const KBuffers& B, const WaveCtx& C, WalkStat
                 want = want && !opq;
                 float sw = 1.f;
                 if constexpr (kGloss) sw = W.gspl ? W.sw : L.wgt;
-                splat_defer<kGloss>(B, W.q, want, L.x, sq_word_a(rrb, pend, W.face, L.comp),
+                splat_defer<kGloss>(B, W.q, want, L.x,
+                                    sq_word_a(rrb, pend, pend == PEND_MEDIUM ? L.region : W.face, L.comp),
                                     (uint32_t)L.lam | (L.batch << 16), sw, exhausted);
             }
         } else if constexpr (GEOM == FPT_GEOM_BOX) {
@@ -2041,15 +2073,11 @@ __global__ void __launch_bounds__(256) k_splat_jobs(const KParams P, const KBuff
     Counters cnt = {0u, 0u, 0u};
     for (uint32_t b0 = wv * 64; b0 < n; b0 += blockDim.x) {  // uniform per wave
         const uint32_t i = b0 + lane;
-        Deposit d;
-        d.has = false;
-        d.idx = 0;
-        d.v = 0.f;
-        if (i < n) {
-            const float x[3] = {__uint_as_float(sl[i]), __uint_as_float(sl[S + i]), __uint_as_float(sl[2 * S + i])};
-            const float wgt = P.glossy ? __uint_as_float(sl[5 * S + i]) : 1.f;
-            d = splat_entry(P, T, SPw, tally, cnt, x, sl[3 * S + i], sl[4 * S + i], wgt);
-        }
+        const bool valid = i < n;
+        const uint32_t j = valid ? i : 0u;
+        const float x[3] = {__uint_as_float(sl[j]), __uint_as_float(sl[S + j]), __uint_as_float(sl[2 * S + j])};
+        const float wgt = P.glossy ? __uint_as_float(sl[5 * S + j]) : 1.f;
+        const Deposit d = splat_entries(P, T, SPw, tally, cnt, valid, x, sl[3 * S + j], sl[4 * S + j], wgt);
         film_add_merged(P, B.film, agg, d, lane);
     }
     uint32_t h = cnt.splat_hit;
