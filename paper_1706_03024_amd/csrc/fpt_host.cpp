@@ -422,17 +422,17 @@ uint32_t clear_spheres(const fpt_scene_desc& d) {
     return bits;
 }
 
-// Spheres whose medium reaches an optical depth of kTauZero across the
-// sphere at some wavelength (bit s): only there can a connection be opaque
-// within the sphere itself, which the kernels count as a zero-valued hit
-// without evaluating it.
-uint32_t opaque_capable(const fpt_scene_desc& d, const std::vector<float>& st) {
+// Spheres whose medium reaches an optical depth of tau0 across the sphere at
+// some wavelength (bit s): only there can a connection be opaque within the
+// sphere itself, which the kernels count as a zero-valued hit without
+// evaluating it.
+uint32_t opaque_capable(const fpt_scene_desc& d, const std::vector<float>& st, float tau0) {
     uint32_t bits = 0u;
     for (int s = 0; s < d.n_spheres; ++s) {
         const fpt_sphere& sp = d.spheres[s];
         float stmax = 0.f;
         for (int k = 0; k < d.n_bins; ++k) stmax = std::max(stmax, st[(size_t)sp.medium * d.n_bins + k]);
-        if ((double)stmax * 2.0 * sp.radius >= (double)kTauZero) bits |= 1u << s;
+        if ((double)stmax * 2.0 * sp.radius >= (double)tau0) bits |= 1u << s;
     }
     return bits;
 }
@@ -731,7 +731,8 @@ int32_t build_tables(fpt_scene* sc) {
     }
     P.np = np;
     P.geo_clear = cam ? clear_spheres(d) : 0u;
-    P.sph_clear = P.geo_clear & opaque_capable(d, sc->h_st);
+    P.tau_zero = kTauZero;
+    P.sph_clear = P.geo_clear & opaque_capable(d, sc->h_st, kTauZero);
     sphere_occluders(d, P.sph_occl);
     return FPT_OK;
 }
@@ -766,6 +767,24 @@ int32_t check_run(const fpt_scene* sc, const fpt_run* run, uint32_t* B) {
     return FPT_OK;
 }
 
+// The optical depth from which a medium vertex's pinhole connection deposits
+// exactly 0 in fp32.  The kernels form the deposit as wscale * f * tr * ...
+// from the left, f = 1/(4 pi) in a medium; once the first product
+// (wscale f) tr is below 2^-150 it rounds to 0, and so does every later
+// product (all other factors are finite for the clear spheres the shortcut
+// applies to).  With tr = exp(-tau) to a few ulps that holds for
+// tau >= ln(wscale f) + 150 ln 2; 0.5 of margin covers the fp32 evaluation of
+// tau (the connection's own-sphere chord; other spheres only add to it).  With
+// connection roulette (splat_rr > 0) a transmittance that is not exactly 0
+// takes part in the roulette, so the threshold stays kTauZero.
+float exact_zero_depth(const KParams& P) {
+    if (P.splat_rr > 0.f) return kTauZero;
+    const float a = P.wscale * 0.0795774715459476679f;  // fp32, as the kernels form it
+    if (!(a > 0.f)) return kTauZero;
+    const double t = std::log((double)a) + 150.0 * std::log(2.0) + 0.5;
+    return (float)std::min(t, (double)kTauZero);
+}
+
 void fill_run(const fpt_scene* sc, const fpt_run* run, uint32_t B, KParams* P) {
     *P = sc->base;
     P->key0 = (uint32_t)run->seed;
@@ -795,6 +814,8 @@ void fill_run(const fpt_scene* sc, const fpt_run* run, uint32_t B, KParams* P) {
     P->block_min_v = sc->tune.block_min_vertices > 0 ? (uint32_t)sc->tune.block_min_vertices : (pin ? 2u : 8u);
     P->max_segments = sc->tune.block_segments > 0 ? sc->tune.block_segments : 4;
     P->wide_rounds = sc->tune.wide_rounds < 0 ? 0 : (sc->tune.wide_rounds > 0 ? sc->tune.wide_rounds : (pin ? 1 : 2));
+    P->tau_zero = exact_zero_depth(*P);
+    P->sph_clear = P->geo_clear & opaque_capable(sc->desc, sc->h_st, P->tau_zero);
 }
 
 // Deferred-connection entries per transport wave (20 bytes each).

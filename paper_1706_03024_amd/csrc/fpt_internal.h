@@ -100,6 +100,9 @@ struct KParams {
     // (s itself included; a sphere outside it meets no such segment)
     uint32_t geo_clear;
     uint32_t sph_occl[FPT_MAX_SPHERES];
+    // optical depth from which a medium vertex's connection deposits exactly 0
+    // (at most kTauZero; set per run from the deposit's weight)
+    float tau_zero;
 };
 
 // Optical depth past which a transmittance is exactly 0 in fp32: exp(-103.3)

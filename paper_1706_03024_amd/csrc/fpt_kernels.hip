@@ -315,9 +315,10 @@ DEV KParamsArg kernel_params() {
 }
 
 // A medium vertex whose connection to the eye would cross an optical depth of
-// at least kTauZero inside its own sphere alone has a transmittance of exactly
-// 0 in fp32: the splat deposits nothing, whatever the other spheres on the way
-// add.  Where the host has shown that every point of that sphere passes the
+// at least P.tau_zero inside its own sphere alone deposits exactly 0 in fp32
+// (at kTauZero its transmittance is 0; below that, at the run's path weight,
+// the deposit's first product already rounds to 0), whatever the other
+// spheres on the way add.  Where the host has shown that every point of that sphere passes the
 // connection's geometric tests (P.sph_clear), its outcome is also known -- a
 // hit of value 0, or a roulette kill when splat_rr > 0 -- so it is counted
 // without being queued and evaluated (about a third of the large scene's
@@ -328,7 +329,7 @@ DEV bool opaque_to_eye(const float* x, int region, float st, const float* sc, fl
     const float d0 = K.eye[0] - x[0], d1 = K.eye[1] - x[1], d2 = K.eye[2] - x[2];
     const float ri = __builtin_amdgcn_rsqf(d0 * d0 + d1 * d1 + d2 * d2);
     const float wc[3] = {d0 * ri, d1 * ri, d2 * ri};
-    return st * sphere_exit(x, wc, sc, sr2) >= kTauZero;
+    return st * sphere_exit(x, wc, sc, sr2) >= K.tau_zero;
 }
 
 // -------------------------------------------------------------------------
