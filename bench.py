@@ -541,6 +541,78 @@ def profile_run(name, steps):
 
 HEADLINE_TUNE = "large-512-1024spp"
 
+# main kernel(s) of each profiled workload (name prefixes in rocprofv3's output)
+PROFILED_KERNELS = {
+    "cornell": ("void fpt::k_transport<4, 0,",), "large": ("void fpt::k_transport<4, 0,",),
+    "slab": ("void fpt::k_transport<0, 0,",), "batched": ("void fpt::k_batch<",),
+    "camera": ("void fpt::k_camera<",),
+    "adjoint": ("void fpt::k_transport<4, 0,", "void fpt::k_transport<4, 1,"),
+}
+
+
+def record_counters(workload, csv_paths):
+    """Writes profiles/traffic.json's entry for `workload` from rocprofv3
+    counter-collection CSVs of `bench.py --profile <workload>` runs (one pass
+    per counter set): FETCH_SIZE / WRITE_SIZE per dispatch of the workload's
+    kernel(s) and of k_splat_jobs, scaled by what the same counters read for
+    the run's 256 MiB device copy, and SQ_INSTS_VALU_FLOPS_FP32 (wave
+    instructions x 64 lanes, FMA = 2).  The entry is keyed by the kernel
+    source hash, so it is ignored once the kernels change."""
+    import collections
+    import csv
+    per = collections.defaultdict(lambda: collections.defaultdict(list))
+    for path in csv_paths:
+        with open(path) as f:
+            for r in csv.DictReader(f):
+                name = r["Kernel_Name"]
+                if name.startswith("__amd_rocclr_copyBuffer"):
+                    key = "copy"
+                elif name.startswith("fpt::k_splat_jobs"):
+                    key = "deferred"
+                elif any(name.startswith(k) for k in PROFILED_KERNELS[workload]):
+                    key = "main"
+                else:
+                    continue
+                per[key][(r["Counter_Name"], r["Dispatch_Id"])].append(float(r["Counter_Value"]))
+
+    def mean(key, counter):
+        v = [sum(x) for (c, _), x in per[key].items() if c == counter]
+        return sum(v) / len(v) if v else None
+
+    def largest(key, counter):  # the calibration copy (other small copies may run too)
+        v = [sum(x) for (c, _), x in per[key].items() if c == counter]
+        return max(v) if v else None
+
+    launches = len(PROFILED_KERNELS[workload])  # kernels per step
+    entry = {}
+    copy_kib = COPY_BYTES / 1024.0
+    f_copy, w_copy = largest("copy", "FETCH_SIZE"), largest("copy", "WRITE_SIZE")
+    f_main, w_main = mean("main", "FETCH_SIZE"), mean("main", "WRITE_SIZE")
+    if None not in (f_copy, w_copy, f_main, w_main):
+        ff, wf_ = copy_kib / f_copy, copy_kib / w_copy
+        f_def, w_def = mean("deferred", "FETCH_SIZE") or 0.0, mean("deferred", "WRITE_SIZE") or 0.0
+        tb = (f_main * ff + w_main * wf_) * 1024.0 * launches
+        db = (f_def * ff + w_def * wf_) * 1024.0
+        entry.update({"bytes_per_launch": tb + db, "transport_bytes": tb, "deferred_bytes": db,
+                      "fetch_kib_raw": f_main, "write_kib_raw": w_main,
+                      "deferred_fetch_kib_raw": f_def, "deferred_write_kib_raw": w_def,
+                      "fetch_factor": ff, "write_factor": wf_})
+    fl = mean("main", "SQ_INSTS_VALU_FLOPS_FP32")
+    if fl is not None:
+        entry["fp32_flops_per_launch"] = fl * 64.0 * launches
+    try:
+        with open(TRAFFIC_JSON) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        rec = {}
+    if rec.get("kernel_source") != kernel_source_hash():
+        rec = {"kernel_source": kernel_source_hash(), "copy_bytes": COPY_BYTES, "workloads": {}}
+    rec["workloads"][workload] = entry
+    with open(TRAFFIC_JSON, "w") as f:
+        json.dump(rec, f, indent=1, sort_keys=True)
+        f.write("\n")
+    print(json.dumps({workload: entry}), flush=True)
+
 
 def form_summary(f, workload):
     """The per-form fields of a forward render: throughput, the algorithmic
@@ -569,7 +641,13 @@ def main():
                                           "camera"],
                     help="profiler run: one 256 MiB device copy (traffic calibration) and "
                          "--steps renders of the named workload, nothing else")
+    ap.add_argument("--record-counters", nargs="+", metavar=("WORKLOAD", "CSV"),
+                    help="write profiles/traffic.json's entry for WORKLOAD from the rocprofv3 "
+                         "counter CSVs of its --profile runs (no GPU work)")
     args = ap.parse_args()
+    if args.record_counters:
+        record_counters(args.record_counters[0], args.record_counters[1:])
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
               "sharding of this path is a design note, not a measured configuration.",
