@@ -412,6 +412,17 @@ int32_t fpt_render_camera(fpt_scene* scene, const fpt_run* run, float* film_dev,
 int32_t fpt_scene_tables(const fpt_scene* scene, float* sigma_t, float* emis_cdf, float* rho,
                          int32_t* line_bin);
 
+/* Test hook: the scene's pinhole-connection geometry precomputed by the host
+ * (box scenes with a pinhole sensor; 0 otherwise).  *geo_clear: bit s set when
+ * every point of sphere s passes a camera connection's geometric tests (inside
+ * the image, through the open face, clear of the light quad; eqs. 3-6) with a
+ * margin far above fp32 rounding, so the kernels skip those tests for its
+ * medium vertices.  occluders[FPT_MAX_SPHERES]: bit t of occluders[s] set when
+ * a segment from a point of sphere s to the eye can meet sphere t (s itself
+ * included); the kernels take the transmittance of such connections (eq. 5)
+ * over these spheres only.  Either pointer may be NULL. */
+int32_t fpt_scene_connection_masks(const fpt_scene* scene, uint32_t* geo_clear, uint32_t* occluders);
+
 /* Batched form: n independent escape-sensor body scenes (one medium each,
  * equal n_bins) rendered by one persistent launch that claims (instance, path
  * chunk) work items from a device queue; the launch sequence is captured in a

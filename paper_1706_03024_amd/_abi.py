@@ -147,6 +147,7 @@ def lib():
         "fpt_render_records": (C.c_int32, [vp, C.POINTER(Run), vp, C.c_uint32, vp, vp, vp]),
         "fpt_render_camera": (C.c_int32, [vp, C.POINTER(Run), vp, vp, vp, C.c_uint32, vp]),
         "fpt_scene_tables": (C.c_int32, [vp, vp, vp, vp, vp]),
+        "fpt_scene_connection_masks": (C.c_int32, [vp, vp, vp]),
         "fpt_batch_create": (C.c_int32, [C.POINTER(SceneDesc), C.POINTER(Run), C.c_int32,
                                          C.POINTER(Tune), C.POINTER(vp)]),
         "fpt_batch_render": (C.c_int32, [vp, vp, vp, vp]),

@@ -1245,6 +1245,14 @@ int32_t fpt_scene_tables(const fpt_scene* sc, float* sigma_t, float* emis_cdf, f
     return FPT_OK;
 }
 
+int32_t fpt_scene_connection_masks(const fpt_scene* sc, uint32_t* geo_clear, uint32_t* occluders) {
+    if (!sc) return set_err(FPT_E_INVALID, "NULL scene");
+    if (geo_clear) *geo_clear = sc->base.geo_clear;
+    if (occluders)
+        for (int s = 0; s < FPT_MAX_SPHERES; ++s) occluders[s] = s < sc->desc.n_spheres ? sc->base.sph_occl[s] : 0u;
+    return FPT_OK;
+}
+
 int32_t fpt_render(fpt_scene* sc, const fpt_run* run, float* film, uint64_t* tallies, void* stream) {
     if (!sc || !film) return set_err(FPT_E_INVALID, "NULL argument");
     uint32_t B;

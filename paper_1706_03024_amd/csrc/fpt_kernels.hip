@@ -429,7 +429,11 @@ DEV SplatOut splat_eval(const uint32_t* S, const KSphere* SP, const float* x, in
         v = fdiv(v, q);
     }
     o.v = o.status == 0 ? v : 0.f;
-    const int px = min((int)(ok ? fx : 0.f), P.W - 1), py = min((int)(ok ? fy : 0.f), P.H - 1);
+    int px = min((int)(ok ? fx : 0.f), P.W - 1), py = min((int)(ok ? fy : 0.f), P.H - 1);
+    if (CLEAR) {  // the host's margin keeps fx, fy inside the image; never index outside it
+        px = max(px, 0);
+        py = max(py, 0);
+    }
     o.idx = ((long long)((int)batch * 2 + comp) * (P.H * P.W) + (py * P.W + px)) * P.N + lam;
     return o;
 }

@@ -129,6 +129,13 @@ class Scene:
         return {"sigma_t": st, "emis_cdf": cdf[: len(d["dyes"])], "rho": rho,
                 "line_bin": lb[: len(d["light"]["lines"])]}
 
+    def connection_masks(self):
+        """fpt_scene_connection_masks: (geo_clear bits, occluder bits per sphere)."""
+        g = C.c_uint32()
+        occ = np.zeros(_abi.MAX_SPHERES, np.uint32)
+        check(lib().fpt_scene_connection_masks(self._h, C.byref(g), occ.ctypes.data))
+        return int(g.value), [int(x) for x in occ[: len(self.desc["geometry"].get("spheres", []))]]
+
     def new_film(self, batches=1, device="cuda"):
         return torch.zeros(self.film_shape(batches), dtype=torch.float32, device=device)
 
