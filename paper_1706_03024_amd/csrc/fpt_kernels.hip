@@ -323,13 +323,17 @@ DEV KParamsArg kernel_params() {
 // hit of value 0, or a roulette kill when splat_rr > 0 -- so it is counted
 // without being queued and evaluated (about a third of the large scene's
 // connections, from deep inside its densest spheres).
-DEV bool opaque_to_eye(const float* x, int region, float st, const float* sc, float sr2) {
+// For x inside the (convex) sphere the exit distance along the eye direction
+// w is at least L = P.tau_zero / sigma_t exactly when x + L w is inside too, so
+// the test is one point-in-sphere check instead of a chord (no square root).
+// inv_st = 1 / sigma_t of the vertex's medium and wavelength.
+DEV bool opaque_to_eye(const float* x, int region, float inv_st, const float* sc, float sr2) {
     const auto& K = *kernel_params();
     if (region < 0 || !((K.sph_clear >> (uint32_t)region) & 1u)) return false;
     const float d0 = K.eye[0] - x[0], d1 = K.eye[1] - x[1], d2 = K.eye[2] - x[2];
-    const float ri = __builtin_amdgcn_rsqf(d0 * d0 + d1 * d1 + d2 * d2);
-    const float wc[3] = {d0 * ri, d1 * ri, d2 * ri};
-    return st * sphere_exit(x, wc, sc, sr2) >= K.tau_zero;
+    const float s = K.tau_zero * inv_st * __builtin_amdgcn_rsqf(d0 * d0 + d1 * d1 + d2 * d2);
+    const float p0 = x[0] - sc[0] + s * d0, p1 = x[1] - sc[1] + s * d1, p2 = x[2] - sc[2] + s * d2;
+    return p0 * p0 + p1 * p1 + p2 * p2 <= sr2;
 }
 
 // -------------------------------------------------------------------------
@@ -434,7 +438,11 @@ DEV SplatOut splat_eval(const uint32_t* S, const KSphere* SP, const float* x, in
         px = max(px, 0);
         py = max(py, 0);
     }
-    o.idx = ((long long)((int)batch * 2 + comp) * (P.H * P.W) + (py * P.W + px)) * P.N + lam;
+    if (P.film_u32)  // the film's element count is below 2^32: 32-bit index arithmetic
+        o.idx = (long long)((((uint32_t)batch * 2u + (uint32_t)comp) * (uint32_t)(P.H * P.W) +
+                             (uint32_t)(py * P.W + px)) * (uint32_t)P.N + (uint32_t)lam);
+    else
+        o.idx = ((long long)((int)batch * 2 + comp) * (P.H * P.W) + (py * P.W + px)) * P.N + lam;
     return o;
 }
 
@@ -568,7 +576,9 @@ DEV void film_add_merged(const KParams& P, float* film, uint32_t* agg, const Dep
 template <bool CLEAR>
 DEV Deposit splat_entry(const KParams& P, const uint32_t* T, const KSphere* SP, uint32_t* tally,
                         Counters& cnt, const float* x, uint32_t wa, uint32_t wb, float wgt, uint32_t smask) {
-    const int pend = (int)((wa >> 24) & 3u), face = (int)((wa >> 26) & 7u), comp = (int)((wa >> 29) & 1u);
+    // a CLEAR batch holds medium vertices only (splat_entries)
+    const int pend = CLEAR ? PEND_MEDIUM : (int)((wa >> 24) & 3u), face = (int)((wa >> 26) & 7u);
+    const int comp = (int)((wa >> 29) & 1u);
     // surface normal: the light's for its own vertex, a wall's inward normal otherwise
     const int ax = face >> 1;
     const float sg = (face & 1) ? -1.f : 1.f;
@@ -890,7 +900,7 @@ DEV void block_walk(const KParams& P, const KBuffers& B, const uint32_t* T, cons
     if constexpr (GEOM == FPT_GEOM_BOX && MODE == MODE_FWD) {
         if (pinhole) {
             bool want = mine && !(P.fluo_only && Q.comp == 0);
-            const bool opq = want && opaque_to_eye(Lk.x, Q.region, Q.st, Q.sc, Q.sr2);
+            const bool opq = want && opaque_to_eye(Lk.x, Q.region, Q.inv, Q.sc, Q.sr2);
             count_opaque(tally, cnt, opq);
             want = want && !opq;
             splat_defer<GLOSS>(B, q, want, Lk.x, sq_word_a(rr_bits(r), PEND_MEDIUM, Q.region, Q.comp),
@@ -1086,14 +1096,14 @@ DEV void deep_round(const KParams& P, const KBuffers& B, const uint32_t* T, cons
         if (pinhole) {
             const bool dep = !(P.fluo_only && Q.comp == 0);
             const uint32_t wb = (uint32_t)Q.lam | (Q.batch << 16);
-            const bool o1 = m1 && dep && opaque_to_eye(x1, Q.region, Q.st, Q.sc, Q.sr2);
+            const bool o1 = m1 && dep && opaque_to_eye(x1, Q.region, Q.inv, Q.sc, Q.sr2);
             count_opaque(tally, cnt, o1);
             const bool w1 = m1 && dep && !o1;
             splat_defer<GLOSS>(B, q, w1, x1, sq_word_a(__float_as_uint(x1[3]), PEND_MEDIUM, Q.region, Q.comp), wb, Q.wgt,
                                exhausted);
             sq_drain(P, B.film, T, SP, tally, q, cnt, lane, false);
             if (k2 > 0) {
-                const bool o2 = m2 && dep && opaque_to_eye(x2, Q.region, Q.st, Q.sc, Q.sr2);
+                const bool o2 = m2 && dep && opaque_to_eye(x2, Q.region, Q.inv, Q.sc, Q.sr2);
                 count_opaque(tally, cnt, o2);
                 const bool w2 = m2 && dep && !o2;
                 splat_defer<GLOSS>(B, q, w2, x2, sq_word_a(__float_as_uint(x2[3]), PEND_MEDIUM, Q.region, Q.comp), wb,
@@ -1423,7 +1433,7 @@ DEV void advance(const KParams& P, const KBuffers& B, const WaveCtx& C, WalkStat
                 bool want = pend != PEND_NONE && alive && (exit_code < 0 || (kGloss && W.gdie)) &&
                             !(P.fluo_only && L.comp == 0);
                 const bool opq = want && medium && pend == PEND_MEDIUM &&
-                                 opaque_to_eye(L.x, L.region, L.st, L.sc, L.sr2);
+                                 opaque_to_eye(L.x, L.region, L.inv, L.sc, L.sr2);
                 count_opaque(tally, cnt, opq);
                 want = want && !opq;
                 float sw = 1.f;
