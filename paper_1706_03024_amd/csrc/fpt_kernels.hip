@@ -1056,6 +1056,13 @@ DEV void deep_half(const KParams& P, const Lane& Q, uint32_t v0, uint32_t lane, 
     xk[3] = __uint_as_float(rr_bits(r));
 }
 
+// Consecutive rounds of one path run in one call while each commits all 128
+// vertices (at most kDeepRounds): the path's state stays uniform between them
+// instead of being read back from its lane each round, and the rounds are the
+// same as separate calls would walk.  Measured on the large scene: 4 rounds
+// per call 58.8 ms, 16 57.8 ms, 32 or more 57.7 ms (2 rounds 60.3 ms).
+constexpr int kDeepRounds = 1024;
+
 template <int GEOM, bool GLOSS>
 DEV void deep_round(const KParams& P, const KBuffers& B, const uint32_t* T, const KSphere* SP,
                     uint32_t* tally, Lane& L, int j, uint32_t lane, bool pinhole, Counters& cnt, bool& full,
@@ -1079,54 +1086,67 @@ DEV void deep_round(const KParams& P, const KBuffers& B, const uint32_t* T, cons
     Q.nsc = rlu(L.nsc, j);
     Q.batch = rlu(L.batch, j);
     Q.wgt = GLOSS ? rl(L.wgt, j) : 1.f;
-    float wn1[3], x1[4], p1[3], win1[3], wn2[3], x2[4], p2[3], win2[3];
-    bool st1, st2;
-    deep_half<GEOM>(P, Q, Q.v, lane, Q.w, Q.x, wn1, x1, p1, win1, st1);
-    // the second half starts from the state after the first half's vertex 64
-    const float w64[3] = {rl(wn1[0], 63), rl(wn1[1], 63), rl(wn1[2], 63)};
-    const float x64[3] = {rl(x1[0], 63), rl(x1[1], 63), rl(x1[2], 63)};
-    deep_half<GEOM>(P, Q, Q.v + 64u, lane, w64, x64, wn2, x2, p2, win2, st2);
-    const uint64_t sm1 = __ballot(st1), sm2 = __ballot(st2);
-    const int k1 = sm1 ? (__ffsll((unsigned long long)sm1) - 1) : 64;
-    const int k2 = k1 < 64 ? 0 : (sm2 ? (__ffsll((unsigned long long)sm2) - 1) : 64);
-    const bool m1 = (int)lane < k1, m2 = (int)lane < k2;
-    cnt.vertices += (uint32_t)m1 + (uint32_t)m2;
-    cnt.scatters += (uint32_t)m1 + (uint32_t)m2;
-    if constexpr (GEOM == FPT_GEOM_BOX) {
-        if (pinhole) {
-            const bool dep = !(P.fluo_only && Q.comp == 0);
-            const uint32_t wb = (uint32_t)Q.lam | (Q.batch << 16);
-            const bool o1 = m1 && dep && opaque_to_eye(x1, Q.region, Q.inv, Q.sc, Q.sr2);
-            count_opaque(tally, cnt, o1);
-            const bool w1 = m1 && dep && !o1;
-            splat_defer<GLOSS>(B, q, w1, x1, sq_word_a(__float_as_uint(x1[3]), PEND_MEDIUM, Q.region, Q.comp), wb, Q.wgt,
-                               exhausted);
-            sq_drain(P, B.film, T, SP, tally, q, cnt, lane, false);
-            if (k2 > 0) {
-                const bool o2 = m2 && dep && opaque_to_eye(x2, Q.region, Q.inv, Q.sc, Q.sr2);
-                count_opaque(tally, cnt, o2);
-                const bool w2 = m2 && dep && !o2;
-                splat_defer<GLOSS>(B, q, w2, x2, sq_word_a(__float_as_uint(x2[3]), PEND_MEDIUM, Q.region, Q.comp), wb,
-                                   Q.wgt, exhausted);
+    const bool dep = !(P.fluo_only && Q.comp == 0);
+    const uint32_t wb = (uint32_t)Q.lam | (Q.batch << 16);
+    uint32_t walked = 0;
+    for (int round = 0;; ++round) {
+        float wn1[3], x1[4], p1[3], win1[3], wn2[3], x2[4], p2[3], win2[3];
+        bool st1, st2;
+        deep_half<GEOM>(P, Q, Q.v, lane, Q.w, Q.x, wn1, x1, p1, win1, st1);
+        // the second half starts from the state after the first half's vertex 64
+        const float w64[3] = {rl(wn1[0], 63), rl(wn1[1], 63), rl(wn1[2], 63)};
+        const float x64[3] = {rl(x1[0], 63), rl(x1[1], 63), rl(x1[2], 63)};
+        deep_half<GEOM>(P, Q, Q.v + 64u, lane, w64, x64, wn2, x2, p2, win2, st2);
+        const uint64_t sm1 = __ballot(st1), sm2 = __ballot(st2);
+        const int k1 = sm1 ? (__ffsll((unsigned long long)sm1) - 1) : 64;
+        const int k2 = k1 < 64 ? 0 : (sm2 ? (__ffsll((unsigned long long)sm2) - 1) : 64);
+        const bool m1 = (int)lane < k1, m2 = (int)lane < k2;
+        cnt.vertices += (uint32_t)m1 + (uint32_t)m2;
+        cnt.scatters += (uint32_t)m1 + (uint32_t)m2;
+        if constexpr (GEOM == FPT_GEOM_BOX) {
+            if (pinhole) {
+                const bool o1 = m1 && dep && opaque_to_eye(x1, Q.region, Q.inv, Q.sc, Q.sr2);
+                count_opaque(tally, cnt, o1);
+                const bool w1 = m1 && dep && !o1;
+                splat_defer<GLOSS>(B, q, w1, x1, sq_word_a(__float_as_uint(x1[3]), PEND_MEDIUM, Q.region, Q.comp),
+                                   wb, Q.wgt, exhausted);
+                sq_drain(P, B.film, T, SP, tally, q, cnt, lane, false);
+                if (k2 > 0) {
+                    const bool o2 = m2 && dep && opaque_to_eye(x2, Q.region, Q.inv, Q.sc, Q.sr2);
+                    count_opaque(tally, cnt, o2);
+                    const bool w2 = m2 && dep && !o2;
+                    splat_defer<GLOSS>(B, q, w2, x2,
+                                       sq_word_a(__float_as_uint(x2[3]), PEND_MEDIUM, Q.region, Q.comp), wb,
+                                       Q.wgt, exhausted);
+                }
             }
         }
-    }
-    const int k = k1 + k2;
-    full = k == 128;
-    if (k > 0) {
-        const int u = (k2 > 0 ? k2 : k1) - 1;
-        const float nx0 = k2 > 0 ? rl(x2[0], u) : rl(x1[0], u);
-        const float nx1 = k2 > 0 ? rl(x2[1], u) : rl(x1[1], u);
-        const float nx2 = k2 > 0 ? rl(x2[2], u) : rl(x1[2], u);
-        const float nw0 = k2 > 0 ? rl(wn2[0], u) : rl(wn1[0], u);
-        const float nw1 = k2 > 0 ? rl(wn2[1], u) : rl(wn1[1], u);
-        const float nw2 = k2 > 0 ? rl(wn2[2], u) : rl(wn1[2], u);
-        if ((int)lane == j) {
-            L.x[0] = nx0; L.x[1] = nx1; L.x[2] = nx2;
-            L.w[0] = nw0; L.w[1] = nw1; L.w[2] = nw2;
-            L.v += (uint32_t)k;
-            L.nsc += (uint32_t)k;
+        const int k = k1 + k2;
+        full = k == 128;
+        if (k > 0) {
+            // the state after the last committed vertex (the source is uniform)
+            const int u = (k2 > 0 ? k2 : k1) - 1;
+            const bool h2 = k2 > 0;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                Q.x[c] = rl(h2 ? x2[c] : x1[c], u);
+                Q.w[c] = rl(h2 ? wn2[c] : wn1[c], u);
+            }
+            Q.v += (uint32_t)k;
+            Q.nsc += (uint32_t)k;
+            walked += (uint32_t)k;
         }
+        if (!full || round + 1 == kDeepRounds) break;
+        // the ring holds fewer than 64 entries before the next round's appends
+        if constexpr (GEOM == FPT_GEOM_BOX) {
+            if (pinhole) sq_drain(P, B.film, T, SP, tally, q, cnt, lane, false);
+        }
+    }
+    if (walked > 0 && (int)lane == j) {
+        L.x[0] = Q.x[0]; L.x[1] = Q.x[1]; L.x[2] = Q.x[2];
+        L.w[0] = Q.w[0]; L.w[1] = Q.w[1]; L.w[2] = Q.w[2];
+        L.v += walked;
+        L.nsc += walked;
     }
 }
 
