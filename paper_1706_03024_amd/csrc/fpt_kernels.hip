@@ -494,6 +494,7 @@ __host__ __device__ inline int sq_words(const KParams& P) { return (P.glossy ? k
 struct SplatQ {
     uint32_t* base;  // this wave's ring: [5][kSqCap] words
     uint32_t* agg;   // this wave's deposit-merging table: kAggWords words
+    int held;        // its occupied slots
     int head, count;
     uint32_t* slice;  // this wave's slice of the deferred-connection buffer, or null
     int sj_n;         // entries written to it
@@ -527,13 +528,17 @@ DEV void sq_push(SplatQ& q, bool want, const float* x, uint32_t wa, uint32_t wb,
 // to the same pixel at the same wavelength, and a device atomic instruction
 // whose lanes hit one address is executed lane by lane at the memory side;
 // so the lanes first add their values into a small per-wave LDS hash table
-// keyed by film index (linear probing, at most 64 keys in kAggSlots slots),
-// and each occupied slot then issues one device atomic.  The table is empty
-// (keys kAggEmpty, values 0) between calls.  Film indices must fit 32 bits
-// below kAggEmpty (P.film_u32); larger films go out lane by lane.
+// keyed by film index (linear probing; empty slots hold key kAggEmpty and
+// value 0), and each occupied slot later issues one device atomic.  The table
+// keeps its keys from batch to batch -- the next batches of a long path land
+// mostly on the same elements -- and is written out once it holds more than
+// kAggKeep keys before a batch (so it is never more than (kAggKeep + 64) /
+// kAggSlots full) and when the wave ends.  Film indices must fit 32 bits below
+// kAggEmpty (P.film_u32); larger films go out lane by lane.
 constexpr int kAggSlots = 128;
 constexpr int kAggWords = 2 * kAggSlots;  // keys, then values
 constexpr uint32_t kAggEmpty = 0xFFFFFFFFu;
+constexpr int kAggKeep = 32;
 
 struct Deposit {
     bool has;
@@ -541,23 +546,10 @@ struct Deposit {
     float v;
 };
 
-DEV void film_add_merged(const KParams& P, float* film, uint32_t* agg, const Deposit& d, uint32_t lane) {
-    if (!P.film_u32) {
-        if (d.has) unsafeAtomicAdd(&film[d.idx], d.v);
-        return;
-    }
+// One device atomic per occupied slot, leaving the table empty (whole wave).
+DEV void agg_write_out(float* film, uint32_t* agg, uint32_t lane) {
     uint32_t* keys = agg;
     float* vals = reinterpret_cast<float*>(agg + kAggSlots);
-    if (d.has) {
-        const uint32_t key = (uint32_t)d.idx;
-        uint32_t h = (key * 0x9E3779B1u) >> 25;  // 7 bits: kAggSlots = 128
-        for (;;) {
-            const uint32_t old = atomicCAS(&keys[h], kAggEmpty, key);
-            if (old == kAggEmpty || old == key) break;
-            h = (h + 1u) & (uint32_t)(kAggSlots - 1);
-        }
-        atomicAdd(&vals[h], d.v);
-    }
     wave_sync();
 #pragma unroll
     for (int j = 0; j < kAggSlots / 64; ++j) {
@@ -569,6 +561,36 @@ DEV void film_add_merged(const KParams& P, float* film, uint32_t* agg, const Dep
             vals[sl] = 0.f;
         }
     }
+    wave_sync();
+}
+
+// Adds the lanes' deposits to the table (whole wave); `held` is the
+// wave-uniform count of its occupied slots.
+DEV void film_add_merged(const KParams& P, float* film, uint32_t* agg, int& held, const Deposit& d,
+                         uint32_t lane) {
+    if (!P.film_u32) {
+        if (d.has) unsafeAtomicAdd(&film[d.idx], d.v);
+        return;
+    }
+    if (held > kAggKeep) {
+        agg_write_out(film, agg, lane);
+        held = 0;
+    }
+    uint32_t* keys = agg;
+    float* vals = reinterpret_cast<float*>(agg + kAggSlots);
+    bool fresh = false;  // this lane's key took an empty slot
+    if (d.has) {
+        const uint32_t key = (uint32_t)d.idx;
+        uint32_t h = (key * 0x9E3779B1u) >> 25;  // 7 bits: kAggSlots = 128
+        for (;;) {
+            const uint32_t old = atomicCAS(&keys[h], kAggEmpty, key);
+            fresh = old == kAggEmpty;
+            if (fresh || old == key) break;
+            h = (h + 1u) & (uint32_t)(kAggSlots - 1);
+        }
+        atomicAdd(&vals[h], d.v);
+    }
+    held += __popcll(__ballot(fresh));
     wave_sync();
 }
 
@@ -632,7 +654,7 @@ DEV void sq_flush(const KParams& P, float* film, const uint32_t* T, const KSpher
     const float wgt = P.glossy ? __uint_as_float(q.base[5 * kSqCap + k]) : 1.f;
     const Deposit d = splat_entries(P, T, SP, tally, cnt, valid, x, q.base[3 * kSqCap + k], q.base[4 * kSqCap + k],
                                     wgt);
-    film_add_merged(P, film, q.agg, d, lane);
+    film_add_merged(P, film, q.agg, q.held, d, lane);
     q.head = (q.head + n) & (kSqCap - 1);
     q.count -= n;
     wave_sync();
@@ -1828,6 +1850,7 @@ __global__ void __launch_bounds__(256) k_transport(const KParams P, const KBuffe
     }
     W.q.head = 0;
     W.q.count = 0;
+    W.q.held = 0;
     const uint32_t gwave = blockIdx.x * (blockDim.x >> 6) + (uint32_t)__builtin_amdgcn_readfirstlane(wave);
     W.q.slice = (DEFER && B.sjobs) ? B.sjobs + (size_t)gwave * kEntryWords * B.sjob_slice : nullptr;
     W.q.sj_n = 0;
@@ -1885,6 +1908,9 @@ __global__ void __launch_bounds__(256) k_transport(const KParams P, const KBuffe
         if (exhausted && __ballot(W.alive) == 0ull) break;
     }
 
+    if constexpr (DEFER) {
+        if (W.q.held > 0) agg_write_out(B.film, W.q.agg, lane);  // the deposits still merging
+    }
     if (DEFER && W.q.slice && lane == 0) B.sjob_counts[gwave] = (uint32_t)W.q.sj_n;
     // ---- flush counters: per-lane -> wave -> block LDS -> global
     {
@@ -2007,6 +2033,7 @@ __global__ void __launch_bounds__(256) k_batch(const KBatch Bt) {
     W.q.agg = nullptr;
     W.q.head = 0;
     W.q.count = 0;
+    W.q.held = 0;
     W.q.slice = nullptr;
     W.q.sj_n = 0;
     AdjView A;
@@ -2106,6 +2133,7 @@ __global__ void __launch_bounds__(256) k_splat_jobs(const KParams P, const KBuff
         agg[kAggSlots + i] = 0u;
     }
     Counters cnt = {0u, 0u, 0u};
+    int held = 0;
     for (uint32_t b0 = wv * 64; b0 < n; b0 += blockDim.x) {  // uniform per wave
         const uint32_t i = b0 + lane;
         const bool valid = i < n;
@@ -2113,8 +2141,9 @@ __global__ void __launch_bounds__(256) k_splat_jobs(const KParams P, const KBuff
         const float x[3] = {__uint_as_float(sl[j]), __uint_as_float(sl[S + j]), __uint_as_float(sl[2 * S + j])};
         const float wgt = P.glossy ? __uint_as_float(sl[5 * S + j]) : 1.f;
         const Deposit d = splat_entries(P, T, SPw, tally, cnt, valid, x, sl[3 * S + j], sl[4 * S + j], wgt);
-        film_add_merged(P, B.film, agg, d, lane);
+        film_add_merged(P, B.film, agg, held, d, lane);
     }
+    if (held > 0) agg_write_out(B.film, agg, lane);
     uint32_t h = cnt.splat_hit;
     for (int off = 32; off > 0; off >>= 1) h += __shfl_xor(h, off);
     if (lane_id() == 0 && h) atomicAdd(&tally[FPT_T_SPLAT_HIT], h);
