@@ -55,17 +55,12 @@ def rebin(film, factor):
     if (n - 1) % factor:
         raise ValueError("the fine grid does not refine the coarse one")
     m = (n - 1) // factor + 1
-    w = torch.zeros((n, m), dtype=film.dtype, device=film.device)
-    h = factor / 2.0
-    for j in range(n):
-        # fine point j lies at coarse coordinate j / factor
-        for k in (j // factor, j // factor + 1):
-            if k < m:
-                dist = abs(j - k * factor)
-                if dist < h:
-                    w[j, k] = 1.0
-                elif dist == h:
-                    w[j, k] = 0.5
+    # distance of fine point j from coarse point k, in fine steps
+    dist = (torch.arange(n, device=film.device)[:, None] * 2
+            - torch.arange(m, device=film.device)[None, :] * (2 * factor)).abs()
+    one, half = torch.ones((), dtype=film.dtype, device=film.device), torch.tensor(0.5, dtype=film.dtype,
+                                                                                   device=film.device)
+    w = torch.where(dist < factor, one, torch.where(dist == factor, half, torch.zeros_like(one)))
     return film @ w
 
 
