@@ -139,12 +139,19 @@ struct Hit {
     int idx;  // wall face or sphere
 };
 
+// Exit distance of the ray x + t w from the sphere (c, r2) holding x.  Every
+// rounding is written out (explicit fma, contraction off): the copies of this
+// code inlined into the different walk loops then give the same bits, so the
+// loops take the same stop decisions (with contraction left to the compiler
+// two copies fused differently, and a path near a tie walked differently
+// depending on which loop served it).
 DEV float sphere_exit(const float* x, const float* w, const float* c, float r2) {
+#pragma clang fp contract(off)
     const float o0 = x[0] - c[0], o1 = x[1] - c[1], o2 = x[2] - c[2];
-    const float b = o0 * w[0] + o1 * w[1] + o2 * w[2];
-    const float cc = o0 * o0 + o1 * o1 + o2 * o2 - r2;
-    const float disc = b * b - cc;
-    return fmaxf(0.f, -b + fsqrt(fmaxf(disc, 0.f)));
+    const float b = __builtin_fmaf(o2, w[2], __builtin_fmaf(o1, w[1], o0 * w[0]));
+    const float cc = __builtin_fmaf(o2, o2, __builtin_fmaf(o1, o1, o0 * o0)) - r2;
+    const float disc = __builtin_fmaf(b, b, -cc);
+    return fmaxf(0.f, fsqrt(fmaxf(disc, 0.f)) - b);
 }
 
 template <int GEOM>
@@ -327,13 +334,18 @@ DEV KParamsArg kernel_params() {
 // w is at least L = P.tau_zero / sigma_t exactly when x + L w is inside too, so
 // the test is one point-in-sphere check instead of a chord (no square root).
 // inv_st = 1 / sigma_t of the vertex's medium and wavelength.
+// Roundings written out, as in sphere_exit: every walk loop counts the same
+// connections as opaque.
 DEV bool opaque_to_eye(const float* x, int region, float inv_st, const float* sc, float sr2) {
+#pragma clang fp contract(off)
     const auto& K = *kernel_params();
     if (region < 0 || !((K.sph_clear >> (uint32_t)region) & 1u)) return false;
     const float d0 = K.eye[0] - x[0], d1 = K.eye[1] - x[1], d2 = K.eye[2] - x[2];
-    const float s = K.tau_zero * inv_st * __builtin_amdgcn_rsqf(d0 * d0 + d1 * d1 + d2 * d2);
-    const float p0 = x[0] - sc[0] + s * d0, p1 = x[1] - sc[1] + s * d1, p2 = x[2] - sc[2] + s * d2;
-    return p0 * p0 + p1 * p1 + p2 * p2 <= sr2;
+    const float dd = __builtin_fmaf(d2, d2, __builtin_fmaf(d1, d1, d0 * d0));
+    const float s = K.tau_zero * inv_st * __builtin_amdgcn_rsqf(dd);
+    const float p0 = __builtin_fmaf(s, d0, x[0] - sc[0]), p1 = __builtin_fmaf(s, d1, x[1] - sc[1]),
+                p2 = __builtin_fmaf(s, d2, x[2] - sc[2]);
+    return __builtin_fmaf(p2, p2, __builtin_fmaf(p1, p1, p0 * p0)) <= sr2;
 }
 
 // -------------------------------------------------------------------------
@@ -727,7 +739,8 @@ DEV void score_length(const KParams& P, const uint32_t* T, const Lane& L, AdjVie
 // vertex that leaves the medium or is not a scatter.  The scatter vertices
 // before it are committed (and splat) in parallel; that vertex itself is left
 // to the ordinary step.  A round serves one path with 64 lanes, two with 32 or
-// four with 16.  The result depends on the path's state and the segment width.
+// four with 16.  Every width, and deep_round's 128-vertex rounds, give the
+// same bits: a path walks the same way whichever lanes share its wave.
 DEV float rl(float x, int j) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), j)); }
 // Cross-lane moves on the VALU (DPP) instead of through the LDS crossbar.
 // row_shr:d takes the value of lane i-d within each row of 16 lanes; lanes
@@ -766,6 +779,8 @@ DEV void block_walk(const KParams& P, const KBuffers& B, const uint32_t* T, cons
                     uint32_t* tally, Lane& L, uint64_t& elig, uint32_t lane, bool pinhole,
                     Counters& cnt, float* Sw, float* Gxl, float* G, bool& full, bool& deep, SplatQ& q,
                     bool exhausted, uint64_t deepmask) {
+    // the vertex arithmetic below must round exactly as deep_half's does
+#pragma clang fp contract(off)
     constexpr bool ADJ = (MODE == MODE_ADJ || MODE == MODE_REC_ADJ);
     constexpr bool REC = (MODE == MODE_REC || MODE == MODE_REC_ADJ);
     // segment width: one path per 64 lanes, two per 32, or four per 16.  A
@@ -848,7 +863,7 @@ DEV void block_walk(const KParams& P, const KBuffers& B, const uint32_t* T, cons
     const bool scat = u1 * Q.st < Q.ss;
     float sp, cp;
     sincos_rev(u3, &sp, &cp);
-    const float ct = 1.f - 2.f * u2, stt = 2.f * fsqrt(u2 * (1.f - u2));
+    const float ct = __builtin_fmaf(-2.f, u2, 1.f), stt = 2.f * fsqrt(u2 * (1.f - u2));
     const float wn[3] = {stt * cp, stt * sp, ct};
     // incoming direction of segment k: the new direction of vertex k-1
     float win[3];
@@ -891,8 +906,15 @@ DEV void block_walk(const KParams& P, const KBuffers& B, const uint32_t* T, cons
         }
     }
     tt += bt;
-    // segment k starts at p_k and, if it stays in the medium, ends at q_k
-    const float pk[3] = {b0 + (s0 - seg3[0]), b1 + (s1 - seg3[1]), b2 + (s2 - seg3[2])};
+    // segment k ends at q_k if it stays in the medium, and starts where
+    // segment k-1 ended (the segment's owner position for the first)
+    const float qk[3] = {b0 + s0, b1 + s1, b2 + s2};
+    float pk[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const float up = wave_shr1(qk[c], Q.x[c]);
+        pk[c] = pos == 0 ? Q.x[c] : up;
+    }
     const float dif = medium_exit<GEOM>(P, pk, win, Q.sc, Q.sr2);
     bool stop = !active || !(tk < dif) || !scat || (Q.nsc + pos + 1u > P.max_scatter) ||
                 (vk >= kMaxPathVertices);
@@ -903,9 +925,9 @@ DEV void block_walk(const KParams& P, const KBuffers& B, const uint32_t* T, cons
     const int kstar = mybits ? (__ffsll((unsigned long long)mybits) - 1) : W;
     const bool mine = active && (int)pos < kstar;
     Lane Lk = Q;
-    Lk.x[0] = b0 + s0;
-    Lk.x[1] = b1 + s1;
-    Lk.x[2] = b2 + s2;
+    Lk.x[0] = qk[0];
+    Lk.x[1] = qk[1];
+    Lk.x[2] = qk[2];
     float dep = 0.f;
     if (mine) {
         cnt.vertices++;
@@ -1037,6 +1059,8 @@ DEV void block_walk(const KParams& P, const KBuffers& B, const uint32_t* T, cons
 template <int GEOM>
 DEV void deep_half(const KParams& P, const Lane& Q, uint32_t v0, uint32_t lane, const float* wprev,
                    const float* xbase, float* wn, float* xk, float* pk, float* win, bool& stop_out) {
+    // the vertex arithmetic rounds exactly as block_walk's does
+#pragma clang fp contract(off)
     const uint32_t vk = v0 + 1u + lane;
     const uint4 r = philox(Q.pid, vk, 0u, 0u, P.key0, P.key1);
     const float u0 = u24(r.x), u1 = u24(r.y), u2 = u24(r.z), u3 = u24(r.w);
@@ -1044,7 +1068,7 @@ DEV void deep_half(const KParams& P, const Lane& Q, uint32_t v0, uint32_t lane, 
     const bool scat = u1 * Q.st < Q.ss;
     float sp, cp;
     sincos_rev(u3, &sp, &cp);
-    const float ct = 1.f - 2.f * u2, stt = 2.f * fsqrt(u2 * (1.f - u2));
+    const float ct = __builtin_fmaf(-2.f, u2, 1.f), stt = 2.f * fsqrt(u2 * (1.f - u2));
     wn[0] = stt * cp;
     wn[1] = stt * sp;
     wn[2] = ct;
@@ -1066,12 +1090,12 @@ DEV void deep_half(const KParams& P, const Lane& Q, uint32_t v0, uint32_t lane, 
     if (chunk > 0) { b0 += a15[0]; b1 += a15[1]; b2 += a15[2]; }
     if (chunk > 1) { b0 += a31[0]; b1 += a31[1]; b2 += a31[2]; }
     if (chunk > 2) { b0 += a47[0]; b1 += a47[1]; b2 += a47[2]; }
-    pk[0] = b0 + (s0 - seg3[0]);
-    pk[1] = b1 + (s1 - seg3[1]);
-    pk[2] = b2 + (s2 - seg3[2]);
     xk[0] = b0 + s0;
     xk[1] = b1 + s1;
     xk[2] = b2 + s2;
+    // each segment starts where the one before it ended
+#pragma unroll
+    for (int c = 0; c < 3; ++c) pk[c] = wave_shr1(xk[c], xbase[c]);
     const float dif = medium_exit<GEOM>(P, pk, win, Q.sc, Q.sr2);
     stop_out = !(tk < dif) || !scat || (Q.nsc + (vk - Q.v) > P.max_scatter) || (vk >= kMaxPathVertices);
     // the rr bits of the vertex's own uniforms, for its camera connection

@@ -401,6 +401,44 @@ def test_block_rounds_are_width_independent(scene_name):
         assert torch.equal(f, outs[0][0])
 
 
+
+def test_large_scene_paths_are_schedule_independent():
+    """At the large scene's full size (2^28 paths into the pinhole film) the
+    launch shape and the timing of the path queue decide which paths share a
+    wave, and with that which rounds walk each path (16, 32 or 64 lanes, or
+    128-vertex deep rounds).  Every shape gives the same paths bit for bit, so
+    every integer tally is identical, in repeated renders too.  Paths whose
+    stop decision sits within an ulp of a tie (a flight ending at a sphere's
+    surface; a few in 2^28) expose any difference between the rounding of the
+    rounds' code paths: before their arithmetic was written out, one or two
+    such paths per render walked differently from render to render.  The film
+    is a sum of float atomics in no fixed order, so it agrees to rounding."""
+    import torch
+    fpt = _fpt()
+    scene, run = workloads.large_config()
+    sc = fpt.Scene(scene)
+    base = {"block_min_vertices": 1}
+    outs = []
+    for tune in ({"block_threads": 256, "refill_lanes": 16, "block_segments": 4, "wide_rounds": 1},
+                 {"block_threads": 256, "refill_lanes": 16, "block_segments": 4, "wide_rounds": 1},
+                 {"block_segments": 1},
+                 {"block_segments": 2, "block_threads": 128, "refill_lanes": 40},
+                 {"block_segments": 4, "wide_rounds": -1},
+                 {"block_segments": 4, "wide_rounds": 2, "block_threads": 64, "refill_lanes": 1}):
+        sc.set_tune(**base, **tune)
+        t = fpt.new_tallies()
+        f = sc.render(run, tallies=t)
+        torch.cuda.synchronize()
+        outs.append((f.clone(), t.clone()))
+        print("tune", tune, "vertices", int(t[1]), flush=True)
+    sc.close()
+    f0, t0 = outs[0]
+    tol = 1e-5 * float(f0.abs().max())
+    for f, t in outs[1:]:
+        assert torch.equal(t, t0), (fpt.tallies_dict(t), fpt.tallies_dict(t0))
+        assert torch.allclose(f, f0, rtol=1e-3, atol=tol)
+
+
 def test_tabulated_spectra():
     """Tabulated spectra (one value per grid point, as measured spectra come):
     the Cornell scene with every spectrum sampled on its grid has the same fp32
