@@ -756,6 +756,34 @@ DEV float wave_shr1(float x, float first) {
     return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(first), __float_as_int(x), 0x138, 0xf, 0xf,
                                                       false));
 }
+// Chains the rows of three prefix-summed values in place: row 0 (lanes 0..15)
+// adds a base (ba, bb, bc), then row r adds lane 15 of row r-1, for r = 1, 2
+// and 3 in turn (DPP with one row enabled at a time; the other rows keep
+// their values).  Row r ends up with its own prefix sums plus the base and the
+// totals of chunks 0..r-1 added one at a time.  Written in assembly because
+// the compiler folds a DPP move into a float add only with every row enabled
+// (a move, an add and a constant per step otherwise).  Each add reads its
+// operand at least two instructions after writing it (the two wait states a
+// DPP read needs after a VALU write); the s_nop covers the instructions before
+// the block (five wait states, as after an EXEC write).  The whole wave must
+// be active.
+DEV void chain_rows3(float& a, float& b, float& c, float ba, float bb, float bc) {
+    asm("s_nop 4\n\t"
+        "v_add_f32_dpp %0, %3, %0 quad_perm:[0,1,2,3] row_mask:0x1 bank_mask:0xf\n\t"
+        "v_add_f32_dpp %1, %4, %1 quad_perm:[0,1,2,3] row_mask:0x1 bank_mask:0xf\n\t"
+        "v_add_f32_dpp %2, %5, %2 quad_perm:[0,1,2,3] row_mask:0x1 bank_mask:0xf\n\t"
+        "v_add_f32_dpp %0, %0, %0 row_bcast:15 row_mask:0x2 bank_mask:0xf\n\t"
+        "v_add_f32_dpp %1, %1, %1 row_bcast:15 row_mask:0x2 bank_mask:0xf\n\t"
+        "v_add_f32_dpp %2, %2, %2 row_bcast:15 row_mask:0x2 bank_mask:0xf\n\t"
+        "v_add_f32_dpp %0, %0, %0 row_bcast:15 row_mask:0x4 bank_mask:0xf\n\t"
+        "v_add_f32_dpp %1, %1, %1 row_bcast:15 row_mask:0x4 bank_mask:0xf\n\t"
+        "v_add_f32_dpp %2, %2, %2 row_bcast:15 row_mask:0x4 bank_mask:0xf\n\t"
+        "v_add_f32_dpp %0, %0, %0 row_bcast:15 row_mask:0x8 bank_mask:0xf\n\t"
+        "v_add_f32_dpp %1, %1, %1 row_bcast:15 row_mask:0x8 bank_mask:0xf\n\t"
+        "v_add_f32_dpp %2, %2, %2 row_bcast:15 row_mask:0x8 bank_mask:0xf"
+        : "+v"(a), "+v"(b), "+v"(c)
+        : "v"(ba), "v"(bb), "v"(bc));
+}
 DEV int rli(int x, int j) { return __builtin_amdgcn_readlane(x, j); }
 DEV uint32_t rlu(uint32_t x, int j) { return (uint32_t)__builtin_amdgcn_readlane((int)x, j); }
 
@@ -1082,17 +1110,13 @@ DEV void deep_half(const KParams& P, const Lane& Q, uint32_t v0, uint32_t lane, 
     FPT_SCAN3(4)
     FPT_SCAN3(8)
 #undef FPT_SCAN3
-    float b0 = xbase[0], b1 = xbase[1], b2 = xbase[2];
-    const int chunk = (int)(lane >> 4);
-    const float a15[3] = {rl(s0, 15), rl(s1, 15), rl(s2, 15)};
-    const float a31[3] = {rl(s0, 31), rl(s1, 31), rl(s2, 31)};
-    const float a47[3] = {rl(s0, 47), rl(s1, 47), rl(s2, 47)};
-    if (chunk > 0) { b0 += a15[0]; b1 += a15[1]; b2 += a15[2]; }
-    if (chunk > 1) { b0 += a31[0]; b1 += a31[1]; b2 += a31[2]; }
-    if (chunk > 2) { b0 += a47[0]; b1 += a47[1]; b2 += a47[2]; }
-    xk[0] = b0 + s0;
-    xk[1] = b1 + s1;
-    xk[2] = b2 + s2;
+    // chunk 0 adds the base, then each chunk the position its predecessor
+    // ended at: the chunk totals chained in order, exactly as block_walk's
+    // readlane adds chain them (a + b rounds as b + a)
+    xk[0] = s0;
+    xk[1] = s1;
+    xk[2] = s2;
+    chain_rows3(xk[0], xk[1], xk[2], xbase[0], xbase[1], xbase[2]);
     // each segment starts where the one before it ended
 #pragma unroll
     for (int c = 0; c < 3; ++c) pk[c] = wave_shr1(xk[c], xbase[c]);
@@ -1100,6 +1124,43 @@ DEV void deep_half(const KParams& P, const Lane& Q, uint32_t v0, uint32_t lane, 
     stop_out = !(tk < dif) || !scat || (Q.nsc + (vk - Q.v) > P.max_scatter) || (vk >= kMaxPathVertices);
     // the rr bits of the vertex's own uniforms, for its camera connection
     xk[3] = __uint_as_float(rr_bits(r));
+}
+
+// The camera connections of one half of a deep round, all of one path: one
+// wavelength, component, parity slice and sphere.  When every committed
+// vertex of the half connects (none was found opaque), its sphere passes the
+// geometric tests (P.geo_clear) and the path queue is not yet exhausted, the
+// half evaluates them in place, with as many lanes busy as a full ring batch
+// and the path's values uniform; the ring's push, read-back and decode are
+// saved.  Otherwise they join the ring.  `committed`: the half's committed
+// lanes; x[3] holds the vertex's roulette bits.
+template <bool GLOSS>
+DEV void deep_connect(const KParams& P, const KBuffers& B, const uint32_t* T, const KSphere* SP, uint32_t* tally,
+                      SplatQ& q, Counters& cnt, uint32_t lane, bool want, uint64_t committed, const float* x,
+                      const Lane& Q, uint32_t wb, bool exhausted) {
+    const uint64_t wm = __ballot(want);
+    const auto& K = *kernel_params();
+    if (wm && wm == committed && !exhausted && Q.region >= 0 && ((K.geo_clear >> (uint32_t)Q.region) & 1u)) {
+        Deposit d;
+        d.has = false;
+        d.idx = 0;
+        d.v = 0.f;
+        if (want) {
+            const float zero3[3] = {0.f, 0.f, 0.f};
+            const SplatOut so = splat_eval<true>(T, SP, x, Q.lam, Q.comp, Q.batch, PEND_MEDIUM, zero3,
+                                                 __float_as_uint(x[3]), GLOSS ? Q.wgt : 1.f,
+                                                 K.sph_occl[Q.region]);
+            d.has = so.status == 0 && so.v != 0.f;  // +0 changes nothing
+            d.idx = so.idx;
+            d.v = so.v;
+            if (so.status == 0) cnt.splat_hit++;
+            else lds_count(tally, so.status == 2 ? FPT_T_SPLAT_RR_KILL : FPT_T_SPLAT_MISS);
+        }
+        film_add_merged(P, B.film, q.agg, q.held, d, lane);
+        return;
+    }
+    splat_defer<GLOSS>(B, q, want, x, sq_word_a(__float_as_uint(x[3]), PEND_MEDIUM, Q.region, Q.comp), wb,
+                       GLOSS ? Q.wgt : 1.f, exhausted);
 }
 
 // Consecutive rounds of one path run in one call while each commits all 128
@@ -1154,16 +1215,15 @@ DEV void deep_round(const KParams& P, const KBuffers& B, const uint32_t* T, cons
                 const bool o1 = m1 && dep && opaque_to_eye(x1, Q.region, Q.inv, Q.sc, Q.sr2);
                 count_opaque(tally, cnt, o1);
                 const bool w1 = m1 && dep && !o1;
-                splat_defer<GLOSS>(B, q, w1, x1, sq_word_a(__float_as_uint(x1[3]), PEND_MEDIUM, Q.region, Q.comp),
-                                   wb, Q.wgt, exhausted);
+                const uint64_t c1 = k1 >= 64 ? ~0ull : ((1ull << k1) - 1ull);
+                deep_connect<GLOSS>(P, B, T, SP, tally, q, cnt, lane, w1, c1, x1, Q, wb, exhausted);
                 sq_drain(P, B.film, T, SP, tally, q, cnt, lane, false);
                 if (k2 > 0) {
                     const bool o2 = m2 && dep && opaque_to_eye(x2, Q.region, Q.inv, Q.sc, Q.sr2);
                     count_opaque(tally, cnt, o2);
                     const bool w2 = m2 && dep && !o2;
-                    splat_defer<GLOSS>(B, q, w2, x2,
-                                       sq_word_a(__float_as_uint(x2[3]), PEND_MEDIUM, Q.region, Q.comp), wb,
-                                       Q.wgt, exhausted);
+                    const uint64_t c2 = k2 >= 64 ? ~0ull : ((1ull << k2) - 1ull);
+                    deep_connect<GLOSS>(P, B, T, SP, tally, q, cnt, lane, w2, c2, x2, Q, wb, exhausted);
                 }
             }
         }
