@@ -1078,12 +1078,13 @@ DEV void block_walk(const KParams& P, const KBuffers& B, const uint32_t* T, cons
 }
 
 // A deep path in a forward render (its last round ran the whole wave) walks
-// 128 vertices per round: lane k draws vertices v+1+k and v+65+k.  The second
-// half's generator and direction work is independent of the first half, so
-// the two interleave; its positions chain from the first half's last vertex
-// exactly as a following 64-lane round would, so the result is the same as
-// two consecutive rounds (and the second half counts only if the first one
-// committed all 64 vertices).
+// 128 vertices per round: lane k draws vertices v+1+k and, once the first 64
+// are all committed, v+65+k.  The second half's positions chain from the
+// first half's last vertex exactly as a following 64-lane round would, so
+// the result is the same as two consecutive rounds.  (Drawing both halves
+// together, for the overlap of their independent generator work, cost 1.4 %
+// more on the large scene: the waves of a full chip hide that latency anyway,
+// and a round that stops in its first half then wasted the second.)
 template <int GEOM>
 DEV void deep_half(const KParams& P, const Lane& Q, uint32_t v0, uint32_t lane, const float* wprev,
                    const float* xbase, float* wn, float* xk, float* pk, float* win, bool& stop_out) {
@@ -1200,13 +1201,19 @@ DEV void deep_round(const KParams& P, const KBuffers& B, const uint32_t* T, cons
         float wn1[3], x1[4], p1[3], win1[3], wn2[3], x2[4], p2[3], win2[3];
         bool st1, st2;
         deep_half<GEOM>(P, Q, Q.v, lane, Q.w, Q.x, wn1, x1, p1, win1, st1);
-        // the second half starts from the state after the first half's vertex 64
-        const float w64[3] = {rl(wn1[0], 63), rl(wn1[1], 63), rl(wn1[2], 63)};
-        const float x64[3] = {rl(x1[0], 63), rl(x1[1], 63), rl(x1[2], 63)};
-        deep_half<GEOM>(P, Q, Q.v + 64u, lane, w64, x64, wn2, x2, p2, win2, st2);
-        const uint64_t sm1 = __ballot(st1), sm2 = __ballot(st2);
+        const uint64_t sm1 = __ballot(st1);
         const int k1 = sm1 ? (__ffsll((unsigned long long)sm1) - 1) : 64;
-        const int k2 = k1 < 64 ? 0 : (sm2 ? (__ffsll((unsigned long long)sm2) - 1) : 64);
+        int k2 = 0;
+        x2[0] = x2[1] = x2[2] = x2[3] = 0.f;
+        wn2[0] = wn2[1] = wn2[2] = 0.f;
+        if (k1 == 64) {
+            // the second half starts from the state after the first half's vertex 64
+            const float w64[3] = {rl(wn1[0], 63), rl(wn1[1], 63), rl(wn1[2], 63)};
+            const float x64[3] = {rl(x1[0], 63), rl(x1[1], 63), rl(x1[2], 63)};
+            deep_half<GEOM>(P, Q, Q.v + 64u, lane, w64, x64, wn2, x2, p2, win2, st2);
+            const uint64_t sm2 = __ballot(st2);
+            k2 = sm2 ? (__ffsll((unsigned long long)sm2) - 1) : 64;
+        }
         const bool m1 = (int)lane < k1, m2 = (int)lane < k2;
         cnt.vertices += (uint32_t)m1 + (uint32_t)m2;
         cnt.scatters += (uint32_t)m1 + (uint32_t)m2;
