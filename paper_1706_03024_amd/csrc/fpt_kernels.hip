@@ -1113,11 +1113,29 @@ DEV void deep_half(const KParams& P, const Lane& Q, uint32_t v0, uint32_t lane, 
 #undef FPT_SCAN3
     // chunk 0 adds the base, then each chunk the position its predecessor
     // ended at: the chunk totals chained in order, exactly as block_walk's
-    // readlane adds chain them (a + b rounds as b + a)
-    xk[0] = s0;
-    xk[1] = s1;
-    xk[2] = s2;
-    chain_rows3(xk[0], xk[1], xk[2], xbase[0], xbase[1], xbase[2]);
+    // readlane adds chain them (a + b rounds as b + a).  The DPP chain is
+    // used by the box kernel only: in the smaller body-medium kernels its
+    // operands in vector registers cost more registers (occupancy) than the
+    // readlanes it saves (slab, 2^22 paths: 0.79 ms with readlanes, 0.87 ms
+    // with the chain).
+    if constexpr (GEOM == FPT_GEOM_BOX) {
+        xk[0] = s0;
+        xk[1] = s1;
+        xk[2] = s2;
+        chain_rows3(xk[0], xk[1], xk[2], xbase[0], xbase[1], xbase[2]);
+    } else {
+        float b0 = xbase[0], b1 = xbase[1], b2 = xbase[2];
+        const int chunk = (int)(lane >> 4);
+        const float a15[3] = {rl(s0, 15), rl(s1, 15), rl(s2, 15)};
+        const float a31[3] = {rl(s0, 31), rl(s1, 31), rl(s2, 31)};
+        const float a47[3] = {rl(s0, 47), rl(s1, 47), rl(s2, 47)};
+        if (chunk > 0) { b0 += a15[0]; b1 += a15[1]; b2 += a15[2]; }
+        if (chunk > 1) { b0 += a31[0]; b1 += a31[1]; b2 += a31[2]; }
+        if (chunk > 2) { b0 += a47[0]; b1 += a47[1]; b2 += a47[2]; }
+        xk[0] = b0 + s0;
+        xk[1] = b1 + s1;
+        xk[2] = b2 + s2;
+    }
     // each segment starts where the one before it ended
 #pragma unroll
     for (int c = 0; c < 3; ++c) pk[c] = wave_shr1(xk[c], xbase[c]);
