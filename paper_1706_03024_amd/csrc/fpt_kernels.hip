@@ -1145,6 +1145,51 @@ DEV void deep_half(const KParams& P, const Lane& Q, uint32_t v0, uint32_t lane, 
     xk[3] = __uint_as_float(rr_bits(r));
 }
 
+// splat_eval's CLEAR form for the usual case of a deep round's half: a
+// medium vertex inside sphere sp, whose only possible occluder is sp itself,
+// with the film's element count below 2^32.  The same operations in the same
+// order (so the same deposit), written for that case: one chord, the medium's
+// factor, 32-bit film indices.  `base` = ((batch * 2 + comp) * H * W) * N + lam,
+// uniform over the half.  Roulette and its status as in splat_eval.
+DEV SplatOut splat_own_sphere(const uint32_t* S, const KSphere& sp, const float* x, int lam, uint32_t base,
+                              uint32_t rrb, float wgt) {
+    const auto& P = *kernel_params();
+    const float d[3] = {P.eye[0] - x[0], P.eye[1] - x[1], P.eye[2] - x[2]};
+    const float dist2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+    const float rdist = __builtin_amdgcn_rsqf(dist2);
+    const float dist = dist2 * rdist;
+    const float wc[3] = {d[0] * rdist, d[1] * rdist, d[2] * rdist};
+    const float zc = -(d[0] * P.cf[0] + d[1] * P.cf[1] + d[2] * P.cf[2]);
+    const float izc = __builtin_amdgcn_rcpf(zc);
+    const float xi = -(d[0] * P.cr[0] + d[1] * P.cr[1] + d[2] * P.cr[2]) * izc * P.inv_tanx;
+    const float yi = -(d[0] * P.cu[0] + d[1] * P.cu[1] + d[2] * P.cu[2]) * izc * P.inv_tany;
+    const float fx = (xi + 1.f) * 0.5f * (float)P.W;
+    const float fy = (1.f - yi) * 0.5f * (float)P.H;
+    const float o0 = x[0] - sp.c[0], o1 = x[1] - sp.c[1], o2 = x[2] - sp.c[2];
+    const float b = o0 * wc[0] + o1 * wc[1] + o2 * wc[2];
+    const float p0 = o0 - b * wc[0], p1 = o1 - b * wc[1], p2 = o2 - b * wc[2];
+    const float disc = sp.r2 - (p0 * p0 + p1 * p1 + p2 * p2);
+    const float sq = fsqrt(fmaxf(disc, 0.f));
+    const float lo = fmaxf(-b - sq, 0.f), hi = fminf(-b + sq, dist);
+    const float len = disc > 0.f ? fmaxf(hi - lo, 0.f) : 0.f;
+    const float tau = 0.f + wf(S, sp.st_row + 2 * lam) * len;
+    const float tr = tau < kTauZero ? __expf(-tau) : 0.f;
+    const float cosc = zc * rdist;
+    float v = P.wscale * kInv4Pi * tr * P.splat_norm * __builtin_amdgcn_rcpf(cosc * cosc * cosc * dist2) * wgt;
+    SplatOut o;
+    o.status = 0;
+    if (P.splat_rr > 0.f && tr < P.splat_rr) {
+        const float q = tr * P.inv_splat_rr;
+        const float u = (float)rrb * 5.9604644775390625e-08f;
+        if (!(u < q)) o.status = 2;
+        v = fdiv(v, q);
+    }
+    o.v = o.status == 0 ? v : 0.f;
+    const int px = max(min((int)fx, P.W - 1), 0), py = max(min((int)fy, P.H - 1), 0);
+    o.idx = (long long)(base + (uint32_t)(py * P.W + px) * (uint32_t)P.N);
+    return o;
+}
+
 // The camera connections of one half of a deep round, all of one path: one
 // wavelength, component, parity slice and sphere.  When every committed
 // vertex of the half connects (none was found opaque), its sphere passes the
@@ -1164,11 +1209,16 @@ DEV void deep_connect(const KParams& P, const KBuffers& B, const uint32_t* T, co
         d.has = false;
         d.idx = 0;
         d.v = 0.f;
+        const uint32_t occl = K.sph_occl[Q.region];
+        const bool own = occl == (1u << (uint32_t)Q.region) && K.film_u32;
+        const uint32_t base = (((uint32_t)Q.batch * 2u + (uint32_t)Q.comp) * (uint32_t)(K.H * K.W)) * (uint32_t)K.N +
+                              (uint32_t)Q.lam;
         if (want) {
             const float zero3[3] = {0.f, 0.f, 0.f};
-            const SplatOut so = splat_eval<true>(T, SP, x, Q.lam, Q.comp, Q.batch, PEND_MEDIUM, zero3,
-                                                 __float_as_uint(x[3]), GLOSS ? Q.wgt : 1.f,
-                                                 K.sph_occl[Q.region]);
+            const SplatOut so = own ? splat_own_sphere(T, SP[Q.region], x, Q.lam, base, __float_as_uint(x[3]),
+                                                       GLOSS ? Q.wgt : 1.f)
+                                    : splat_eval<true>(T, SP, x, Q.lam, Q.comp, Q.batch, PEND_MEDIUM, zero3,
+                                                       __float_as_uint(x[3]), GLOSS ? Q.wgt : 1.f, occl);
             d.has = so.status == 0 && so.v != 0.f;  // +0 changes nothing
             d.idx = so.idx;
             d.v = so.v;
