@@ -22,7 +22,7 @@ namespace fpt {
 
 constexpr float kInf = __builtin_inff();
 constexpr uint32_t kMaxPathVertices = 1u << 28;
-constexpr int kBlockPasses = 4;   // block passes per iteration for paths that never stop
+constexpr int kBlockPasses = 4;   // block passes per iteration for paths that never stop (see advance)
 constexpr int kLdsSpheres = 32;
 constexpr int kQueueShards = 64;   // path-queue heads (see k_transport)
 constexpr int kShardStride = 16;   // u64 words between heads: separate 128-byte lines                                // word offset of the sphere table
@@ -1481,8 +1481,14 @@ DEV void advance(const KParams& P, const KBuffers& B, const WaveCtx& C, WalkStat
     if (dm) __builtin_amdgcn_s_setprio(2);
     if constexpr (MODE != MODE_REC_ADJ) {
         // paths whose last block ran its full width without stopping go again,
-        // up to kBlockPasses passes per iteration
-        for (int pass = 0; pass < kBlockPasses; ++pass) {
+        // up to kBlockPasses passes per iteration.  The box forward kernel takes
+        // one: such a path skips its step and goes again in the next iteration.
+        // There further passes kept loop-invariant lane masks live across its
+        // large round code, spilled to VGPR lanes (four passes: the large scene
+        // 0.8 % slower), while the slab and adjoint kernels gain from them
+        // (one pass: 4 % and 1.5 % slower).
+        constexpr int kPasses = (GEOM == FPT_GEOM_BOX && MODE == MODE_FWD) ? 1 : kBlockPasses;
+        for (int pass = 0; pass < kPasses; ++pass) {
             uint64_t elig = __ballot(alive && !fresh && L.v >= P.block_min_v && L.medium >= 0 &&
                                      L.st > 0.f && (P.exc_scatter || L.nem > 0u) &&
                                      (pass == 0 || full));
