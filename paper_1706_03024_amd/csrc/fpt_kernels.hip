@@ -461,6 +461,7 @@ DEV SplatOut splat_eval(const uint32_t* S, const KSphere* SP, const float* x, in
 // Per-block LDS tally of rare events (u32) and per-lane counters of frequent ones.
 struct Counters {
     uint32_t vertices, scatters, splat_hit;
+    uint32_t opaque;  // connections known to deposit exactly 0 (count_opaque)
 };
 
 DEV void lds_count(uint32_t* tally, int slot) { atomicAdd(&tally[slot], 1u); }
@@ -470,15 +471,18 @@ DEV void lds_count(uint32_t* tally, int slot) { atomicAdd(&tally[slot], 1u); }
 // splat_rr > 0 a roulette kill, and the count of such connections.  Called by
 // the whole wave.
 DEV void count_opaque(uint32_t* tally, Counters& cnt, bool opaque) {
-    const uint64_t m = __ballot(opaque);
-    if (!m) return;
-    const bool rr = kernel_params()->splat_rr > 0.f;
-    if (opaque && !rr) cnt.splat_hit++;
-    if (lane_id() == (uint32_t)(__ffsll((unsigned long long)m) - 1)) {
-        const uint32_t n = (uint32_t)__popcll(m);
-        atomicAdd(&tally[FPT_T_SPLAT_OPAQUE], n);
-        if (rr) atomicAdd(&tally[FPT_T_SPLAT_RR_KILL], n);
+    if (kernel_params()->splat_rr > 0.f) {  // roulette kills: rare runs, counted in LDS
+        const uint64_t m = __ballot(opaque);
+        if (m && lane_id() == (uint32_t)(__ffsll((unsigned long long)m) - 1)) {
+            const uint32_t n = (uint32_t)__popcll(m);
+            atomicAdd(&tally[FPT_T_SPLAT_OPAQUE], n);
+            atomicAdd(&tally[FPT_T_SPLAT_RR_KILL], n);
+        }
+        return;
     }
+    // hits: per-lane counters, summed when the wave ends
+    cnt.opaque += opaque ? 1u : 0u;
+    cnt.splat_hit += opaque ? 1u : 0u;
 }
 
 DEV void wave_sync() {
@@ -1992,7 +1996,7 @@ __global__ void __launch_bounds__(256) k_transport(const KParams P, const KBuffe
     C.pinhole = (GEOM == FPT_GEOM_BOX) && P.sensor == FPT_SENSOR_PINHOLE;
     C.lane = lane;
     WalkState W;
-    W.cnt = {0u, 0u, 0u};
+    W.cnt = {0u, 0u, 0u, 0u};
     W.L.pid = 0;
     W.alive = false;
     W.deep = false;
@@ -2079,16 +2083,18 @@ __global__ void __launch_bounds__(256) k_transport(const KParams P, const KBuffe
     if (DEFER && W.q.slice && lane == 0) B.sjob_counts[gwave] = (uint32_t)W.q.sj_n;
     // ---- flush counters: per-lane -> wave -> block LDS -> global
     {
-        uint32_t a = W.cnt.vertices, b = W.cnt.scatters, c = W.cnt.splat_hit;
+        uint32_t a = W.cnt.vertices, b = W.cnt.scatters, c = W.cnt.splat_hit, o = W.cnt.opaque;
         for (int off = 32; off > 0; off >>= 1) {
             a += __shfl_xor(a, off);
             b += __shfl_xor(b, off);
             c += __shfl_xor(c, off);
+            o += __shfl_xor(o, off);
         }
         if (lane == 0) {
             atomicAdd(&tally[FPT_T_VERTICES], a);
             atomicAdd(&tally[FPT_T_SCATTERS], b);
             atomicAdd(&tally[FPT_T_SPLAT_HIT], c);
+            if (o) atomicAdd(&tally[FPT_T_SPLAT_OPAQUE], o);
         }
     }
     if constexpr (ADJ && !REC) {
@@ -2143,7 +2149,7 @@ DEV void batch_flush(const KBatch& Bt, int inst, uint32_t* tally, uint32_t* hist
         b += __shfl_xor(b, off);
         c += __shfl_xor(c, off);
     }
-    cnt = {0u, 0u, 0u};
+    cnt = {0u, 0u, 0u, 0u};
     if (lane == 0) {
         tally[FPT_T_VERTICES] += a;
         tally[FPT_T_SCATTERS] += b;
@@ -2182,7 +2188,7 @@ __global__ void __launch_bounds__(256) k_batch(const KBatch Bt) {
     C.pinhole = false;
     C.lane = lane;
     WalkState W;
-    W.cnt = {0u, 0u, 0u};
+    W.cnt = {0u, 0u, 0u, 0u};
     W.L.pid = 0;
     W.alive = false;
     W.deep = false;
@@ -2297,7 +2303,7 @@ __global__ void __launch_bounds__(256) k_splat_jobs(const KParams P, const KBuff
         agg[i] = kAggEmpty;
         agg[kAggSlots + i] = 0u;
     }
-    Counters cnt = {0u, 0u, 0u};
+    Counters cnt = {0u, 0u, 0u, 0u};
     int held = 0;
     for (uint32_t b0 = wv * 64; b0 < n; b0 += blockDim.x) {  // uniform per wave
         const uint32_t i = b0 + lane;
@@ -2723,7 +2729,7 @@ __global__ void __launch_bounds__(256) k_camera(const KParams P, const KBuffers 
     C.fidx = 0;
     C.L.pid = 0u;
     C.L.v = 0u;
-    Counters cnt = {0u, 0u, 0u};
+    Counters cnt = {0u, 0u, 0u, 0u};
     bool alive = false, exhausted = false;
     bool seq_next = false;  // the lane's last wave round stopped short of 64 vertices
     uint32_t q_next = 0u, q_end = 0u;  // the wave's current chunk of path indices (uniform)
