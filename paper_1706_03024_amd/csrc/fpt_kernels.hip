@@ -768,9 +768,12 @@ DEV float wave_shr1(float x, float first) {
 // the compiler folds a DPP move into a float add only with every row enabled
 // (a move, an add and a constant per step otherwise).  Each add reads its
 // operand at least two instructions after writing it (the two wait states a
-// DPP read needs after a VALU write); the s_nop covers the instructions before
-// the block (five wait states, as after an EXEC write).  The whole wave must
-// be active.
+// DPP read needs after a VALU write); the leading s_nop covers the
+// instructions before the block (five wait states, as after an EXEC write) and
+// the trailing one those after it: the compiler's hazard checks do not see
+// the block's writes as VALU results, so a DPP read of a result right after
+// the block would otherwise get no wait states.  The whole wave must be
+// active.
 DEV void chain_rows3(float& a, float& b, float& c, float ba, float bb, float bc) {
     asm("s_nop 4\n\t"
         "v_add_f32_dpp %0, %3, %0 quad_perm:[0,1,2,3] row_mask:0x1 bank_mask:0xf\n\t"
@@ -784,7 +787,8 @@ DEV void chain_rows3(float& a, float& b, float& c, float ba, float bb, float bc)
         "v_add_f32_dpp %2, %2, %2 row_bcast:15 row_mask:0x4 bank_mask:0xf\n\t"
         "v_add_f32_dpp %0, %0, %0 row_bcast:15 row_mask:0x8 bank_mask:0xf\n\t"
         "v_add_f32_dpp %1, %1, %1 row_bcast:15 row_mask:0x8 bank_mask:0xf\n\t"
-        "v_add_f32_dpp %2, %2, %2 row_bcast:15 row_mask:0x8 bank_mask:0xf"
+        "v_add_f32_dpp %2, %2, %2 row_bcast:15 row_mask:0x8 bank_mask:0xf\n\t"
+        "s_nop 1"
         : "+v"(a), "+v"(b), "+v"(c)
         : "v"(ba), "v"(bb), "v"(bc));
 }
