@@ -348,6 +348,38 @@ DEV bool opaque_to_eye(const float* x, int region, float inv_st, const float* sc
     return __builtin_fmaf(p2, p2, __builtin_fmaf(p1, p1, p0 * p0)) <= sr2;
 }
 
+// The segment from a medium vertex x to the eye, shared by a deep round's
+// opaque test and its in-place evaluation: d = eye - x, |d|^2 as the fma chain
+// opaque_to_eye forms it, its reciprocal square root, and x minus the centre
+// of the vertex's sphere.
+struct EyeRay {
+    float d[3], dist2, rdist, o[3];
+};
+DEV EyeRay eye_ray(const float* x, const float* sc) {
+#pragma clang fp contract(off)
+    const auto& K = *kernel_params();
+    EyeRay r;
+    r.d[0] = K.eye[0] - x[0];
+    r.d[1] = K.eye[1] - x[1];
+    r.d[2] = K.eye[2] - x[2];
+    r.dist2 = __builtin_fmaf(r.d[2], r.d[2], __builtin_fmaf(r.d[1], r.d[1], r.d[0] * r.d[0]));
+    r.rdist = __builtin_amdgcn_rsqf(r.dist2);
+    r.o[0] = x[0] - sc[0];
+    r.o[1] = x[1] - sc[1];
+    r.o[2] = x[2] - sc[2];
+    return r;
+}
+// opaque_to_eye from a precomputed ray (the same operations).
+DEV bool opaque_to_eye(const EyeRay& r, int region, float inv_st, float sr2) {
+#pragma clang fp contract(off)
+    const auto& K = *kernel_params();
+    if (region < 0 || !((K.sph_clear >> (uint32_t)region) & 1u)) return false;
+    const float s = K.tau_zero * inv_st * r.rdist;
+    const float p0 = __builtin_fmaf(s, r.d[0], r.o[0]), p1 = __builtin_fmaf(s, r.d[1], r.o[1]),
+                p2 = __builtin_fmaf(s, r.d[2], r.o[2]);
+    return __builtin_fmaf(p2, p2, __builtin_fmaf(p1, p1, p0 * p0)) <= sr2;
+}
+
 // -------------------------------------------------------------------------
 // Pinhole splat at a realised vertex (eqs. 3-6).  Returns the deposited value
 // (0 if rejected) and the film index.  f = 1/(4 pi) in a medium, cos/pi on a
@@ -1159,12 +1191,12 @@ DEV void deep_half(const KParams& P, const Lane& Q, uint32_t v0, uint32_t lane, 
 // order (so the same deposit), written for that case: one chord, the medium's
 // factor, 32-bit film indices.  `base` = ((batch * 2 + comp) * H * W) * N + lam,
 // uniform over the half.  Roulette and its status as in splat_eval.
-DEV SplatOut splat_own_sphere(const uint32_t* S, const KSphere& sp, const float* x, int lam, uint32_t base,
+DEV SplatOut splat_own_sphere(const uint32_t* S, const KSphere& sp, const EyeRay& ray, int lam, uint32_t base,
                               uint32_t rrb, float wgt) {
     const auto& P = *kernel_params();
-    const float d[3] = {P.eye[0] - x[0], P.eye[1] - x[1], P.eye[2] - x[2]};
-    const float dist2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
-    const float rdist = __builtin_amdgcn_rsqf(dist2);
+    const float* d = ray.d;
+    const float dist2 = ray.dist2;
+    const float rdist = ray.rdist;
     const float dist = dist2 * rdist;
     const float wc[3] = {d[0] * rdist, d[1] * rdist, d[2] * rdist};
     const float zc = -(d[0] * P.cf[0] + d[1] * P.cf[1] + d[2] * P.cf[2]);
@@ -1173,7 +1205,7 @@ DEV SplatOut splat_own_sphere(const uint32_t* S, const KSphere& sp, const float*
     const float yi = -(d[0] * P.cu[0] + d[1] * P.cu[1] + d[2] * P.cu[2]) * izc * P.inv_tany;
     const float fx = (xi + 1.f) * 0.5f * (float)P.W;
     const float fy = (1.f - yi) * 0.5f * (float)P.H;
-    const float o0 = x[0] - sp.c[0], o1 = x[1] - sp.c[1], o2 = x[2] - sp.c[2];
+    const float o0 = ray.o[0], o1 = ray.o[1], o2 = ray.o[2];
     const float b = o0 * wc[0] + o1 * wc[1] + o2 * wc[2];
     const float p0 = o0 - b * wc[0], p1 = o1 - b * wc[1], p2 = o2 - b * wc[2];
     const float disc = sp.r2 - (p0 * p0 + p1 * p1 + p2 * p2);
@@ -1209,7 +1241,7 @@ DEV SplatOut splat_own_sphere(const uint32_t* S, const KSphere& sp, const float*
 template <bool GLOSS>
 DEV void deep_connect(const KParams& P, const KBuffers& B, const uint32_t* T, const KSphere* SP, uint32_t* tally,
                       SplatQ& q, Counters& cnt, uint32_t lane, bool want, uint64_t committed, const float* x,
-                      const Lane& Q, uint32_t wb, bool exhausted) {
+                      const EyeRay& ray, const Lane& Q, uint32_t wb, bool exhausted) {
     const uint64_t wm = __ballot(want);
     const auto& K = *kernel_params();
     if (wm && wm == committed && !exhausted && Q.region >= 0 && ((K.geo_clear >> (uint32_t)Q.region) & 1u)) {
@@ -1223,7 +1255,7 @@ DEV void deep_connect(const KParams& P, const KBuffers& B, const uint32_t* T, co
                               (uint32_t)Q.lam;
         if (want) {
             const float zero3[3] = {0.f, 0.f, 0.f};
-            const SplatOut so = own ? splat_own_sphere(T, SP[Q.region], x, Q.lam, base, __float_as_uint(x[3]),
+            const SplatOut so = own ? splat_own_sphere(T, SP[Q.region], ray, Q.lam, base, __float_as_uint(x[3]),
                                                        GLOSS ? Q.wgt : 1.f)
                                     : splat_eval<true>(T, SP, x, Q.lam, Q.comp, Q.batch, PEND_MEDIUM, zero3,
                                                        __float_as_uint(x[3]), GLOSS ? Q.wgt : 1.f, occl);
@@ -1295,18 +1327,20 @@ DEV void deep_round(const KParams& P, const KBuffers& B, const uint32_t* T, cons
         cnt.scatters += (uint32_t)m1 + (uint32_t)m2;
         if constexpr (GEOM == FPT_GEOM_BOX) {
             if (pinhole) {
-                const bool o1 = m1 && dep && opaque_to_eye(x1, Q.region, Q.inv, Q.sc, Q.sr2);
+                const EyeRay r1 = eye_ray(x1, Q.sc);
+                const bool o1 = m1 && dep && opaque_to_eye(r1, Q.region, Q.inv, Q.sr2);
                 count_opaque(tally, cnt, o1);
                 const bool w1 = m1 && dep && !o1;
                 const uint64_t c1 = k1 >= 64 ? ~0ull : ((1ull << k1) - 1ull);
-                deep_connect<GLOSS>(P, B, T, SP, tally, q, cnt, lane, w1, c1, x1, Q, wb, exhausted);
+                deep_connect<GLOSS>(P, B, T, SP, tally, q, cnt, lane, w1, c1, x1, r1, Q, wb, exhausted);
                 sq_drain(P, B.film, T, SP, tally, q, cnt, lane, false);
                 if (k2 > 0) {
-                    const bool o2 = m2 && dep && opaque_to_eye(x2, Q.region, Q.inv, Q.sc, Q.sr2);
+                    const EyeRay r2 = eye_ray(x2, Q.sc);
+                    const bool o2 = m2 && dep && opaque_to_eye(r2, Q.region, Q.inv, Q.sr2);
                     count_opaque(tally, cnt, o2);
                     const bool w2 = m2 && dep && !o2;
                     const uint64_t c2 = k2 >= 64 ? ~0ull : ((1ull << k2) - 1ull);
-                    deep_connect<GLOSS>(P, B, T, SP, tally, q, cnt, lane, w2, c2, x2, Q, wb, exhausted);
+                    deep_connect<GLOSS>(P, B, T, SP, tally, q, cnt, lane, w2, c2, x2, r2, Q, wb, exhausted);
                 }
             }
         }
