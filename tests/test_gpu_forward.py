@@ -402,6 +402,48 @@ def test_block_rounds_are_width_independent(scene_name):
 
 
 
+
+def test_spheres_in_line_forward_film():
+    """Two dense spheres in line with the eye: connections from the far one
+    cross the near one, so its occluder mask holds both spheres and the deep
+    rounds' in-place evaluation takes the clear form over that mask, while
+    the near sphere, occluded by itself only, takes the one-chord form.  In
+    the Cornell box's tuned launch shape at 16x16 pixels the film agrees bin by
+    bin with the oracle's (batch-mean z), and on the same paths its total equals
+    the sum of the replayed records' deposits."""
+    import torch
+    fpt = _fpt()
+    from paper_1706_03024_amd import autotune
+    scene = workloads.cornell_scene(16, 16)
+    scene["geometry"]["spheres"] = [
+        {"center": [0.0, -0.40, 0.35], "radius": 0.2, "medium": 2},   # near the eye
+        {"center": [0.0, -0.50, -0.40], "radius": 0.2, "medium": 2},  # behind it, in line
+    ]
+    sc = fpt.Scene(scene)
+    clear, occl = sc.connection_masks()
+    assert clear == 3 and occl[0] == 1 and occl[1] == 3, (clear, occl)
+    _, big_run = workloads.cornell_config()
+    autotune.autotune("cornell-128-64spp", scene=sc, run=big_run, measure=False)
+    B = 32
+    g = sc.render(workloads.make_run(1 << 24, seed=41, parity_batches=B)).cpu().numpy().astype(np.float64)
+    same = workloads.make_run(1 << 21, seed=43)
+    t = fpt.new_tallies()
+    film = sc.render(same, tallies=t)
+    rec, _ = sc.records(same)
+    torch.cuda.synchronize()
+    total = float(film.double().sum())
+    sc.close()
+    assert abs(total - float(rec["splat_sum"].astype(np.float64).sum())) <= 1e-4 * total
+    td = fpt.tallies_dict(t)
+    # paths enter the spheres and walk long chains there (deep rounds); none is
+    # deep enough for a zero-valued connection, so every full half of a deep
+    # round connects in place
+    assert td["crossings"] > 0 and td["splat_opaque"] == 0, td
+    o = oracle.render(scene, workloads.make_run(1 << 22, seed=42, parity_batches=B))["film"]
+    z = batch_z(g, o)
+    assert z.size > 500, z.size  # chiefly the three excitation lines: emission is rare here
+    check_z(z, "in-line spheres film: GPU vs oracle", dof=B - 1)
+
 def test_large_scene_paths_are_schedule_independent():
     """At the large scene's full size (2^28 paths into the pinhole film) the
     launch shape and the timing of the path queue decide which paths share a
